@@ -1,0 +1,26 @@
+"""Seeded synthetic inputs for the LSMS tau00 path.
+
+This package prepares what the path takes as input: fcc NiAu-shaped
+supercells (positions, species, vacancies, positional noise), the list of
+(site, energy) instances with their LIZ cutoff radii, the complex energy
+contour and the square-well phase shifts that stand in for real muffin-tin
+potentials.  It contains no step of the path itself (no LIZ extraction, no
+t-matrix, no structure constants, no factorisation); both the product path
+and the oracle take their inputs from here.
+"""
+
+from .workloads import (  # noqa: F401
+    A_LAT,
+    R_MT,
+    V0_SPECIES,
+    Workload,
+    config1,
+    config2,
+    config3,
+    config4,
+    contour_energies,
+    fcc_supercell,
+    phase_shift_table,
+    square_well_delta,
+    subset,
+)

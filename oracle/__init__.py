@@ -1,0 +1,213 @@
+"""CPU FP64 oracle for the LSMS tau00 path (ctypes over lsms_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the benchmark's CPU-baseline leg.  The product package never imports it.
+
+Every function follows the definitions cited in lsms_oracle.c (paper Sec. 2.1
+eq. Dyson_equation, Sec. 2.2, Sec. 3.2).  Arrays are numpy; complex values are
+complex128; matrices are returned with natural [row, column] indexing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lsms_oracle.c")
+_LIB = os.path.join(_HERE, "liblsms_oracle.so")
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+
+
+def build(force: bool = True) -> str:
+    """Compile lsms_oracle.c into liblsms_oracle.so beside it (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O3", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fcx-limited-range", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.orc_liz.restype = _I
+        L.orc_liz.argtypes = [_P, _I, _P, _I, ctypes.c_double, _I, _P, _P]
+        L.orc_ylm.argtypes = [_I, _P, _P]
+        L.orc_gaunt.restype = _I
+        L.orc_gaunt.argtypes = [_I, _P]
+        L.orc_hankel.argtypes = [_I, _P, _P]
+        L.orc_tmat.argtypes = [_I, _P, _P, _P]
+        L.orc_structure_constants.argtypes = [_I, _P, _P, _P, _P]
+        L.orc_build_m.restype = _I
+        L.orc_build_m.argtypes = [_I, _I, _P, _P, _P, _P, _I, _P, _P]
+        L.orc_lu_factor.restype = _I
+        L.orc_lu_factor.argtypes = [_I, _P, _P]
+        L.orc_lu_solve.argtypes = [_I, _P, _P, _I, _P]
+        L.orc_tau00_batch.argtypes = [_I, _I, _P, _P, _P, _P, _P, _P, _I, _I, _I, _P, _P]
+        L.orc_tau00_schur.restype = _I
+        L.orc_tau00_schur.argtypes = [_I, _I, _P, _P, _P, _P, _I, _P, _P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ---------------------------------------------------------------- a1: LIZ
+def liz(pos, box, centre: int, rc: float, max_out: int = 4096):
+    """LIZ of one centre: (rel [n, 3] relative vectors, idx [n] atom ids), centre first."""
+    pos = _c(pos, np.float64)
+    box = _c(box, np.float64)
+    rel = np.zeros((max_out, 3))
+    idx = np.zeros(max_out, np.int32)
+    n = lib().orc_liz(_ptr(pos), pos.shape[0], _ptr(box), int(centre), float(rc), max_out, _ptr(rel), _ptr(idx))
+    if n > max_out:
+        raise ValueError(f"LIZ of {n} atoms exceeds max_out={max_out}")
+    return rel[:n].copy(), idx[:n].copy()
+
+
+def liz_batch(w):
+    """LIZs of every instance of a workload: (liz_off [n+1] int64, pos [tot, 3], species [tot])."""
+    offs = [0]
+    rels, specs = [], []
+    for c, r in zip(w.centre, w.rc):
+        rel, idx = liz(w.atom_pos, w.box, int(c), float(r))
+        rels.append(rel)
+        specs.append(w.atom_species[idx])
+        offs.append(offs[-1] + rel.shape[0])
+    return (np.asarray(offs, np.int64), np.concatenate(rels).astype(np.float64),
+            np.concatenate(specs).astype(np.int32))
+
+
+# ------------------------------------------------------- angular / radial
+def ylm(lmax: int, r):
+    r = _c(r, np.float64)
+    Y = np.zeros((lmax + 1) ** 2)
+    lib().orc_ylm(lmax, _ptr(r), _ptr(Y))
+    return Y
+
+
+def gaunt(lmax: int):
+    """Real Gaunt table C[L, L', L''] (l, l' <= lmax, l'' <= 2 lmax) and its nonzero count."""
+    kk = (lmax + 1) ** 2
+    kk2 = (2 * lmax + 1) ** 2
+    C = np.zeros((kk, kk, kk2))
+    nnz = lib().orc_gaunt(lmax, _ptr(C))
+    return C, nnz
+
+
+def hankel(lmax: int, z: complex):
+    zz = np.array([complex(z).real, complex(z).imag])
+    h = np.zeros(2 * (lmax + 1))
+    lib().orc_hankel(lmax, _ptr(zz), _ptr(h))
+    return h[0::2] + 1j * h[1::2]
+
+
+def tmat(lmax: int, E: complex, delta_l):
+    Er = np.array([complex(E).real, complex(E).imag])
+    d = _c(delta_l, np.complex128)
+    t = np.zeros(lmax + 1, np.complex128)
+    lib().orc_tmat(lmax, _ptr(Er), _ptr(d), _ptr(t))
+    return t
+
+
+def structure_constants(lmax: int, kappa: complex, R, C=None):
+    """G^{ij}[L, L'] for R = R_i - R_j."""
+    if C is None:
+        C, _ = gaunt(lmax)
+    C = _c(C, np.float64)
+    kk = (lmax + 1) ** 2
+    k = np.array([complex(kappa).real, complex(kappa).imag])
+    R = _c(R, np.float64)
+    G = np.zeros((kk, kk), np.complex128, order="F")
+    lib().orc_structure_constants(lmax, _ptr(k), _ptr(R), _ptr(C), _ptr(G))
+    return G
+
+
+# --------------------------------------------------------- a2 + a3: M
+def build_m(lmax: int, rel, spec, E: complex, delta_e, C=None):
+    """M = 1 - t G over one LIZ; delta_e [n_species, lmax + 1] at this energy.
+    Returns (M [N, N], status)."""
+    if C is None:
+        C, _ = gaunt(lmax)
+    C = _c(C, np.float64)
+    rel = _c(rel, np.float64)
+    spec = _c(spec, np.int32)
+    d = _c(delta_e, np.complex128)
+    n_liz = rel.shape[0]
+    N = (lmax + 1) ** 2 * n_liz
+    M = np.zeros((N, N), np.complex128, order="F")
+    Er = np.array([complex(E).real, complex(E).imag])
+    st = lib().orc_build_m(lmax, n_liz, _ptr(rel), _ptr(spec), _ptr(Er), _ptr(d), d.shape[0], _ptr(C), _ptr(M))
+    return M, st
+
+
+# ------------------------------------------------------ a4 + a5: LU, tau00
+def lu_factor(A):
+    LU = np.array(A, dtype=np.complex128, order="F", copy=True)
+    n = LU.shape[0]
+    ipiv = np.zeros(n, np.int32)
+    info = lib().orc_lu_factor(n, _ptr(LU), _ptr(ipiv))
+    return LU, ipiv, info
+
+
+def lu_solve(LU, ipiv, B):
+    X = np.array(B, dtype=np.complex128, order="F", copy=True)
+    if X.ndim == 1:
+        X = X.reshape(-1, 1, order="F")
+    lib().orc_lu_solve(LU.shape[0], _ptr(np.asfortranarray(LU)), _ptr(_c(ipiv, np.int32)), X.shape[1], _ptr(X))
+    return X
+
+
+def tau00_batch(lmax: int, liz_off, pos, species, energies, e_idx, delta, refine: int = 2):
+    """tau00 [n_inst, kk, kk] (natural [L, L'] indexing) and info [n_inst]."""
+    liz_off = _c(liz_off, np.int64)
+    pos = _c(pos, np.float64)
+    species = _c(species, np.int32)
+    energies = _c(energies, np.complex128)
+    e_idx = _c(e_idx, np.int32)
+    delta = _c(delta, np.complex128)
+    n = e_idx.shape[0]
+    kk = (lmax + 1) ** 2
+    tau = np.zeros((n, kk, kk), np.complex128)  # [i][L'][L] in memory = column-major per instance
+    info = np.zeros(n, np.int32)
+    lib().orc_tau00_batch(lmax, n, _ptr(liz_off), _ptr(pos), _ptr(species), _ptr(energies), _ptr(e_idx),
+                          _ptr(delta), delta.shape[0], delta.shape[1], int(refine), _ptr(tau), _ptr(info))
+    return tau.transpose(0, 2, 1).copy(), info
+
+
+def tau00_schur(lmax: int, rel, spec, E: complex, delta_e, C=None):
+    if C is None:
+        C, _ = gaunt(lmax)
+    kk = (lmax + 1) ** 2
+    rel = _c(rel, np.float64)
+    spec = _c(spec, np.int32)
+    d = _c(delta_e, np.complex128)
+    Er = np.array([complex(E).real, complex(E).imag])
+    tau = np.zeros((kk, kk), np.complex128, order="F")
+    info = lib().orc_tau00_schur(lmax, rel.shape[0], _ptr(rel), _ptr(spec), _ptr(Er), _ptr(d), d.shape[0],
+                                 _ptr(_c(C, np.float64)), _ptr(tau))
+    return tau, info
+
+
+def tau00_workload(w, refine: int = 2):
+    """Oracle tau00 for every instance of an inputs.Workload."""
+    liz_off, pos, spec = liz_batch(w)
+    return tau00_batch(w.lmax, liz_off, pos, spec, w.energies, w.e_idx, w.delta, refine)
