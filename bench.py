@@ -1,0 +1,173 @@
+"""Benchmark of the LSMS tau00 hot path on one MI355X.
+
+One step = the whole path over one batch: LIZ extraction for every
+(site, energy) instance, KKR matrix assembly and FP64 LU/Schur elimination
+with tau00, for the 8192 instances of the fcc NiAu 50/50 workload with a
+135-atom LIZ (N = 2160, lmax = 3, 256 sites x 32 contour energies).  Inputs
+are synthetic and resident on the GPU before the timed region.
+
+Prints one JSON line (see the contract in the design doc).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6
+METRIC = "τ00 solves/s at N=2160, 1e-10 rel: mixed/batched vs plain FP64; TFLOP/s vs peak"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, n_threads: int):
+    """The oracle on a bounded sample of the same workload: one instance per
+    thread (OpenMP over instances), at both contour ends and mid-contour."""
+    import inputs
+    import oracle
+
+    n = max(1, n_threads)
+    idx = np.linspace(0, w.n_inst - 1, n).astype(int)
+    ws = inputs.subset(w, idx)
+    liz_off, pos, spec = oracle.liz_batch(ws)
+    oracle.set_threads(n_threads)
+    t0 = time.perf_counter()
+    tau, info = oracle.tau00_batch(ws.lmax, liz_off, pos, spec, ws.energies, ws.e_idx, ws.delta, refine=2)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "solves/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"{n} instances of the same workload (N=2160), one per OpenMP thread, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--chunk", type=int, default=1024, help="instances per build/LU launch")
+    ap.add_argument("--nb", type=int, default=0)
+    ap.add_argument("--n-inst", type=int, default=0, help="limit the batch (0 = all 8192)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import inputs
+    import paper_2308_16317_amd as P
+
+    w = inputs.config2()
+    if args.n_inst:
+        w = inputs.subset(w, np.arange(args.n_inst))
+    log(f"[bench] workload {w.name}: {w.n_inst} instances")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    h = P.Handle()
+    # inputs resident on the device
+    atom_pos = torch.as_tensor(w.atom_pos, device=dev)
+    atom_spec = torch.as_tensor(w.atom_species, device=dev)
+    centre = torch.as_tensor(w.centre, device=dev)
+    rc = torch.as_tensor(w.rc, device=dev)
+    energy = torch.as_tensor(w.energies, device=dev)
+    e_idx = torch.as_tensor(w.e_idx, device=dev)
+    delta = torch.as_tensor(w.delta, device=dev)
+    max_liz = 160  # bound on the 135-atom LIZ of this workload (checked every step)
+    kk = w.kk
+    chunk = min(args.chunk, w.n_inst)
+    nslot = kk * max_liz
+    M = torch.empty(chunk * nslot * nslot, dtype=torch.complex128, device=dev)
+    tau = torch.empty((w.n_inst, kk * kk), dtype=torch.complex128, device=dev)
+    info = torch.empty(w.n_inst, dtype=torch.int32, device=dev)
+    opts = P.Opts(0, args.nb, 0, 0)
+    stream = torch.cuda.current_stream()
+    lu_events = []
+
+    def step(record: bool):
+        liz = P.build_liz(h, atom_pos, atom_spec, w.box, centre, rc, max_liz)
+        sizes = liz["liz_off"][1:] - liz["liz_off"][:-1]
+        N = kk * sizes
+        for i0 in range(0, w.n_inst, chunk):
+            n = min(chunk, w.n_inst - i0)
+            sl = slice(i0, i0 + n)
+            # instance i of the chunk owns LIZ rows liz_off[i0+i] .. liz_off[i0+i+1]-1
+            prob = P.Problem(w.lmax, liz["liz_off"][i0:i0 + n + 1], liz["pos"], liz["species"], energy,
+                             e_idx[sl], delta, max_liz=max_liz)
+            Nc = N[sl]
+            m_off = torch.cumsum(Nc * Nc, 0) - Nc * Nc
+            P.build_kkr(h, prob, M, m_off)
+            if record:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            P.tau00_batched(h, prob, M, m_off, opts, tau=tau[sl], info=info[sl])
+            if record:
+                e1.record(stream)
+                lu_events.append((e0, e1, n, Nc))
+        return liz
+
+    for _ in range(args.warmup):
+        liz = step(False)
+    torch.cuda.synchronize()
+    sizes = (liz["liz_n"]).cpu().numpy()
+    if sizes.max() > max_liz:
+        raise RuntimeError("LIZ larger than the bench's max_liz")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    bad = int((info != 0).sum().item())
+    if bad:
+        raise RuntimeError(f"{bad} instances reported nonzero info")
+    n_inst = w.n_inst
+    Ns = kk * sizes.astype(np.float64)
+    flops_step = float(np.sum(8.0 / 3.0 * Ns ** 3))
+    ms = 1e3 * dt / args.steps
+    lu_ms = [e0.elapsed_time(e1) for (e0, e1, _, _) in lu_events]
+    lu_flops = [float(np.sum(8.0 / 3.0 * (Nc.double().cpu().numpy()) ** 3)) for (_, _, _, Nc) in lu_events]
+    ach = float(np.sum(lu_flops) / (np.sum(lu_ms) * 1e-3) / 1e12)
+    out = {
+        "metric": METRIC,
+        "value": n_inst * args.steps / dt,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: fcc NiAu 50/50, 256 sites x 32 energies = {n_inst} instances, "
+                               f"135-atom LIZ, N=2160, lmax=3, complex FP64 LU/Schur",
+                   "n_inst": n_inst, "N": int(Ns.max()), "lmax": w.lmax, "chunk": chunk},
+        "tflops": flops_step / (ms * 1e-3) / 1e12,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "lu_schur_fp64_kernel", "lu_ms_per_launch": float(np.mean(lu_ms)),
+                     "instances_per_launch": chunk},
+    }
+    if not args.no_cpu:
+        nthr = args.cpu_threads or min(16, os.cpu_count() or 1)
+        log(f"[bench] cpu baseline: oracle on {nthr} threads")
+        out["cpu_baseline"] = cpu_baseline(w, nthr)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * liblsms_tau: the LSMS tau00 hot path on one AMD Instinct MI355X (gfx950).
+ *
+ * For each (site, complex energy) instance the library forms the KKR matrix
+ * over the site's local interaction zone (LIZ) and returns the central block
+ * of the multiple-scattering matrix,
+ *     tau00 = [M^{-1}]_{00} t_0,   M = 1 - t(E) G(E),
+ * which equals the central block of the Dyson-equation inverse
+ * tau = [t^{-1} - g0]^{-1} (paper Sec. 2.1, eq. Dyson_equation; Sec. 2.2 for
+ * the LIZ and the block-LU route that needs only the first block).
+ *
+ * Conventions (all entry points)
+ *   - Units: Rydberg atomic units; lengths in bohr, energies in Ry.
+ *   - Complex numbers are interleaved (re, im) pairs of double, i.e. the
+ *     memory layout of C99 double complex / torch.complex128.
+ *   - Angular index L = l*l + l + m (real spherical harmonics, no
+ *     Condon-Shortley factor), kk = (lmax + 1)^2.
+ *   - Matrices are column-major.
+ *   - Pointers documented as "device" must point to memory of the handle's
+ *     device; "host" pointers are read before the call returns.  The caller
+ *     owns every buffer; the library never frees caller memory.
+ *   - Every call enqueues work on `stream` (a hipStream_t, passed as void*;
+ *     NULL is the default stream) and returns without synchronising.
+ *     Outputs are valid after the stream has been synchronised.
+ *   - Return value: 0 on success; -k when argument k (1-based) is invalid
+ *     (checked on the host before anything is enqueued); LSMS_EHIP when the
+ *     HIP runtime reports an error.  Per-instance status goes to info[].
+ *
+ * Per-instance info[i]
+ *    0  success
+ *   k>0 an exactly zero pivot at elimination step k (1-based, in the
+ *       library's elimination order: non-central columns first, the central
+ *       block last); tau00 of the instance is NaN
+ *   -1  non-finite tau00 (non-finite energy or phase shift, overflow)
+ *   -2  two LIZ sites closer than 1e-8 bohr (M undefined); tau00 is NaN
+ *   -3  invalid instance: empty LIZ, LIZ larger than max_liz, energy index
+ *       or species out of range; tau00 is NaN and M is not written
+ */
+#ifndef LSMS_TAU_H
+#define LSMS_TAU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LSMS_EHIP (-100)
+#define LSMS_PREC_FP64 0
+
+typedef struct lsms_handle_s *lsms_handle_t;
+
+/* One batch of (site, energy) instances with ragged LIZs.  The struct itself
+ * lives in host memory; its array members are device pointers. */
+typedef struct {
+    int32_t lmax;        /* angular cutoff, 0..4; kk = (lmax+1)^2                      */
+    int32_t n_inst;      /* number of instances (>= 0)                                 */
+    int32_t n_species;   /* number of species in delta (1..8)                          */
+    int32_t n_energy;    /* number of energies in energy/delta (>= 1)                  */
+    int32_t max_liz;     /* upper bound on every LIZ size (>= 1); sizes workspace slots */
+    int32_t reserved;
+    const int64_t *liz_off;  /* device [n_inst+1]: instance i owns LIZ rows liz_off[i] ..
+                                liz_off[i+1]-1 (non-decreasing, liz_off[0] = 0)       */
+    const double *pos;       /* device [liz_off[n_inst]][3]: site positions relative to
+                                the instance's centre; row liz_off[i] is the centre (0,0,0) */
+    const int32_t *species;  /* device [liz_off[n_inst]]: species of each LIZ site,
+                                in 0..n_species-1                                      */
+    const double *energy;    /* device [n_energy] complex: E (Ry), Im E > 0            */
+    const int32_t *e_idx;    /* device [n_inst]: energy index of each instance         */
+    const double *delta;     /* device [n_species][n_energy][lmax+1] complex phase
+                                shifts delta_l(E); t_l = -(1/kappa) sin(delta_l)
+                                exp(i delta_l), kappa = sqrt(E) (principal branch)     */
+} lsms_problem;
+
+typedef struct {
+    int32_t precision;   /* LSMS_PREC_FP64                                             */
+    int32_t nb;          /* panel width of the LU, 0 = default (64); 16..64, multiple of 16 */
+    int32_t chunk;       /* tau00_solve: instances per workspace pass, 0 = as many as fit */
+    int32_t reserved;
+} lsms_opts;
+
+/* Create a handle bound to HIP device `device`: uploads the real Gaunt
+ * tables (Wigner-3j closed form) for lmax = 0..4.  Returns 0 or an error. */
+int lsms_create(lsms_handle_t *h, int device);
+
+/* Release the handle's device tables. */
+int lsms_destroy(lsms_handle_t h);
+
+/* LIZ extraction (paper Sec. 2.2: each atom's KKR matrix is built over the
+ * atoms of the cluster centred on it).
+ *   atom_pos     device [n_atoms][3]  periodic supercell positions (bohr)
+ *   atom_species device [n_atoms]
+ *   box          host   [3]           orthorhombic box lengths (bohr), > 0
+ *   centre       device [n_inst]      centre atom of each instance
+ *   rc           device [n_inst]      cutoff radius of each instance (bohr)
+ *   max_liz      rows reserved per instance (>= 1)
+ * Outputs (device, caller-allocated):
+ *   liz_n        [n_inst]              true LIZ size (centre included); a size
+ *                                      above max_liz means the LIZ was truncated
+ *   liz_off      [n_inst+1]            offsets of the compact output (sizes
+ *                                      clamped to max_liz)
+ *   liz_pos      [n_inst*max_liz][3]   relative positions, centre first, then by
+ *                                      ascending |d|^2, ties by (dx, dy, dz)
+ *   liz_species  [n_inst*max_liz]
+ *   liz_atom     [n_inst*max_liz] or NULL: supercell index of each LIZ site
+ * Membership: minimum-image d with dx*dx+dy*dy+dz*dz <= rc*rc (no FMA
+ * contraction), each component reduced by box*rint(d/box). */
+int lsms_build_liz(lsms_handle_t h, const double *atom_pos, const int32_t *atom_species, int32_t n_atoms,
+                   const double *box, const int32_t *centre, const double *rc, int32_t n_inst, int32_t max_liz,
+                   int32_t *liz_n, int64_t *liz_off, double *liz_pos, int32_t *liz_species, int32_t *liz_atom,
+                   void *stream);
+
+/* KKR matrix assembly (paper Sec. 2.1: M built from the single-site t and the
+ * propagator between two different sites; Sec. 3.2 builds it on the CPU, the
+ * paper's conclusion names building it on the GPU as the next step).
+ *   M      device complex; instance i is an N_i x N_i column-major matrix at
+ *          M + 2*m_off[i] doubles, N_i = kk * (liz_off[i+1] - liz_off[i]);
+ *          M_ii = I_kk, M_ij = -diag(t_{s(i),l(L)}) G^{ij} with
+ *          G^{ij}_{LL'} = -4 pi i kappa sum_L'' i^{l-l'+l''} C^{L''}_{LL'}
+ *                          h_l''(kappa |R_ij|) Y_L''(R_ij), R_ij = R_i - R_j
+ *   m_off  device [n_inst] offsets in complex elements (regions must not overlap)
+ *   info   device [n_inst] out: 0 or -2 (coincident sites) */
+int build_kkr(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *m_off, int32_t *info,
+              void *stream);
+
+/* tau00 from caller-built matrices (paper Sec. 2.2: block LU, first block of
+ * the inverse only; Sec. 3.2: LU with partial pivoting in complex FP64).
+ *   M      device complex, layout as build_kkr; overwritten by factors
+ *   m_off  device [n_inst]
+ *   opts   host, may be NULL (defaults)
+ *   tau00  device [n_inst][kk*kk] complex out, column-major kk x kk:
+ *          tau00[i][L + kk*L'] = ([M_i^{-1}]_{00} diag(t_0))_{L L'}
+ *   info   device [n_inst] out
+ *   work / work_bytes: unused by this precision (may be NULL / 0). */
+int tau00_batched(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *m_off, const lsms_opts *opts,
+                  double *tau00, int32_t *info, void *work, size_t work_bytes, void *stream);
+
+/* Workspace that tau00_solve needs to process `chunk` instances per pass:
+ * chunk * (kk*max_liz)^2 * 16 bytes (one M slot per instance). */
+int lsms_workspace_size(lsms_handle_t h, const lsms_problem *p, const lsms_opts *opts, int32_t chunk,
+                        size_t *bytes);
+
+/* Fused build_kkr + tau00_batched: M never leaves the device workspace; the
+ * instances are processed in passes of floor(work_bytes / slot) (or
+ * opts->chunk) instances.  Arguments as above; work is a device buffer of at
+ * least lsms_workspace_size(.., 1, ..) bytes. */
+int tau00_solve(lsms_handle_t h, const lsms_problem *p, const lsms_opts *opts, double *tau00, int32_t *info,
+                void *work, size_t work_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSMS_TAU_H */

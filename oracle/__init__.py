@@ -56,10 +56,20 @@ def lib():
         L.orc_lu_factor.argtypes = [_I, _P, _P]
         L.orc_lu_solve.argtypes = [_I, _P, _P, _I, _P]
         L.orc_tau00_batch.argtypes = [_I, _I, _P, _P, _P, _P, _P, _P, _I, _I, _I, _P, _P]
+        L.orc_set_threads.argtypes = [_I]
+        L.orc_max_threads.restype = _I
         L.orc_tau00_schur.restype = _I
         L.orc_tau00_schur.argtypes = [_I, _I, _P, _P, _P, _P, _I, _P, _P]
         _lib = L
     return _lib
+
+
+def set_threads(n: int):
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _ptr(a: np.ndarray):

@@ -31,6 +31,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -39,6 +40,10 @@ typedef double complex zc;
 typedef long double complex lzc;
 
 #define ORC_PI 3.14159265358979323846264338327950288
+
+/* OpenMP thread count used by orc_tau00_batch. */
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ */
 /* a1: local interaction zone                                          */

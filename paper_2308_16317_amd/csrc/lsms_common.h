@@ -1,0 +1,108 @@
+// Device-side helpers shared by the HIP kernels of liblsms_tau (complex FP64
+// arithmetic, index maps) and the internal launch interface between the C-ABI
+// layer and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lsms {
+
+typedef double2 zd;  // complex FP64, (re, im)
+
+__device__ __forceinline__ zd zmake(double r, double i) { return make_double2(r, i); }
+__device__ __forceinline__ zd zadd(zd a, zd b) { return zmake(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ zd zsub(zd a, zd b) { return zmake(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ zd zmul(zd a, zd b) { return zmake(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ zd zscale(zd a, double s) { return zmake(a.x * s, a.y * s); }
+// a - b*c
+__device__ __forceinline__ zd zfms(zd a, zd b, zd c) {
+  return zmake(a.x - b.x * c.x + b.y * c.y, a.y - b.x * c.y - b.y * c.x);
+}
+__device__ __forceinline__ double zcabs1(zd a) { return fabs(a.x) + fabs(a.y); }
+// 1 / a, scaled to avoid overflow in |a|^2
+__device__ __forceinline__ zd zinv(zd a) {
+  const double s = fmax(fabs(a.x), fabs(a.y));
+  const double ar = a.x / s, ai = a.y / s;
+  const double d = s * (ar * ar + ai * ai);
+  return zmake(ar / d, -ai / d);
+}
+__device__ __forceinline__ zd zdiv(zd a, zd b) { return zmul(a, zinv(b)); }
+// principal square root
+__device__ __forceinline__ zd zsqrt(zd z) {
+  const double r = hypot(z.x, z.y);
+  if (r == 0.0) return zmake(0.0, 0.0);
+  if (z.x >= 0.0) {
+    const double s = sqrt(0.5 * (r + z.x));
+    return zmake(s, z.y / (2.0 * s));
+  }
+  const double s = sqrt(0.5 * (r - z.x));
+  return zmake(fabs(z.y) / (2.0 * s), copysign(s, z.y));
+}
+// exp(i z)
+__device__ __forceinline__ zd zexpi(zd z) {
+  double s, c;
+  sincos(z.x, &s, &c);
+  const double e = exp(-z.y);
+  return zmake(e * c, e * s);
+}
+// single-site t-matrix element t = -(1/kappa) sin(d) e^{i d}
+__device__ __forceinline__ zd tmat_from_delta(zd d, zd kap) {
+  double sa, ca;
+  sincos(d.x, &sa, &ca);
+  const double sd = sa * cosh(d.y), cd = ca * sinh(d.y);  // sin(a + ib)
+  const zd s = zmake(sd, cd);
+  const zd e = zexpi(d);
+  const zd se = zmul(s, e);
+  const zd q = zdiv(se, kap);
+  return zmake(-q.x, -q.y);
+}
+__device__ __forceinline__ bool zfinite(zd a) { return isfinite(a.x) && isfinite(a.y); }
+
+__host__ __device__ __forceinline__ int l_of(int L) {
+  int l = 0;
+  while ((l + 1) * (l + 1) <= L) ++l;
+  return l;
+}
+
+}  // namespace lsms
+
+// ---------------------------------------------------------------------------
+// Internal launch interface (host functions defined in the kernel TUs).
+// ---------------------------------------------------------------------------
+struct lsms_gaunt_dev {
+  const int32_t* row_ptr;  // [kk*kk + 1], pair index p = L + kk*L'
+  const int16_t* lpp;      // L'' of each nonzero
+  const double* coef;      // C^{L''}_{LL'} * i^{l-l'+l''} (always real: l-l'+l'' is even)
+  int32_t lmax;
+  int32_t nnz;
+};
+
+struct lsms_prob_dev {
+  int32_t lmax, kk, n_inst, n_species, n_energy, max_liz;
+  const int64_t* liz_off;
+  const double* pos;
+  const int32_t* species;
+  const double* energy;  // complex
+  const int32_t* e_idx;
+  const double* delta;   // complex [n_species][n_energy][lmax+1]
+};
+
+hipError_t lsms_launch_liz(const double* atom_pos, const int32_t* atom_species, int32_t n_atoms,
+                           double bx, double by, double bz, const int32_t* centre, const double* rc,
+                           int32_t n_inst, int32_t max_liz, int32_t* liz_n, int64_t* liz_off,
+                           double* liz_pos, int32_t* liz_species, int32_t* liz_atom, hipStream_t s);
+
+// Build M for instances [i0, i0 + n) of the problem.  M_i is written at
+// M + 2 * moff(i) doubles, where moff(i) = m_off[i] if m_off is non-null and
+// (i - i0) * slot otherwise.  info[i] = 0 or -2 (coincident sites).
+hipError_t lsms_launch_build(const lsms_prob_dev& p, const lsms_gaunt_dev& g, int32_t i0, int32_t n,
+                             double* M, const int64_t* m_off, int64_t slot, int32_t* info,
+                             hipStream_t s);
+
+// FP64 LU / Schur elimination and tau00 for instances [i0, i0 + n); M
+// addressing as lsms_launch_build.  If keep_info, instances whose info is
+// already nonzero are skipped (tau00 filled with NaN).
+hipError_t lsms_launch_lu_fp64(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M,
+                               const int64_t* m_off, int64_t slot, double* tau00, int32_t* info,
+                               int keep_info, int32_t nb, hipStream_t s);

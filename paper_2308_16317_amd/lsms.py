@@ -1,0 +1,234 @@
+"""ctypes binding of liblsms_tau.so with the entry points' own names.
+
+Argument marshalling only: tensors are allocated with torch on the current
+CUDA (HIP) device and passed by data pointer together with the current
+stream.  There is no fallback: if the library is missing, `lib()` raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblsms_tau.so")
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("lmax", ctypes.c_int32),
+        ("n_inst", ctypes.c_int32),
+        ("n_species", ctypes.c_int32),
+        ("n_energy", ctypes.c_int32),
+        ("max_liz", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("liz_off", _P),
+        ("pos", _P),
+        ("species", _P),
+        ("energy", _P),
+        ("e_idx", _P),
+        ("delta", _P),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("nb", ctypes.c_int32),
+        ("chunk", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+SYMBOLS = ("lsms_create", "lsms_destroy", "lsms_build_liz", "build_kkr", "tau00_batched",
+           "lsms_workspace_size", "tau00_solve")
+
+
+def lib():
+    """Load liblsms_tau.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2308_16317_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.lsms_create.argtypes = [ctypes.POINTER(_P), ctypes.c_int]
+        L.lsms_destroy.argtypes = [_P]
+        L.lsms_build_liz.argtypes = [_P, _P, _P, _I32, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P]
+        L.build_kkr.argtypes = [_P, ctypes.POINTER(_Problem), _P, _P, _P, _P]
+        L.tau00_batched.argtypes = [_P, ctypes.POINTER(_Problem), _P, _P, ctypes.POINTER(Opts), _P, _P, _P,
+                                    ctypes.c_size_t, _P]
+        L.lsms_workspace_size.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(Opts), _I32,
+                                          ctypes.POINTER(ctypes.c_size_t)]
+        L.tau00_solve.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(Opts), _P, _P, _P, ctypes.c_size_t,
+                                  _P]
+        for s in SYMBOLS:
+            getattr(L, s).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"{what} returned {rc}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(a, dtype):
+    if isinstance(a, torch.Tensor):
+        return a.to(device="cuda", dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+class Handle:
+    """lsms_create / lsms_destroy on the current device."""
+
+    def __init__(self, device: int | None = None):
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        _check(lib().lsms_create(ctypes.byref(h), self.device), "lsms_create")
+        self._h = h
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().lsms_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """Device-resident lsms_problem: ragged LIZs, energies, phase shifts."""
+
+    def __init__(self, lmax, liz_off, pos, species, energy, e_idx, delta, max_liz=None):
+        self.lmax = int(lmax)
+        self.liz_off = _dev(liz_off, torch.int64)
+        self.pos = _dev(pos, torch.float64)
+        self.species = _dev(species, torch.int32)
+        self.energy = _dev(energy, torch.complex128)
+        self.e_idx = _dev(e_idx, torch.int32)
+        self.delta = _dev(delta, torch.complex128)
+        self.n_inst = int(self.e_idx.shape[0])
+        if max_liz is None:
+            sizes = (self.liz_off[1:] - self.liz_off[:-1]) if self.n_inst else torch.zeros(1)
+            max_liz = int(sizes.max().item()) if self.n_inst else 1
+        self.max_liz = int(max_liz)
+
+    @property
+    def kk(self):
+        return (self.lmax + 1) ** 2
+
+    def struct(self) -> _Problem:
+        return _Problem(self.lmax, self.n_inst, int(self.delta.shape[0]), int(self.delta.shape[1]), self.max_liz, 0,
+                        _ptr(self.liz_off), _ptr(self.pos), _ptr(self.species), _ptr(self.energy), _ptr(self.e_idx),
+                        _ptr(self.delta))
+
+
+def build_liz(h: Handle, atom_pos, atom_species, box, centre, rc, max_liz: int, with_atoms: bool = False):
+    """lsms_build_liz: returns dict(liz_n, liz_off, pos, species[, atom]) of device tensors
+    (pos/species are the compact rows liz_off[0]..liz_off[n])."""
+    ap = _dev(atom_pos, torch.float64)
+    asp = _dev(atom_species, torch.int32)
+    ce = _dev(centre, torch.int32)
+    r = _dev(rc, torch.float64)
+    n = int(ce.shape[0])
+    box_h = (ctypes.c_double * 3)(*[float(b) for b in box])
+    out = dict(
+        liz_n=torch.empty(max(n, 1), dtype=torch.int32, device="cuda"),
+        liz_off=torch.empty(n + 1, dtype=torch.int64, device="cuda"),
+        pos=torch.empty((max(n, 1) * max_liz, 3), dtype=torch.float64, device="cuda"),
+        species=torch.empty(max(n, 1) * max_liz, dtype=torch.int32, device="cuda"),
+    )
+    if with_atoms:
+        out["atom"] = torch.empty(max(n, 1) * max_liz, dtype=torch.int32, device="cuda")
+    _check(lib().lsms_build_liz(h.ptr, _ptr(ap), _ptr(asp), int(ap.shape[0]), box_h, _ptr(ce), _ptr(r), n,
+                                int(max_liz), _ptr(out["liz_n"]), _ptr(out["liz_off"]), _ptr(out["pos"]),
+                                _ptr(out["species"]), _ptr(out.get("atom")), _stream()), "lsms_build_liz")
+    out["liz_n"] = out["liz_n"][:n]
+    return out
+
+
+def build_kkr(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tensor) -> torch.Tensor:
+    """build_kkr into the complex128 buffer M at offsets m_off; returns info (device)."""
+    info = torch.empty(max(prob.n_inst, 1), dtype=torch.int32, device="cuda")
+    ps = prob.struct()
+    _check(lib().build_kkr(h.ptr, ctypes.byref(ps), _ptr(M), _ptr(m_off), _ptr(info), _stream()), "build_kkr")
+    return info[:prob.n_inst]
+
+
+def _tau_view(tau: torch.Tensor, kk: int) -> torch.Tensor:
+    # column-major kk x kk per instance -> natural [i, L, L'] indexing
+    return tau.view(-1, kk, kk).transpose(1, 2)
+
+
+def tau00_batched(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tensor, opts: Opts | None = None,
+                  tau=None, info=None):
+    """tau00_batched on caller-built M (overwritten); returns (tau00 [n, kk, kk], info).
+    `tau` / `info` may be given as contiguous device buffers of n*kk*kk complex128 / n int32."""
+    kk = prob.kk
+    if tau is None:
+        tau = torch.empty(max(prob.n_inst, 1) * kk * kk, dtype=torch.complex128, device="cuda")
+    if info is None:
+        info = torch.empty(max(prob.n_inst, 1), dtype=torch.int32, device="cuda")
+    assert tau.is_contiguous() and info.is_contiguous()
+    ps = prob.struct()
+    o = opts if opts is not None else Opts()
+    _check(lib().tau00_batched(h.ptr, ctypes.byref(ps), _ptr(M), _ptr(m_off), ctypes.byref(o), _ptr(tau),
+                               _ptr(info), None, 0, _stream()), "tau00_batched")
+    return _tau_view(tau, kk)[:prob.n_inst], info[:prob.n_inst]
+
+
+def workspace_size(h: Handle, prob: Problem, chunk: int, opts: Opts | None = None) -> int:
+    b = ctypes.c_size_t()
+    ps = prob.struct()
+    o = opts if opts is not None else Opts()
+    _check(lib().lsms_workspace_size(h.ptr, ctypes.byref(ps), ctypes.byref(o), int(chunk), ctypes.byref(b)),
+           "lsms_workspace_size")
+    return int(b.value)
+
+
+def tau00_solve(h: Handle, prob: Problem, work: torch.Tensor, opts: Opts | None = None, tau=None, info=None):
+    """Fused build + solve in `work` (a device byte buffer); returns (tau00 [n, kk, kk], info)."""
+    kk = prob.kk
+    if tau is None:
+        tau = torch.empty(max(prob.n_inst, 1) * kk * kk, dtype=torch.complex128, device="cuda")
+    if info is None:
+        info = torch.empty(max(prob.n_inst, 1), dtype=torch.int32, device="cuda")
+    ps = prob.struct()
+    o = opts if opts is not None else Opts()
+    _check(lib().tau00_solve(h.ptr, ctypes.byref(ps), ctypes.byref(o), _ptr(tau), _ptr(info), _ptr(work),
+                             work.numel() * work.element_size(), _stream()), "tau00_solve")
+    return _tau_view(tau, kk)[:prob.n_inst], info[:prob.n_inst]
+
+
+def problem_for_workload(h: Handle, w, max_liz: int = 1024) -> Problem:
+    """Upload a workload's inputs (supercell, centres, cutoffs, energies, phase
+    shifts) and extract every instance's LIZ with lsms_build_liz.  The
+    problem's max_liz is the largest LIZ found (one device-to-host read)."""
+    liz = build_liz(h, w.atom_pos, w.atom_species, w.box, w.centre, w.rc, max_liz)
+    n_max = int(liz["liz_n"].max().item()) if w.centre.shape[0] else 1
+    if n_max > max_liz:
+        raise RuntimeError(f"a LIZ has {n_max} sites, above max_liz={max_liz}")
+    return Problem(w.lmax, liz["liz_off"], liz["pos"], liz["species"], w.energies, w.e_idx, w.delta,
+                   max_liz=n_max)

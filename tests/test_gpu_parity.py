@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Bars: bit-exact for the LIZ (indices, order, relative vectors); M elementwise
+within 1e-13 of max|M|; tau00 within rel_F = ||tau - tau_ref||_F / ||tau_ref||_F
+<= 1e-12 per instance (the plain FP64 target).  The oracle's tau00 is refined
+with 80-bit residuals, so its own error is far below that bar.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL_TAU = 1e-12
+TOL_M = 1e-13
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def P():
+    _torch()
+    import paper_2308_16317_amd as P
+
+    return P
+
+
+@pytest.fixture(scope="module")
+def h(P):
+    return P.Handle()
+
+
+def rel_f(got, ref):
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    num = np.linalg.norm((got - ref).reshape(got.shape[0], -1), axis=1)
+    den = np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)
+    return num / den
+
+
+def _oracle_tau(w):
+    return oracle.tau00_workload(w)
+
+
+_CACHE = {}
+
+
+def oracle_tau_cached(key, w):
+    if key not in _CACHE:
+        _CACHE[key] = _oracle_tau(w)
+    return _CACHE[key]
+
+
+def _solve(P, h, w, nb=0, chunk=0, work_gb=None):
+    torch = _torch()
+    prob = P.problem_for_workload(h, w)
+    opts = P.Opts(0, nb, chunk, 0)
+    one = P.workspace_size(h, prob, 1, opts)
+    n_slots = prob.n_inst if chunk == 0 else min(chunk, prob.n_inst)
+    if work_gb is not None:
+        n_slots = max(1, min(prob.n_inst, int(work_gb * 2 ** 30 // one)))
+    work = torch.empty(one * max(1, n_slots), dtype=torch.uint8, device="cuda")
+    tau, info = P.tau00_solve(h, prob, work, opts)
+    torch.cuda.synchronize()
+    return tau.cpu().numpy(), info.cpu().numpy()
+
+
+# ---------------------------------------------------------------- a1 LIZ
+@pytest.mark.parametrize("which", ["config1", "config4"])
+def test_liz_bit_exact(P, h, which):
+    w = inputs.config1() if which == "config1" else inputs.config4(n_inst=96)
+    liz = P.build_liz(h, w.atom_pos, w.atom_species, w.box, w.centre, w.rc, 256, with_atoms=True)
+    off = liz["liz_off"].cpu().numpy()
+    n = liz["liz_n"].cpu().numpy()
+    pos = liz["pos"].cpu().numpy()
+    atom = liz["atom"].cpu().numpy()
+    spec = liz["species"].cpu().numpy()
+    for i, (c, rc) in enumerate(zip(w.centre, w.rc)):
+        rel, idx = oracle.liz(w.atom_pos, w.box, int(c), float(rc))
+        assert n[i] == rel.shape[0]
+        a, b = off[i], off[i + 1]
+        assert b - a == rel.shape[0]
+        np.testing.assert_array_equal(atom[a:b], idx)
+        np.testing.assert_array_equal(pos[a:b], rel)
+        np.testing.assert_array_equal(spec[a:b], w.atom_species[idx])
+
+
+# ---------------------------------------------------------- a2 + a3 build
+@pytest.mark.parametrize("lmax", [0, 1, 3, 4])
+def test_build_kkr_matches_oracle(P, h, lmax):
+    torch = _torch()
+    w = inputs.config1()
+    if lmax != 3:
+        w = w.with_lmax(lmax)
+    w = inputs.subset(w, np.arange(0, 128, 9))
+    prob = P.problem_for_workload(h, w)
+    liz_off = prob.liz_off.cpu().numpy()
+    N = prob.kk * np.diff(liz_off)
+    m_off = np.concatenate([[0], np.cumsum(N * N)[:-1]]).astype(np.int64)
+    M = torch.zeros(int((N * N).sum()), dtype=torch.complex128, device="cuda")
+    info = P.build_kkr(h, prob, M, torch.as_tensor(m_off, device="cuda"))
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    Mh = M.cpu().numpy()
+    pos = prob.pos.cpu().numpy()
+    spec = prob.species.cpu().numpy()
+    C, _ = oracle.gaunt(lmax)
+    for i in range(prob.n_inst):
+        a, b = liz_off[i], liz_off[i + 1]
+        e = w.e_idx[i]
+        ref, st = oracle.build_m(lmax, pos[a:b], spec[a:b], w.energies[e], w.delta[:, e, :], C)
+        got = Mh[m_off[i]:m_off[i] + N[i] * N[i]].reshape(N[i], N[i]).T  # column-major
+        assert st == 0
+        assert np.abs(got - ref).max() <= TOL_M * np.abs(ref).max()
+
+
+# ---------------------------------------------------------- a4 + a5 tau00
+def test_tau00_batched_config1_all(P, h):
+    torch = _torch()
+    w = inputs.config1()
+    ref, rinfo = oracle_tau_cached("cfg1", w)
+    assert np.all(rinfo == 0)
+    prob = P.problem_for_workload(h, w)
+    N = prob.kk * np.diff(prob.liz_off.cpu().numpy())
+    m_off = np.concatenate([[0], np.cumsum(N * N)[:-1]]).astype(np.int64)
+    M = torch.zeros(int((N * N).sum()), dtype=torch.complex128, device="cuda")
+    moff = torch.as_tensor(m_off, device="cuda")
+    info_b = P.build_kkr(h, prob, M, moff)
+    tau, info = P.tau00_batched(h, prob, M, moff)
+    torch.cuda.synchronize()
+    assert np.all(info_b.cpu().numpy() == 0) and np.all(info.cpu().numpy() == 0)
+    err = rel_f(tau.cpu().numpy(), ref)
+    print("config1 batched rel_F max", err.max(), "median", np.median(err))
+    assert err.max() <= TOL_TAU
+
+
+@pytest.mark.parametrize("nb,chunk", [(0, 0), (16, 7), (32, 50), (48, 1)])
+def test_tau00_solve_config1_nb_chunk(P, h, nb, chunk):
+    w = inputs.config1()
+    ref, _ = oracle_tau_cached("cfg1", w)
+    tau, info = _solve(P, h, w, nb=nb, chunk=chunk)
+    assert np.all(info == 0)
+    err = rel_f(tau, ref)
+    assert err.max() <= TOL_TAU, (nb, chunk, err.max())
+
+
+@pytest.mark.parametrize("lmax", [0, 1, 2, 4])
+def test_tau00_other_lmax(P, h, lmax):
+    # N = 13, 52, 117, 325: ragged tails smaller than one 16-row tile, and kk = 25
+    w = inputs.subset(inputs.config1().with_lmax(lmax), np.arange(0, 128, 5))
+    ref, rinfo = _oracle_tau(w)
+    tau, info = _solve(P, h, w)
+    assert np.all(info == 0) and np.all(rinfo == 0)
+    assert rel_f(tau, ref).max() <= TOL_TAU
+
+
+def test_tau00_ragged_config4(P, h):
+    w = inputs.config4(n_inst=1024)
+    w = inputs.subset(w, [0, 1, 2, 3, 500, 1023])
+    ref, rinfo = _oracle_tau(w)
+    tau, info = _solve(P, h, w)
+    assert np.all(info == 0) and np.all(rinfo == 0)
+    err = rel_f(tau, ref)
+    print("config4 sample rel_F", err)
+    assert err.max() <= TOL_TAU
+
+
+def test_tau00_config2_full_size_sample(P, h):
+    # the benchmarked workload (N = 2160) at both contour ends and mid-contour,
+    # through tau00_solve with the default launch configuration
+    w2 = inputs.config2()
+    idx = [0 * 32 + 0, 0 * 32 + 16, 0 * 32 + 31, 77 * 32 + 1, 200 * 32 + 30]
+    w = inputs.subset(w2, idx)
+    ref, rinfo = _oracle_tau(w)
+    tau, info = _solve(P, h, w)
+    assert np.all(info == 0) and np.all(rinfo == 0)
+    err = rel_f(tau, ref)
+    print("config2 sample rel_F", err)
+    assert err.max() <= TOL_TAU
+    # tau00 is complex symmetric
+    sym = np.abs(tau - tau.transpose(0, 2, 1)).max(axis=(1, 2)) / np.abs(tau).max(axis=(1, 2))
+    assert sym.max() <= TOL_TAU
+
+
+# --------------------------------------------------------- edge cases
+def test_one_atom_and_zero_t(P, h):
+    torch = _torch()
+    w = inputs.config1()
+    e = np.array([0, 5, 15], np.int32)
+    prob = P.Problem(3, [0, 1, 2, 3], np.zeros((3, 3)), [0, 1, 0], w.energies, e, w.delta)
+    work = torch.empty(P.workspace_size(h, prob, 3), dtype=torch.uint8, device="cuda")
+    tau, info = P.tau00_solve(h, prob, work)
+    torch.cuda.synchronize()
+    tau = tau.cpu().numpy()
+    lv = np.array([int(np.floor(np.sqrt(L) + 1e-9)) for L in range(16)])
+    for q, s in enumerate([0, 1, 0]):
+        t = oracle.tmat(3, w.energies[e[q]], w.delta[s, e[q]])
+        np.testing.assert_allclose(tau[q], np.diag(t[lv]), rtol=0, atol=1e-15 * np.abs(t).max())
+    assert np.all(info.cpu().numpy() == 0)
+    # t = 0 everywhere: tau00 = 0
+    w0 = inputs.subset(inputs.config1(), [0, 1])
+    w0.delta = np.zeros_like(w0.delta)
+    tau0, info0 = _solve(P, h, w0)
+    assert np.all(info0 == 0) and np.all(tau0 == 0)
+
+
+def test_dimer_closed_form(P, h):
+    torch = _torch()
+    E = 0.25 + 0.1j
+    delta = np.array([[[0.3 + 0.02j]], [[-0.7 + 0.05j]]])
+    R = np.array([[0, 0, 0], [2.0, -3.0, 1.5]])
+    prob = P.Problem(0, [0, 2], R, [0, 1], [E], [0], delta)
+    work = torch.empty(P.workspace_size(h, prob, 1), dtype=torch.uint8, device="cuda")
+    tau, info = P.tau00_solve(h, prob, work)
+    torch.cuda.synchronize()
+    tA = oracle.tmat(0, E, delta[0, 0])[0]
+    tB = oracle.tmat(0, E, delta[1, 0])[0]
+    r = np.linalg.norm(R[1])
+    g = -np.exp(1j * np.sqrt(E) * r) / r
+    ref = tA / (1 - tA * tB * g * g)
+    assert info.cpu().numpy()[0] == 0
+    assert abs(tau.cpu().numpy()[0, 0, 0] - ref) <= 1e-14 * abs(ref)
+
+
+def test_error_codes(P, h):
+    torch = _torch()
+    w = inputs.subset(inputs.config1(), [0, 1, 2])
+    prob = P.problem_for_workload(h, w)
+    # coincident sites in instance 1, NaN phase shift for instance 2's energy
+    pos = prob.pos.clone()
+    off = prob.liz_off.cpu().numpy()
+    pos[off[1] + 4] = pos[off[1] + 3]
+    delta = torch.as_tensor(w.delta.copy())
+    delta[1, w.e_idx[2], 2] = float("nan")
+    bad = P.Problem(3, prob.liz_off, pos, prob.species, w.energies, w.e_idx, delta, max_liz=prob.max_liz)
+    work = torch.empty(P.workspace_size(h, bad, 3), dtype=torch.uint8, device="cuda")
+    tau, info = P.tau00_solve(h, bad, work)
+    torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    tau = tau.cpu().numpy()
+    assert info[0] == 0 and info[1] == -2 and info[2] == -1
+    assert np.all(np.isnan(tau[1]))
+    # empty batch is a no-op; an undersized workspace is rejected
+    empty = P.Problem(3, [0], np.zeros((0, 3)), np.zeros(0), w.energies, np.zeros(0), w.delta, max_liz=13)
+    t0, i0 = P.tau00_solve(h, empty, work)
+    assert t0.shape[0] == 0
+    with pytest.raises(RuntimeError):
+        P.tau00_solve(h, prob, work[:16])
+
+
+def test_deterministic(P, h):
+    w = inputs.subset(inputs.config1(), np.arange(0, 128, 3))
+    t1, _ = _solve(P, h, w)
+    t2, _ = _solve(P, h, w, chunk=5)
+    assert np.array_equal(np.ascontiguousarray(t1).view(np.uint64), np.ascontiguousarray(t2).view(np.uint64))
