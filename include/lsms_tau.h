@@ -49,6 +49,11 @@ extern "C" {
 #define LSMS_EHIP (-100)
 #define LSMS_PREC_FP64 0
 
+/* lsms_opts.flags */
+#define LSMS_PERSISTENT 1 /* tau00_solve: one persistent fused kernel, work queue in LPT order */
+#define LSMS_GRAPH 2      /* tau00_solve: capture the launches in a hipGraph on the first call with
+                             a given argument set and replay it afterwards (non-null stream) */
+
 typedef struct lsms_handle_s *lsms_handle_t;
 
 /* One batch of (site, energy) instances with ragged LIZs.  The struct itself
@@ -75,9 +80,11 @@ typedef struct {
 
 typedef struct {
     int32_t precision;   /* LSMS_PREC_FP64                                             */
-    int32_t nb;          /* panel width of the LU, 0 = default (64); 16..64, multiple of 16 */
-    int32_t chunk;       /* tau00_solve: instances per workspace pass, 0 = as many as fit */
-    int32_t reserved;
+    int32_t nb;          /* panel width of the LU, 0 = tuned value (lsms_autotune) or 64;
+                            otherwise 16..64, a multiple of 16                          */
+    int32_t chunk;       /* tau00_solve without LSMS_PERSISTENT: instances per pass,
+                            0 = as many as fit                                          */
+    int32_t flags;       /* LSMS_PERSISTENT | LSMS_GRAPH                                */
 } lsms_opts;
 
 /* Create a handle bound to HIP device `device`: uploads the real Gaunt
@@ -136,17 +143,41 @@ int build_kkr(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *
 int tau00_batched(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *m_off, const lsms_opts *opts,
                   double *tau00, int32_t *info, void *work, size_t work_bytes, void *stream);
 
-/* Workspace that tau00_solve needs to process `chunk` instances per pass:
- * chunk * (kk*max_liz)^2 * 16 bytes (one M slot per instance). */
+/* Workspace of tau00_solve.  Without LSMS_PERSISTENT: `chunk` instances per
+ * pass, chunk * (kk*max_liz)^2 * 16 bytes (one M slot per instance).  With
+ * LSMS_PERSISTENT (chunk ignored): one 256-byte-aligned M slot per resident
+ * workgroup of the persistent kernel (one per compute unit), plus a work
+ * counter and the instance order (4 bytes per instance). */
 int lsms_workspace_size(lsms_handle_t h, const lsms_problem *p, const lsms_opts *opts, int32_t chunk,
                         size_t *bytes);
 
-/* Fused build_kkr + tau00_batched: M never leaves the device workspace; the
- * instances are processed in passes of floor(work_bytes / slot) (or
- * opts->chunk) instances.  Arguments as above; work is a device buffer of at
- * least lsms_workspace_size(.., 1, ..) bytes. */
+/* Fused LIZ-to-tau00 solve (paper Sec. 2.2 per LIZ, Sec. 5: M built on the
+ * GPU): M never leaves the device workspace.
+ * Without LSMS_PERSISTENT the instances are processed in passes of
+ * floor(work_bytes / slot) (or opts->chunk) instances, each pass a build
+ * launch and an elimination launch.  With LSMS_PERSISTENT, one launch of
+ * resident workgroups takes instances from a device counter in order of
+ * decreasing LIZ size (longest first), builds each M in the workgroup's own
+ * slot and eliminates it; ragged batches need no padding.  With LSMS_GRAPH
+ * the launches are captured once per argument set into a hipGraph kept by
+ * the handle and replayed (if `stream` is already capturing, the launches
+ * are simply recorded into the caller's capture).  Arguments as
+ * tau00_batched; work is a device buffer of lsms_workspace_size bytes. */
 int tau00_solve(lsms_handle_t h, const lsms_problem *p, const lsms_opts *opts, double *tau00, int32_t *info,
                 void *work, size_t work_bytes, void *stream);
+
+/* Autotuner: times tau00_solve (with opts->flags) on the problem for panel
+ * widths nb = 16, 32, 48, 64 after one warm-up each, stores the fastest as
+ * the handle's panel width for matrices of this problem's size bucket
+ * (kk*max_liz rounded up to 128), returns it in *best_nb and the four
+ * timings (ms, in the order above) in ms_out[4] (host).  Synchronises the
+ * stream. */
+int lsms_autotune(lsms_handle_t h, const lsms_problem *p, const lsms_opts *opts, double *tau00, int32_t *info,
+                  void *work, size_t work_bytes, void *stream, int32_t *best_nb, double *ms_out);
+
+/* Sets the handle's panel width for matrices of size n (the bucket of
+ * lsms_autotune), e.g. from a cached tuning result. */
+int lsms_set_tuned_nb(lsms_handle_t h, int32_t n, int32_t nb);
 
 #ifdef __cplusplus
 }

@@ -5,13 +5,17 @@ marshals arguments.  PyTorch provides device memory and the current stream.
 """
 
 from .lsms import (  # noqa: F401
+    GRAPH,
+    PERSISTENT,
     Handle,
     Opts,
     Problem,
+    autotune,
     build_kkr,
     build_liz,
     lib,
     problem_for_workload,
+    set_tuned_nb,
     tau00_batched,
     tau00_solve,
     workspace_size,

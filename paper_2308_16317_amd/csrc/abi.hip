@@ -1,5 +1,6 @@
 // C ABI of liblsms_tau (declared in include/lsms_tau.h): argument
-// validation on the host, the handle's Gaunt tables, and the launches.
+// validation on the host, the handle (Gaunt tables, tuned panel widths,
+// captured graphs), and the launches.
 #include <cstring>
 #include <vector>
 
@@ -13,6 +14,8 @@ namespace {
 
 constexpr int kMaxLmax = 4;
 constexpr int kMaxSpeciesAbi = 8;
+constexpr int kBuckets = 33;     // tuned panel width per 128-wide bucket of N <= 4096
+constexpr int kGraphCache = 8;
 
 __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -30,7 +33,8 @@ int check_problem(const lsms_problem* p) {
   if (!p) return -2;
   if (p->lmax < 0 || p->lmax > kMaxLmax) return -2;
   if (p->n_inst < 0 || p->n_species < 1 || p->n_species > kMaxSpeciesAbi || p->n_energy < 1) return -2;
-  if (p->max_liz < 1) return -2;
+  if (p->max_liz < 1 || p->max_liz > 1024) return -2;
+  if ((int64_t)(p->lmax + 1) * (p->lmax + 1) * p->max_liz > 4096) return -2;
   if (p->n_inst > 0 && (!p->liz_off || !p->pos || !p->species || !p->energy || !p->e_idx || !p->delta))
     return -2;
   return 0;
@@ -53,17 +57,36 @@ lsms_prob_dev to_dev(const lsms_problem* p) {
   return d;
 }
 
-int check_opts(const lsms_opts* o, int32_t* nb) {
-  *nb = 64;
+int check_opts(const lsms_opts* o) {
   if (!o) return 0;
   if (o->precision != LSMS_PREC_FP64) return -1;
-  if (o->nb != 0) {
-    if (o->nb < 16 || o->nb > 64 || (o->nb % 16) != 0) return -1;
-    *nb = o->nb;
-  }
+  if (o->nb != 0 && (o->nb < 16 || o->nb > 64 || (o->nb % 16) != 0)) return -1;
   if (o->chunk < 0) return -1;
+  if (o->flags & ~(LSMS_PERSISTENT | LSMS_GRAPH)) return -1;
   return 0;
 }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t slot_elems(const lsms_problem* p) {
+  const size_t kk = (size_t)(p->lmax + 1) * (p->lmax + 1);
+  const size_t n = kk * (size_t)p->max_liz;
+  return n * n;
+}
+
+int bucket_of(int64_t n) { return (int)((n + 127) / 128 < kBuckets ? (n + 127) / 128 : kBuckets - 1); }
+
+struct GraphEntry {
+  bool used;
+  lsms_problem prob;
+  lsms_opts opts;
+  double* tau00;
+  int32_t* info;
+  void* work;
+  size_t work_bytes;
+  hipGraphExec_t exec;
+  uint64_t stamp;
+};
 
 }  // namespace
 
@@ -71,12 +94,83 @@ struct lsms_handle_s {
   int device;
   lsms_gaunt_dev g[kMaxLmax + 1];
   void* mem[kMaxLmax + 1];
+  int32_t tuned_nb[kBuckets];
+  GraphEntry graphs[kGraphCache];
+  uint64_t clock;
 };
 
 #define HIP_TRY(x)                          \
   do {                                      \
     if ((x) != hipSuccess) return LSMS_EHIP; \
   } while (0)
+
+namespace {
+
+int32_t panel_width(const lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o) {
+  if (o && o->nb) return o->nb;
+  const int32_t t = h->tuned_nb[bucket_of((int64_t)(p->lmax + 1) * (p->lmax + 1) * p->max_liz)];
+  return t ? t : 64;
+}
+
+struct PersistLayout {
+  int grid;
+  size_t order_off, slots_off, slot_stride, total;  // bytes
+};
+
+int persist_layout(const lsms_handle_s* h, const lsms_problem* p, PersistLayout* L) {
+  const lsms_prob_dev d = to_dev(p);
+  if (lsms_persistent_grid(d, h->device, &L->grid) != hipSuccess) return LSMS_EHIP;
+  L->order_off = 256;
+  L->slots_off = align256(256 + 4 * (size_t)p->n_inst);
+  L->slot_stride = align256(slot_elems(p) * 16);
+  L->total = L->slots_off + (size_t)L->grid * L->slot_stride;
+  return 0;
+}
+
+// Enqueue the launches of one tau00_solve call (no graph handling).
+int enqueue_solve(lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o, double* tau00, int32_t* info,
+                  void* work, size_t work_bytes, hipStream_t s) {
+  const lsms_prob_dev d = to_dev(p);
+  const int32_t nb = panel_width(h, p, o);
+  if (o && (o->flags & LSMS_PERSISTENT)) {
+    PersistLayout L;
+    if (persist_layout(h, p, &L)) return LSMS_EHIP;
+    if (work_bytes < L.total) return -7;
+    char* w = (char*)work;
+    int32_t* counter = (int32_t*)w;
+    int32_t* order = (int32_t*)(w + L.order_off);
+    if (fill_i32(counter, 0, 1, s) != hipSuccess) return LSMS_EHIP;
+    if (lsms_launch_lpt_order(d, order, s) != hipSuccess) return LSMS_EHIP;
+    if (lsms_launch_persistent(d, h->g[p->lmax], order, counter, (double*)(w + L.slots_off),
+                               (int64_t)(L.slot_stride / 16), L.grid, tau00, info, nb, s) != hipSuccess)
+      return LSMS_EHIP;
+    return 0;
+  }
+  const size_t slot_b = slot_elems(p) * 16;
+  if (work_bytes < slot_b) return -7;
+  int64_t chunk = (int64_t)(work_bytes / slot_b);
+  if (o && o->chunk > 0 && o->chunk < chunk) chunk = o->chunk;
+  if (fill_i32(info, 0, p->n_inst, s) != hipSuccess) return LSMS_EHIP;
+  for (int64_t i0 = 0; i0 < p->n_inst; i0 += chunk) {
+    const int32_t n = (int32_t)(p->n_inst - i0 < chunk ? p->n_inst - i0 : chunk);
+    if (lsms_launch_build(d, h->g[p->lmax], (int32_t)i0, n, (double*)work, nullptr, (int64_t)slot_elems(p), info,
+                          s) != hipSuccess)
+      return LSMS_EHIP;
+    if (lsms_launch_lu_fp64(d, (int32_t)i0, n, (double*)work, nullptr, (int64_t)slot_elems(p), tau00, info, 1, nb,
+                            s) != hipSuccess)
+      return LSMS_EHIP;
+  }
+  return 0;
+}
+
+bool same_args(const GraphEntry& e, const lsms_problem* p, const lsms_opts* o, double* tau00, int32_t* info,
+               void* work, size_t work_bytes) {
+  return e.used && std::memcmp(&e.prob, p, sizeof(lsms_problem)) == 0 &&
+         std::memcmp(&e.opts, o, sizeof(lsms_opts)) == 0 && e.tau00 == tau00 && e.info == info && e.work == work &&
+         e.work_bytes == work_bytes;
+}
+
+}  // namespace
 
 extern "C" int lsms_create(lsms_handle_t* out, int device) {
   if (!out) return -1;
@@ -109,7 +203,11 @@ extern "C" int lsms_create(lsms_handle_t* out, int device) {
     h->g[lmax].lmax = lmax;
     h->g[lmax].nnz = (int32_t)coef.size();
   }
-  if (hipDeviceSynchronize() != hipSuccess) return LSMS_EHIP;
+  if (lsms_prepare_kernels() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    for (int q = 0; q <= kMaxLmax; ++q) (void)hipFree(h->mem[q]);
+    delete h;
+    return LSMS_EHIP;
+  }
   *out = h;
   return 0;
 }
@@ -117,6 +215,8 @@ extern "C" int lsms_create(lsms_handle_t* out, int device) {
 extern "C" int lsms_destroy(lsms_handle_t h) {
   if (!h) return -1;
   (void)hipSetDevice(h->device);
+  for (int q = 0; q < kGraphCache; ++q)
+    if (h->graphs[q].used) (void)hipGraphExecDestroy(h->graphs[q].exec);
   for (int q = 0; q <= kMaxLmax; ++q) (void)hipFree(h->mem[q]);
   delete h;
   return 0;
@@ -169,8 +269,7 @@ extern "C" int tau00_batched(lsms_handle_t h, const lsms_problem* p, double* M, 
   if (!h) return -1;
   int r = check_problem(p);
   if (r) return r;
-  int32_t nb;
-  if (check_opts(opts, &nb)) return -5;
+  if (check_opts(opts)) return -5;
   if (p->n_inst == 0) return 0;
   if (!M) return -3;
   if (!m_off) return -4;
@@ -178,15 +277,10 @@ extern "C" int tau00_batched(lsms_handle_t h, const lsms_problem* p, double* M, 
   if (!info) return -7;
   (void)hipSetDevice(h->device);
   const lsms_prob_dev d = to_dev(p);
-  if (lsms_launch_lu_fp64(d, 0, p->n_inst, M, m_off, 0, tau00, info, 0, nb, (hipStream_t)stream) != hipSuccess)
+  if (lsms_launch_lu_fp64(d, 0, p->n_inst, M, m_off, 0, tau00, info, 0, panel_width(h, p, opts),
+                          (hipStream_t)stream) != hipSuccess)
     return LSMS_EHIP;
   return 0;
-}
-
-static size_t slot_elems(const lsms_problem* p) {
-  const size_t kk = (size_t)(p->lmax + 1) * (p->lmax + 1);
-  const size_t n = kk * (size_t)p->max_liz;
-  return n * n;
 }
 
 extern "C" int lsms_workspace_size(lsms_handle_t h, const lsms_problem* p, const lsms_opts* opts, int32_t chunk,
@@ -194,10 +288,16 @@ extern "C" int lsms_workspace_size(lsms_handle_t h, const lsms_problem* p, const
   if (!h) return -1;
   int r = check_problem(p);
   if (r) return r;
-  int32_t nb;
-  if (check_opts(opts, &nb)) return -3;
-  if (chunk < 1) return -4;
+  if (check_opts(opts)) return -3;
   if (!bytes) return -5;
+  if (opts && (opts->flags & LSMS_PERSISTENT)) {
+    (void)hipSetDevice(h->device);
+    PersistLayout L;
+    if (persist_layout(h, p, &L)) return LSMS_EHIP;
+    *bytes = L.total;
+    return 0;
+  }
+  if (chunk < 1) return -4;
   *bytes = (size_t)chunk * slot_elems(p) * 16;
   return 0;
 }
@@ -207,27 +307,112 @@ extern "C" int tau00_solve(lsms_handle_t h, const lsms_problem* p, const lsms_op
   if (!h) return -1;
   int r = check_problem(p);
   if (r) return r;
-  int32_t nb;
-  if (check_opts(opts, &nb)) return -3;
+  if (check_opts(opts)) return -3;
   if (p->n_inst == 0) return 0;
   if (!tau00) return -4;
   if (!info) return -5;
-  const size_t slot_b = slot_elems(p) * 16;
-  if (!work || work_bytes < slot_b) return -7;
-  int64_t chunk = (int64_t)(work_bytes / slot_b);
-  if (opts && opts->chunk > 0 && opts->chunk < chunk) chunk = opts->chunk;
+  if (!work) return -6;
   (void)hipSetDevice(h->device);
   hipStream_t s = (hipStream_t)stream;
-  const lsms_prob_dev d = to_dev(p);
-  if (fill_i32(info, 0, p->n_inst, s) != hipSuccess) return LSMS_EHIP;
-  for (int64_t i0 = 0; i0 < p->n_inst; i0 += chunk) {
-    const int32_t n = (int32_t)(p->n_inst - i0 < chunk ? p->n_inst - i0 : chunk);
-    if (lsms_launch_build(d, h->g[p->lmax], (int32_t)i0, n, (double*)work, nullptr, (int64_t)slot_elems(p), info,
-                          s) != hipSuccess)
-      return LSMS_EHIP;
-    if (lsms_launch_lu_fp64(d, (int32_t)i0, n, (double*)work, nullptr, (int64_t)slot_elems(p), tau00, info, 1, nb,
-                            s) != hipSuccess)
-      return LSMS_EHIP;
+  const bool graph = opts && (opts->flags & LSMS_GRAPH) && s != nullptr;
+  if (!graph) return enqueue_solve(h, p, opts, tau00, info, work, work_bytes, s);
+
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return LSMS_EHIP;
+  if (cs != hipStreamCaptureStatusNone) return enqueue_solve(h, p, opts, tau00, info, work, work_bytes, s);
+  GraphEntry* hit = nullptr;
+  for (int q = 0; q < kGraphCache; ++q)
+    if (same_args(h->graphs[q], p, opts, tau00, info, work, work_bytes)) hit = &h->graphs[q];
+  if (!hit) {
+    // check the arguments outside the capture (errors must not leave a capture open)
+    if (opts->flags & LSMS_PERSISTENT) {
+      PersistLayout L;
+      if (persist_layout(h, p, &L)) return LSMS_EHIP;
+      if (work_bytes < L.total) return -7;
+    } else if (work_bytes < slot_elems(p) * 16) {
+      return -7;
+    }
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return LSMS_EHIP;
+    const int er = enqueue_solve(h, p, opts, tau00, info, work, work_bytes, s);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(s, &g);
+    if (er != 0 || ee != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return er != 0 ? er : LSMS_EHIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return LSMS_EHIP;
+    GraphEntry* slot = &h->graphs[0];
+    for (int q = 0; q < kGraphCache; ++q) {
+      if (!h->graphs[q].used) {
+        slot = &h->graphs[q];
+        break;
+      }
+      if (h->graphs[q].stamp < slot->stamp) slot = &h->graphs[q];
+    }
+    if (slot->used) (void)hipGraphExecDestroy(slot->exec);
+    slot->used = true;
+    slot->prob = *p;
+    slot->opts = *opts;
+    slot->tau00 = tau00;
+    slot->info = info;
+    slot->work = work;
+    slot->work_bytes = work_bytes;
+    slot->exec = exec;
+    hit = slot;
   }
+  hit->stamp = ++h->clock;
+  return hipGraphLaunch(hit->exec, s) == hipSuccess ? 0 : LSMS_EHIP;
+}
+
+extern "C" int lsms_set_tuned_nb(lsms_handle_t h, int32_t n, int32_t nb) {
+  if (!h) return -1;
+  if (n < 1 || n > 4096) return -2;
+  if (nb < 16 || nb > 64 || nb % 16) return -3;
+  h->tuned_nb[bucket_of(n)] = nb;
+  return 0;
+}
+
+extern "C" int lsms_autotune(lsms_handle_t h, const lsms_problem* p, const lsms_opts* opts, double* tau00,
+                             int32_t* info, void* work, size_t work_bytes, void* stream, int32_t* best_nb,
+                             double* ms_out) {
+  if (!h) return -1;
+  int r = check_problem(p);
+  if (r) return r;
+  if (check_opts(opts)) return -3;
+  if (!best_nb) return -9;
+  (void)hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  lsms_opts o = opts ? *opts : lsms_opts{LSMS_PREC_FP64, 0, 0, 0};
+  o.flags &= ~LSMS_GRAPH;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int32_t cand[4] = {16, 32, 48, 64};
+  int32_t best = 64;
+  float best_ms = 0.0f;
+  for (int c = 0; c < 4; ++c) {
+    o.nb = cand[c];
+    int er = tau00_solve(h, p, &o, tau00, info, work, work_bytes, stream);
+    if (er) return er;
+    HIP_TRY(hipEventRecord(e0, s));
+    er = tau00_solve(h, p, &o, tau00, info, work, work_bytes, stream);
+    if (er) return er;
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms_out) ms_out[c] = ms;
+    if (c == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = cand[c];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->tuned_nb[bucket_of((int64_t)(p->lmax + 1) * (p->lmax + 1) * p->max_liz)] = best;
+  *best_nb = best;
   return 0;
 }

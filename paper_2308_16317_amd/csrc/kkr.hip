@@ -21,6 +21,7 @@
 #include <complex>
 #include <vector>
 
+#include "kkr_device.h"
 #include "lsms_common.h"
 
 using namespace lsms;
@@ -135,161 +136,27 @@ void lsms_gaunt_host(int lmax, std::vector<int32_t>& row_ptr, std::vector<int16_
 namespace {
 
 constexpr int kBuildThreads = 256;
-constexpr int kPairs = 4;            // row blocks processed per round (one per wave)
-constexpr int kMaxL2 = 8;            // 2 * lmax for lmax <= 4
-constexpr int kMaxKK2 = (kMaxL2 + 1) * (kMaxL2 + 1);
-constexpr int kMaxSpecies = 8;
-constexpr int kMaxLm = 5;
 
-// Real spherical harmonics up to l2 for direction r (unnormalised vector),
-// computed by lane m of a wave for m = 0..l2, written to Y[L''].
-__device__ void ylm_column(int m, int l2, double x, double y, double z, double* Y) {
-  const double rho2 = x * x + y * y;
-  const double r = sqrt(rho2 + z * z);
-  const double rho = sqrt(rho2);
-  const double ct = z / r, st = rho / r;
-  // cos(m phi) + i sin(m phi) as (x + i y)^m / rho^m
-  double cm = 1.0, sm = 0.0;
-  if (rho > 0.0) {
-    const double cp = x / rho, sp = y / rho;
-    for (int k = 0; k < m; ++k) {
-      const double c2 = cm * cp - sm * sp;
-      sm = sm * cp + cm * sp;
-      cm = c2;
-    }
-  } else if (m > 0) {
-    cm = 0.0;
-  }
-  double pmm = 1.0;
-  for (int k = 1; k <= m; ++k) pmm *= (2.0 * k - 1.0) * st;
-  double p_lm2 = 0.0, p_lm1 = 0.0;
-  for (int l = m; l <= l2; ++l) {
-    double p;
-    if (l == m) p = pmm;
-    else if (l == m + 1) p = ct * (2.0 * m + 1.0) * p_lm1;
-    else p = ((2.0 * l - 1.0) * ct * p_lm1 - (l + m - 1.0) * p_lm2) / (double)(l - m);
-    p_lm2 = p_lm1;
-    p_lm1 = p;
-    double ratio = 1.0;  // (l-m)!/(l+m)!
-    for (int k = l - m + 1; k <= l + m; ++k) ratio /= (double)k;
-    const double nlm = sqrt((2.0 * l + 1.0) * ratio * 0.07957747154594767);  // 1/(4 pi)
-    if (m == 0) {
-      Y[l * l + l] = nlm * p;
-    } else {
-      const double s = 1.4142135623730951 * nlm * p;
-      Y[l * l + l + m] = s * cm;
-      Y[l * l + l - m] = s * sm;
-    }
-  }
-}
-
+// One workgroup per (block column j, instance).
 __global__ __launch_bounds__(kBuildThreads) void build_kkr_kernel(lsms_prob_dev p, lsms_gaunt_dev g, int i0,
                                                                  int n, double* __restrict__ Mbase,
                                                                  const int64_t* __restrict__ m_off, int64_t slot,
                                                                  int32_t* __restrict__ info) {
-  __shared__ double Ysh[kPairs][kMaxKK2];
-  __shared__ zd hsh[kPairs][kMaxL2 + 1];
-  __shared__ zd tsh[kMaxSpecies][kMaxLm];
-  __shared__ int bad;
-
+  __shared__ BuildSmem sb;
   const int inst = i0 + blockIdx.y;
   const int j = blockIdx.x;
-  const int64_t a = p.liz_off[inst];
-  const int nliz = (int)(p.liz_off[inst + 1] - a);
+  const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
   if (j >= nliz) return;
-  {
-    const int ee = p.e_idx[inst];
-    if (nliz > p.max_liz || ee < 0 || ee >= p.n_energy) {
-      if (j == 0 && threadIdx.x == 0) info[inst] = -3;
-      return;
-    }
+  const int ee = p.e_idx[inst];
+  if (nliz > p.max_liz || ee < 0 || ee >= p.n_energy) {
+    if (j == 0 && threadIdx.x == 0) info[inst] = -3;
+    return;
   }
-  const int kk = p.kk, lmax = p.lmax, l2 = 2 * lmax;
-  const int64_t N = (int64_t)kk * nliz;
   zd* M = reinterpret_cast<zd*>(Mbase) + (m_off ? m_off[inst] : (int64_t)(inst - i0) * slot);
-  const int e = p.e_idx[inst];
-  const zd E = reinterpret_cast<const zd*>(p.energy)[e];
-  const zd kap = zsqrt(E);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-  if (tid < p.n_species * (lmax + 1)) {
-    const int s = tid / (lmax + 1), l = tid % (lmax + 1);
-    const zd d = reinterpret_cast<const zd*>(p.delta)[((int64_t)s * p.n_energy + e) * (lmax + 1) + l];
-    tsh[s][l] = tmat_from_delta(d, kap);
-  }
-  if (tid == 0) bad = 0;
-  __shared__ int bad_species;
-  if (tid == 0) bad_species = 0;
-  const double* rel = p.pos + 3 * a;
-  const int32_t* spec = p.species + a;
-  const double rjx = rel[3 * j], rjy = rel[3 * j + 1], rjz = rel[3 * j + 2];
-  // -4 pi i kappa
-  const zd pref = zmake(4.0 * M_PI * kap.y, -4.0 * M_PI * kap.x);
-  const int kk2pairs = kk * kk;
-  __syncthreads();
-
-  for (int ib = 0; ib < nliz; ib += kPairs) {
-    // phase 1: wave w prepares Y and h for row block ib + w
-    const int iw = ib + wave;
-    if (iw < nliz && iw != j) {
-      const double Rx = rel[3 * iw] - rjx, Ry = rel[3 * iw + 1] - rjy, Rz = rel[3 * iw + 2] - rjz;
-      const double R = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
-      if (R < 1e-8) {
-        if (lane == 0) bad = 1;
-      } else {
-        if (lane <= l2) ylm_column(lane, l2, Rx, Ry, Rz, Ysh[wave]);
-        if (lane == 0) {
-          const zd z = zmake(kap.x * R, kap.y * R);
-          const zd iz = zinv(z);
-          const zd eiz = zexpi(z);
-          zd h0 = zmul(zmake(0.0, -1.0), zmul(eiz, iz));        // -i e^{iz}/z
-          zd h1 = zmul(h0, zmake(iz.x, iz.y - 1.0));            // h0 (1/z - i)
-          hsh[wave][0] = h0;
-          if (l2 >= 1) hsh[wave][1] = h1;
-          for (int l = 1; l < l2; ++l) {
-            const zd h2 = zsub(zscale(zmul(iz, h1), 2.0 * l + 1.0), h0);
-            hsh[wave][l + 1] = h2;
-            h0 = h1;
-            h1 = h2;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    // phase 2: all threads write the kk x kk blocks of the prepared rows
-    const int nb = min(kPairs, nliz - ib);
-    for (int q = tid; q < nb * kk2pairs; q += kBuildThreads) {
-      const int slotw = q / kk2pairs, pidx = q % kk2pairs;
-      const int iw2 = ib + slotw;
-      const int L = pidx % kk, Lp = pidx / kk;
-      zd val;
-      if (iw2 == j) {
-        val = zmake(L == Lp ? 1.0 : 0.0, 0.0);
-      } else {
-        double sr = 0.0, si = 0.0;
-        const int e0 = g.row_ptr[pidx], e1 = g.row_ptr[pidx + 1];
-        for (int k = e0; k < e1; ++k) {
-          const int Lpp = g.lpp[k];
-          const double cy = g.coef[k] * Ysh[slotw][Lpp];
-          const zd h = hsh[slotw][l_of(Lpp)];
-          sr += cy * h.x;
-          si += cy * h.y;
-        }
-        const zd G = zmul(pref, zmake(sr, si));
-        const int sp = spec[iw2];
-        const bool sp_ok = sp >= 0 && sp < p.n_species;
-        if (!sp_ok) bad_species = 1;
-        const zd t = tsh[sp_ok ? sp : 0][l_of(L)];
-        const zd tg = zmul(t, G);
-        val = zmake(-tg.x, -tg.y);
-      }
-      M[(int64_t)(kk * j + Lp) * N + (int64_t)kk * iw2 + L] = val;
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  if (tid == 0 && bad_species) info[inst] = -3;
-  else if (tid == 0 && bad) info[inst] = -2;
+  build_setup<kBuildThreads>(p, g, inst, sb);
+  build_column<kBuildThreads>(p, inst, j, M, sb);
+  if (threadIdx.x == 0 && sb.bad_species) info[inst] = -3;
+  else if (threadIdx.x == 0 && sb.bad) info[inst] = -2;
 }
 
 }  // namespace

@@ -1,0 +1,185 @@
+// Device routines of the KKR matrix assembly (M = 1 - t G over a LIZ), shared
+// by the stand-alone build kernel and the fused persistent kernel.
+//
+//   M_ii = I,   M_ij = -diag(t_{s(i), l(L)}) G^{ij}   (i != j)
+//   G^{ij}_{LL'} = -4 pi i kappa sum_L'' i^{l-l'+l''} C^{L''}_{LL'} h_l''(kappa R) Y_L''(R^),
+// R = R_i - R_j, kappa = sqrt(E) (principal branch), real spherical
+// harmonics without the Condon-Shortley factor, h the spherical Hankel
+// function of the first kind, t_l = -(1/kappa) sin(delta_l) exp(i delta_l)
+// (paper Sec. 2.1: t and the propagator g0 between two different sites;
+// Sec. 2.2: over the LIZ).  M is column-major, ld N = kk * n_liz.
+#pragma once
+
+#include "lsms_common.h"
+
+namespace lsms {
+
+constexpr int kBuildChunk = 64;  // LIZ row blocks prepared per phase
+constexpr int kBMaxL2 = 8;       // 2 * lmax for lmax <= 4
+constexpr int kBMaxKK2 = (kBMaxL2 + 1) * (kBMaxL2 + 1);
+constexpr int kBMaxKK = 25;
+constexpr int kBMaxNnz = 2304;   // >= nonzeros of the lmax = 4 Gaunt table (2229)
+constexpr int kBMaxSpecies = 8;
+constexpr int kBMaxLm = 5;
+
+struct BuildSmem {
+  double Y[kBuildChunk][kBMaxKK2];
+  zd h[kBuildChunk][kBMaxL2 + 1];
+  zd t[kBMaxSpecies][kBMaxLm];
+  double coef[kBMaxNnz];
+  int32_t rp[kBMaxKK * kBMaxKK + 1];
+  int16_t lpp[kBMaxNnz];
+  int8_t lof[kBMaxNnz];
+  int spec[kBuildChunk];
+  int bad, bad_species;
+};
+
+// Real spherical harmonics Y_L''(r), l'' <= l2, of a nonzero vector r, by one
+// thread: cos(m phi) + i sin(m phi) as (x + i y)^m / rho^m, P_l^m by upward
+// recurrence in l from P_m^m = (2m-1)!! sin^m(theta).
+__device__ inline void ylm_all(int l2, double x, double y, double z, double* __restrict__ Y) {
+  const double rho2 = x * x + y * y;
+  const double r = sqrt(rho2 + z * z);
+  const double rho = sqrt(rho2);
+  const double ct = z / r, st = rho / r;
+  const double cp = rho > 0.0 ? x / rho : 1.0, sp = rho > 0.0 ? y / rho : 0.0;
+  double cm = 1.0, sm = 0.0, pmm = 1.0;
+  for (int m = 0; m <= l2; ++m) {
+    if (m > 0) {
+      const double c2 = cm * cp - sm * sp;
+      sm = sm * cp + cm * sp;
+      cm = c2;
+      pmm *= (2.0 * m - 1.0) * st;
+    }
+    double p_lm2 = 0.0, p_lm1 = 0.0;
+    for (int l = m; l <= l2; ++l) {
+      double pl;
+      if (l == m) pl = pmm;
+      else if (l == m + 1) pl = ct * (2.0 * m + 1.0) * p_lm1;
+      else pl = ((2.0 * l - 1.0) * ct * p_lm1 - (l + m - 1.0) * p_lm2) / (double)(l - m);
+      p_lm2 = p_lm1;
+      p_lm1 = pl;
+      double ratio = 1.0;  // (l-m)!/(l+m)!
+      for (int k = l - m + 1; k <= l + m; ++k) ratio /= (double)k;
+      const double nlm = sqrt((2.0 * l + 1.0) * ratio * 0.07957747154594767);  // 1/(4 pi)
+      if (m == 0) {
+        Y[l * l + l] = nlm * pl;
+      } else {
+        const double sc = 1.4142135623730951 * nlm * pl;
+        Y[l * l + l + m] = sc * cm;
+        Y[l * l + l - m] = sc * sm;
+      }
+    }
+  }
+}
+
+// Spherical Hankel functions h_l(z), l <= l2, by upward recurrence from
+// h_0 = -i e^{iz}/z and h_1 = h_0 (1/z - i).
+__device__ inline void hankel_all(int l2, zd z, zd* __restrict__ h) {
+  const zd iz = zinv(z);
+  const zd eiz = zexpi(z);
+  zd h0 = zmul(zmake(0.0, -1.0), zmul(eiz, iz));
+  zd h1 = zmul(h0, zmake(iz.x, iz.y - 1.0));
+  h[0] = h0;
+  if (l2 >= 1) h[1] = h1;
+  for (int l = 1; l < l2; ++l) {
+    const zd h2 = zsub(zscale(zmul(iz, h1), 2.0 * l + 1.0), h0);
+    h[l + 1] = h2;
+    h0 = h1;
+    h1 = h2;
+  }
+}
+
+// Stage the Gaunt list and the instance's t-matrices in LDS.  Ends with a
+// barrier.
+template <int kNT>
+__device__ void build_setup(const lsms_prob_dev& p, const lsms_gaunt_dev& g, int inst, BuildSmem& sb) {
+  const int tid = threadIdx.x;
+  const int lmax = p.lmax, kkp = p.kk * p.kk;
+  const int e = p.e_idx[inst];
+  const zd kap = zsqrt(reinterpret_cast<const zd*>(p.energy)[e]);
+  if (tid < p.n_species * (lmax + 1)) {
+    const int s = tid / (lmax + 1), l = tid % (lmax + 1);
+    const zd d = reinterpret_cast<const zd*>(p.delta)[((int64_t)s * p.n_energy + e) * (lmax + 1) + l];
+    sb.t[s][l] = tmat_from_delta(d, kap);
+  }
+  for (int q = tid; q <= kkp; q += kNT) sb.rp[q] = g.row_ptr[q];
+  for (int q = tid; q < g.nnz; q += kNT) {
+    const int lpp = g.lpp[q];
+    sb.lpp[q] = (int16_t)lpp;
+    sb.lof[q] = (int8_t)l_of(lpp);
+    sb.coef[q] = g.coef[q];
+  }
+  if (tid == 0) {
+    sb.bad = 0;
+    sb.bad_species = 0;
+  }
+  __syncthreads();
+}
+
+// Block column j of M: phase A, one thread per LIZ row block of a chunk,
+// prepares Y_L''(R_ij) and h_l''(kappa R_ij); phase B sweeps the chunk's
+// kk x kk blocks with entry (L, L') of row block i at index L + kk (i + nb L'),
+// so consecutive threads write consecutive rows of one column.
+template <int kNT>
+__device__ void build_column(const lsms_prob_dev& p, int inst, int j, zd* __restrict__ M, BuildSmem& sb) {
+  const int tid = threadIdx.x;
+  const int64_t a = p.liz_off[inst];
+  const int nliz = (int)(p.liz_off[inst + 1] - a);
+  const int kk = p.kk, l2 = 2 * p.lmax;
+  const int64_t N = (int64_t)kk * nliz;
+  const zd kap = zsqrt(reinterpret_cast<const zd*>(p.energy)[p.e_idx[inst]]);
+  const double* rel = p.pos + 3 * a;
+  const int32_t* spec = p.species + a;
+  const double rjx = rel[3 * j], rjy = rel[3 * j + 1], rjz = rel[3 * j + 2];
+  const zd pref = zmake(4.0 * M_PI * kap.y, -4.0 * M_PI * kap.x);  // -4 pi i kappa
+  for (int ib = 0; ib < nliz; ib += kBuildChunk) {
+    const int nb = min(kBuildChunk, nliz - ib);
+    if (tid < nb) {
+      const int iw = ib + tid;
+      const int sp = spec[iw];
+      if (sp < 0 || sp >= p.n_species) sb.bad_species = 1;
+      sb.spec[tid] = (sp >= 0 && sp < p.n_species) ? sp : 0;
+      if (iw != j) {
+        const double Rx = rel[3 * iw] - rjx, Ry = rel[3 * iw + 1] - rjy, Rz = rel[3 * iw + 2] - rjz;
+        const double R = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+        if (R < 1e-8) {
+          sb.bad = 1;
+        } else {
+          ylm_all(l2, Rx, Ry, Rz, sb.Y[tid]);
+          hankel_all(l2, zmake(kap.x * R, kap.y * R), sb.h[tid]);
+        }
+      }
+    }
+    __syncthreads();
+    const int per_col = nb * kk;
+    for (int q = tid; q < per_col * kk; q += kNT) {
+      const int Lp = q / per_col;
+      const int rem = q - Lp * per_col;
+      const int il = rem / kk;
+      const int L = rem - il * kk;
+      const int iw = ib + il;
+      zd val;
+      if (iw == j) {
+        val = zmake(L == Lp ? 1.0 : 0.0, 0.0);
+      } else {
+        double sr = 0.0, si = 0.0;
+        const int pidx = L + kk * Lp;
+        const int e0 = sb.rp[pidx], e1 = sb.rp[pidx + 1];
+        for (int k = e0; k < e1; ++k) {
+          const double cy = sb.coef[k] * sb.Y[il][sb.lpp[k]];
+          const zd h = sb.h[il][sb.lof[k]];
+          sr += cy * h.x;
+          si += cy * h.y;
+        }
+        const zd G = zmul(pref, zmake(sr, si));
+        const zd tg = zmul(sb.t[sb.spec[il]][l_of(L)], G);
+        val = zmake(-tg.x, -tg.y);
+      }
+      M[(int64_t)(kk * j + Lp) * N + (int64_t)kk * iw + L] = val;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace lsms

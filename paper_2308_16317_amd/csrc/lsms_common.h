@@ -106,3 +106,13 @@ hipError_t lsms_launch_build(const lsms_prob_dev& p, const lsms_gaunt_dev& g, in
 hipError_t lsms_launch_lu_fp64(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M,
                                const int64_t* m_off, int64_t slot, double* tau00, int32_t* info,
                                int keep_info, int32_t nb, hipStream_t s);
+
+// Persistent fused path: instance order (largest LIZ first), resident grid
+// size, and the fused build + elimination launch.  `counter` must be zero at
+// launch; slot is the per-workgroup matrix slot in complex elements.
+hipError_t lsms_launch_lpt_order(const lsms_prob_dev& p, int32_t* order, hipStream_t s);
+hipError_t lsms_persistent_grid(const lsms_prob_dev& p, int device, int* grid);
+hipError_t lsms_launch_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order,
+                                  int32_t* counter, double* work, int64_t slot, int grid, double* tau00,
+                                  int32_t* info, int32_t nb, hipStream_t s);
+hipError_t lsms_prepare_kernels();

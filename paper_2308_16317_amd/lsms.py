@@ -43,12 +43,16 @@ class Opts(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("nb", ctypes.c_int32),
         ("chunk", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
     ]
 
 
+PERSISTENT = 1
+GRAPH = 2
+
+
 SYMBOLS = ("lsms_create", "lsms_destroy", "lsms_build_liz", "build_kkr", "tau00_batched",
-           "lsms_workspace_size", "tau00_solve")
+           "lsms_workspace_size", "tau00_solve", "lsms_autotune", "lsms_set_tuned_nb")
 
 
 def lib():
@@ -68,6 +72,10 @@ def lib():
                                           ctypes.POINTER(ctypes.c_size_t)]
         L.tau00_solve.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(Opts), _P, _P, _P, ctypes.c_size_t,
                                   _P]
+        L.lsms_autotune.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(Opts), _P, _P, _P,
+                                    ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_double)]
+        L.lsms_set_tuned_nb.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
         for s in SYMBOLS:
             getattr(L, s).restype = ctypes.c_int
         _lib = L
@@ -145,26 +153,33 @@ class Problem:
                         _ptr(self.delta))
 
 
-def build_liz(h: Handle, atom_pos, atom_species, box, centre, rc, max_liz: int, with_atoms: bool = False):
+def build_liz(h: Handle, atom_pos, atom_species, box, centre, rc, max_liz: int, with_atoms: bool = False,
+              out: dict | None = None):
     """lsms_build_liz: returns dict(liz_n, liz_off, pos, species[, atom]) of device tensors
-    (pos/species are the compact rows liz_off[0]..liz_off[n])."""
+    (pos/species are the compact rows liz_off[0]..liz_off[n]).  `out`, a dict
+    returned by an earlier call with the same sizes, is reused as the output."""
     ap = _dev(atom_pos, torch.float64)
     asp = _dev(atom_species, torch.int32)
     ce = _dev(centre, torch.int32)
     r = _dev(rc, torch.float64)
     n = int(ce.shape[0])
     box_h = (ctypes.c_double * 3)(*[float(b) for b in box])
-    out = dict(
-        liz_n=torch.empty(max(n, 1), dtype=torch.int32, device="cuda"),
-        liz_off=torch.empty(n + 1, dtype=torch.int64, device="cuda"),
-        pos=torch.empty((max(n, 1) * max_liz, 3), dtype=torch.float64, device="cuda"),
-        species=torch.empty(max(n, 1) * max_liz, dtype=torch.int32, device="cuda"),
-    )
-    if with_atoms:
-        out["atom"] = torch.empty(max(n, 1) * max_liz, dtype=torch.int32, device="cuda")
+    if out is None:
+        out = dict(
+            liz_n=torch.empty(max(n, 1), dtype=torch.int32, device="cuda"),
+            liz_off=torch.empty(n + 1, dtype=torch.int64, device="cuda"),
+            pos=torch.empty((max(n, 1) * max_liz, 3), dtype=torch.float64, device="cuda"),
+            species=torch.empty(max(n, 1) * max_liz, dtype=torch.int32, device="cuda"),
+        )
+        if with_atoms:
+            out["atom"] = torch.empty(max(n, 1) * max_liz, dtype=torch.int32, device="cuda")
+    else:
+        out = dict(out)
+        out["liz_n"] = out["liz_n_buf"]
     _check(lib().lsms_build_liz(h.ptr, _ptr(ap), _ptr(asp), int(ap.shape[0]), box_h, _ptr(ce), _ptr(r), n,
                                 int(max_liz), _ptr(out["liz_n"]), _ptr(out["liz_off"]), _ptr(out["pos"]),
                                 _ptr(out["species"]), _ptr(out.get("atom")), _stream()), "lsms_build_liz")
+    out["liz_n_buf"] = out["liz_n"]
     out["liz_n"] = out["liz_n"][:n]
     return out
 
@@ -232,3 +247,22 @@ def problem_for_workload(h: Handle, w, max_liz: int = 1024) -> Problem:
         raise RuntimeError(f"a LIZ has {n_max} sites, above max_liz={max_liz}")
     return Problem(w.lmax, liz["liz_off"], liz["pos"], liz["species"], w.energies, w.e_idx, w.delta,
                    max_liz=n_max)
+
+
+def autotune(h: Handle, prob: Problem, work: torch.Tensor, opts: Opts | None = None):
+    """lsms_autotune: returns (best panel width, {nb: ms}) and stores it in the handle."""
+    kk = prob.kk
+    tau = torch.empty(max(prob.n_inst, 1) * kk * kk, dtype=torch.complex128, device="cuda")
+    info = torch.empty(max(prob.n_inst, 1), dtype=torch.int32, device="cuda")
+    ps = prob.struct()
+    o = opts if opts is not None else Opts()
+    best = ctypes.c_int32()
+    ms = (ctypes.c_double * 4)()
+    _check(lib().lsms_autotune(h.ptr, ctypes.byref(ps), ctypes.byref(o), _ptr(tau), _ptr(info), _ptr(work),
+                               work.numel() * work.element_size(), _stream(), ctypes.byref(best), ms),
+           "lsms_autotune")
+    return int(best.value), dict(zip((16, 32, 48, 64), list(ms)))
+
+
+def set_tuned_nb(h: Handle, n: int, nb: int):
+    _check(lib().lsms_set_tuned_nb(h.ptr, int(n), int(nb)), "lsms_set_tuned_nb")

@@ -31,6 +31,7 @@ def test_struct_layouts():
 
     assert ctypes.sizeof(lsms._Problem) == 6 * 4 + 6 * 8
     assert ctypes.sizeof(lsms.Opts) == 4 * 4
+    assert [f[0] for f in lsms.Opts._fields_] == ["precision", "nb", "chunk", "flags"]
 
 
 def test_null_handle_rejected_without_gpu():

@@ -264,3 +264,96 @@ def test_deterministic(P, h):
     t1, _ = _solve(P, h, w)
     t2, _ = _solve(P, h, w, chunk=5)
     assert np.array_equal(np.ascontiguousarray(t1).view(np.uint64), np.ascontiguousarray(t2).view(np.uint64))
+
+
+# ------------------------------------------- persistent ragged batch (a7)
+def _solve_flags(P, h, w, flags, nb=0, stream=None):
+    torch = _torch()
+    prob = P.problem_for_workload(h, w)
+    opts = P.Opts(0, nb, 0, flags)
+    work = torch.empty(P.workspace_size(h, prob, prob.n_inst, opts), dtype=torch.uint8, device="cuda")
+    tau, info = P.tau00_solve(h, prob, work, opts)
+    torch.cuda.synchronize()
+    return tau.cpu().numpy(), info.cpu().numpy()
+
+
+@pytest.mark.parametrize("which", ["config1", "config1-lmax4", "config4"])
+def test_persistent_matches_oracle(P, h, which):
+    if which == "config1":
+        w = inputs.config1()
+        ref, rinfo = oracle_tau_cached("cfg1", w)
+    elif which == "config1-lmax4":
+        w = inputs.subset(inputs.config1().with_lmax(4), np.arange(0, 128, 7))
+        ref, rinfo = _oracle_tau(w)
+    else:
+        w = inputs.subset(inputs.config4(n_inst=1024), [5, 6, 7, 8, 700])
+        ref, rinfo = _oracle_tau(w)
+    tau, info = _solve_flags(P, h, w, P.PERSISTENT)
+    assert np.all(info == 0) and np.all(rinfo == 0)
+    err = rel_f(tau, ref)
+    assert err.max() <= TOL_TAU, err.max()
+
+
+def test_persistent_error_codes(P, h):
+    # An instance that fails its build takes the kernel's error path and the
+    # workgroup goes on to the next instance (regression: that path once left
+    # all but one thread re-reading a stale work counter).
+    torch = _torch()
+    w = inputs.subset(inputs.config1(), [0, 1, 2])
+    prob = P.problem_for_workload(h, w)
+    pos = prob.pos.clone()
+    off = prob.liz_off.cpu().numpy()
+    pos[off[1] + 4] = pos[off[1] + 3]
+    bad = P.Problem(3, prob.liz_off, pos, prob.species, w.energies, w.e_idx, w.delta, max_liz=prob.max_liz)
+    opts = P.Opts(0, 0, 0, P.PERSISTENT)
+    work = torch.empty(P.workspace_size(h, bad, 0, opts), dtype=torch.uint8, device="cuda")
+    tau, info = P.tau00_solve(h, bad, work, opts)
+    torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    assert info[0] == 0 and info[1] == -2 and info[2] == 0
+    assert np.all(np.isnan(tau.cpu().numpy()[1]))
+
+
+def test_graph_replay(P, h):
+    # captured once, replayed with eager work and an input change between
+    # replays; every replay is checked against the oracle
+    torch = _torch()
+    w = inputs.subset(inputs.config1(), np.arange(0, 128, 4))
+    ref, _ = _oracle_tau(w)
+    w2 = inputs.subset(inputs.config1(), np.arange(0, 128, 4))
+    w2.e_idx = (w2.e_idx + 5) % 16
+    ref2, _ = _oracle_tau(w2)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        prob = P.problem_for_workload(h, w)
+        opts = P.Opts(0, 0, 0, P.PERSISTENT | P.GRAPH)
+        work = torch.empty(P.workspace_size(h, prob, 0, opts), dtype=torch.uint8, device="cuda")
+        tau = torch.empty(prob.n_inst * 256, dtype=torch.complex128, device="cuda")
+        info = torch.empty(prob.n_inst, dtype=torch.int32, device="cuda")
+        for rep in range(4):
+            if rep == 2:
+                prob.e_idx.copy_(torch.as_tensor(w2.e_idx, device="cuda"))
+            tau.fill_(0)
+            t, i = P.tau00_solve(h, prob, work, opts, tau=tau, info=info)
+            s.synchronize()
+            junk = torch.randn(1000, device="cuda").sum()  # eager work between replays
+            s.synchronize()
+            assert np.all(i.cpu().numpy() == 0)
+            err = rel_f(t.cpu().numpy(), ref if rep < 2 else ref2)
+            assert err.max() <= TOL_TAU, (rep, err.max())
+        del junk
+
+
+def test_autotune(P, h):
+    torch = _torch()
+    w = inputs.subset(inputs.config1(), np.arange(0, 128, 2))
+    ref, _ = _oracle_tau(w)
+    prob = P.problem_for_workload(h, w)
+    opts = P.Opts(0, 0, 0, P.PERSISTENT)
+    work = torch.empty(P.workspace_size(h, prob, 0, opts), dtype=torch.uint8, device="cuda")
+    best, ms = P.autotune(h, prob, work, opts)
+    assert best in (16, 32, 48, 64) and all(v > 0 for v in ms.values())
+    tau, info = P.tau00_solve(h, prob, work, opts)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    assert rel_f(tau.cpu().numpy(), ref).max() <= TOL_TAU
