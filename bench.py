@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 METRIC = "τ00 solves/s at N=2160, 1e-10 rel: mixed/batched vs plain FP64; TFLOP/s vs peak"
 
 
@@ -57,6 +58,10 @@ def main():
     ap.add_argument("--mode", choices=["chunked", "persistent", "graph"], default="persistent",
                     help="chunked: build_kkr + tau00_batched per pass; persistent: tau00_solve with one "
                          "fused persistent kernel; graph: the same, replayed from a captured hipGraph")
+    ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64",
+                    help="fp64: complex FP64 elimination; fp32ir: complex FP32 factorisation and solves with "
+                         "FP64 iterative refinement (persistent and graph modes)")
+    ap.add_argument("--tol", type=float, default=0.0, help="refinement tolerance of fp32ir (0 = library default)")
     ap.add_argument("--chunk", type=int, default=1024, help="instances per build/LU launch (chunked)")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--n-inst", type=int, default=0, help="limit the batch (0 = all 8192)")
@@ -66,6 +71,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.precision == "fp32ir" and args.mode == "chunked":
+        print(json.dumps({"error": "--precision fp32ir runs through tau00_solve: use --mode persistent or graph"}))
         sys.exit(2)
 
     import torch
@@ -103,8 +111,12 @@ def main():
     else:
         chunk = w.n_inst
         flags = P.PERSISTENT | (P.GRAPH if args.mode == "graph" else 0)
-        opts = P.Opts(0, args.nb, 0, flags)
-        kernel = "tau00_persistent_kernel (LIZ-to-tau00: build + elimination)"
+        if args.precision == "fp32ir":
+            opts = P.Opts(P.PREC_FP32_IR, args.nb, 0, flags, 0, 0, args.tol)
+            kernel = "tau00_mixed_persistent_kernel (LIZ-to-tau00: build + FP32 LU + FP64 refinement)"
+        else:
+            opts = P.Opts(P.PREC_FP64, args.nb, 0, flags)
+            kernel = "tau00_persistent_kernel (LIZ-to-tau00: build + elimination)"
         work = None
 
     liz_buf = None
@@ -151,9 +163,10 @@ def main():
     sizes = (liz["liz_n"]).cpu().numpy()
     if sizes.max() > max_liz:
         raise RuntimeError("LIZ larger than the bench's max_liz")
-    bad = int((info != 0).sum().item())
+    fallback = int((info == P.INFO_FP64_FALLBACK).sum().item()) if args.precision == "fp32ir" else 0
+    bad = int((info != 0).sum().item()) - fallback
     if bad:
-        raise RuntimeError(f"{bad} instances reported nonzero info")
+        raise RuntimeError(f"{bad} instances reported an error in info")
     n_inst = w.n_inst
     Ns = kk * sizes.astype(np.float64)
     flops_step = float(np.sum(8.0 / 3.0 * Ns ** 3))
@@ -161,6 +174,9 @@ def main():
     lu_ms = [e0.elapsed_time(e1) for (e0, e1, _, _) in events]
     lu_flops = [float(np.sum(8.0 / 3.0 * (Nc.double().cpu().numpy()) ** 3)) for (_, _, _, Nc) in events]
     ach = float(np.sum(lu_flops) / (np.sum(lu_ms) * 1e-3) / 1e12)
+    peak = FP32_PEAK_TFLOPS if args.precision == "fp32ir" else FP64_PEAK_TFLOPS
+    form = ("complex FP32 LU + FP64 iterative refinement to 1e-12 (FP64 fallback per instance)"
+            if args.precision == "fp32ir" else "complex FP64 LU/Schur")
     out = {
         "metric": METRIC,
         "value": n_inst * args.steps / dt,
@@ -172,15 +188,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if args.precision == "fp32ir" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: fcc NiAu 50/50, 256 sites x 32 energies = {n_inst} instances, "
-                               f"135-atom LIZ, N=2160, lmax=3, complex FP64 LU/Schur",
+                               f"135-atom LIZ, N=2160, lmax=3, {form}",
                    "n_inst": n_inst, "N": int(Ns.max()), "lmax": w.lmax, "mode": args.mode,
-                   "instances_per_launch": chunk},
+                   "precision": args.precision, "instances_per_launch": chunk,
+                   "fp64_fallbacks": fallback},
         "tflops": flops_step / (ms * 1e-3) / 1e12,
-        "roofline": {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                     "frac": ach / peak, "traffic": None,
                      "kernel": kernel, "ms_per_launch": float(np.mean(lu_ms)),
                      "instances_per_launch": chunk},
     }

@@ -28,7 +28,9 @@
  *
  * Per-instance info[i]
  *    0  success
- *   k>0 an exactly zero pivot at elimination step k (1-based, in the
+ *   256 (LSMS_INFO_FP64_FALLBACK, LSMS_PREC_FP32_IR only) success, computed
+ *       by the FP64 path after the refinement did not converge
+ *   k>0 (k < 256) an exactly zero pivot at elimination step k (1-based, in the
  *       library's elimination order: non-central columns first, the central
  *       block last); tau00 of the instance is NaN
  *   -1  non-finite tau00 (non-finite energy or phase shift, overflow)
@@ -47,7 +49,20 @@ extern "C" {
 #endif
 
 #define LSMS_EHIP (-100)
-#define LSMS_PREC_FP64 0
+
+/* lsms_opts.precision */
+#define LSMS_PREC_FP64 0    /* complex FP64 elimination throughout                          */
+#define LSMS_PREC_FP32_IR 1 /* complex FP32 factorisation and solves (matrix cores), FP64
+                               residuals and solution, iterative refinement to opts->tol;
+                               an addition to the paper, whose matrices are complex FP64
+                               throughout (Sec. 3.2); the refinement is the classical
+                               mixed-precision scheme (Carson and Higham, SIAM J. Sci.
+                               Comput. 40 (2018) A817); tau00_solve only */
+
+/* info bit set by LSMS_PREC_FP32_IR when the refinement did not reach tol
+ * within max_refine steps (or the FP32 factorisation met an exactly zero
+ * pivot) and the instance was recomputed by the FP64 path */
+#define LSMS_INFO_FP64_FALLBACK 256
 
 /* lsms_opts.flags */
 #define LSMS_PERSISTENT 1 /* tau00_solve: one persistent fused kernel, work queue in LPT order */
@@ -79,12 +94,17 @@ typedef struct {
 } lsms_problem;
 
 typedef struct {
-    int32_t precision;   /* LSMS_PREC_FP64                                             */
+    int32_t precision;   /* LSMS_PREC_FP64 or LSMS_PREC_FP32_IR                         */
     int32_t nb;          /* panel width of the LU, 0 = tuned value (lsms_autotune) or 64;
                             otherwise 16..64, a multiple of 16                          */
     int32_t chunk;       /* tau00_solve without LSMS_PERSISTENT: instances per pass,
                             0 = as many as fit                                          */
     int32_t flags;       /* LSMS_PERSISTENT | LSMS_GRAPH                                */
+    int32_t max_refine;  /* LSMS_PREC_FP32_IR: refinement steps at most, 0 = 10; 1..100  */
+    int32_t reserved;    /* must be 0                                                   */
+    double tol;          /* LSMS_PREC_FP32_IR: stop once the last correction of the central
+                            block is at most tol times the block (Frobenius norms);
+                            0 = 1e-12; otherwise 1e-15 .. 1e-3                          */
 } lsms_opts;
 
 /* Create a handle bound to HIP device `device`: uploads the real Gaunt
@@ -139,15 +159,20 @@ int build_kkr(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *
  *   tau00  device [n_inst][kk*kk] complex out, column-major kk x kk:
  *          tau00[i][L + kk*L'] = ([M_i^{-1}]_{00} diag(t_0))_{L L'}
  *   info   device [n_inst] out
- *   work / work_bytes: unused by this precision (may be NULL / 0). */
+ *   work / work_bytes: unused (may be NULL / 0).
+ * Only LSMS_PREC_FP64 (the FP32 form needs the matrix unmodified and a
+ * workspace: tau00_solve); another precision returns -5. */
 int tau00_batched(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *m_off, const lsms_opts *opts,
                   double *tau00, int32_t *info, void *work, size_t work_bytes, void *stream);
 
 /* Workspace of tau00_solve.  Without LSMS_PERSISTENT: `chunk` instances per
- * pass, chunk * (kk*max_liz)^2 * 16 bytes (one M slot per instance).  With
- * LSMS_PERSISTENT (chunk ignored): one 256-byte-aligned M slot per resident
- * workgroup of the persistent kernel (one per compute unit), plus a work
- * counter and the instance order (4 bytes per instance). */
+ * pass, one slot per instance.  With LSMS_PERSISTENT (chunk ignored): one
+ * 256-byte-aligned slot per resident workgroup of the persistent kernel (one
+ * per compute unit), plus a work counter and the instance order (4 bytes per
+ * instance).  A slot holds the FP64 matrix, n^2 * 16 bytes for
+ * n = kk*max_liz; with LSMS_PREC_FP32_IR also its FP32 copy (n^2 * 8), the
+ * FP32 and FP64 right-hand sides (n * kp * 24, kp = 16 or 32) and the pivots
+ * (n * 4), each 256-byte aligned. */
 int lsms_workspace_size(lsms_handle_t h, const lsms_problem *p, const lsms_opts *opts, int32_t chunk,
                         size_t *bytes);
 

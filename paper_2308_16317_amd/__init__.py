@@ -6,7 +6,10 @@ marshals arguments.  PyTorch provides device memory and the current stream.
 
 from .lsms import (  # noqa: F401
     GRAPH,
+    INFO_FP64_FALLBACK,
     PERSISTENT,
+    PREC_FP32_IR,
+    PREC_FP64,
     Handle,
     Opts,
     Problem,

@@ -59,7 +59,9 @@ lsms_prob_dev to_dev(const lsms_problem* p) {
 
 int check_opts(const lsms_opts* o) {
   if (!o) return 0;
-  if (o->precision != LSMS_PREC_FP64) return -1;
+  if (o->precision != LSMS_PREC_FP64 && o->precision != LSMS_PREC_FP32_IR) return -1;
+  if (o->max_refine < 0 || o->max_refine > 100 || o->reserved != 0) return -1;
+  if (!(o->tol == 0.0 || (o->tol >= 1e-15 && o->tol <= 1e-3))) return -1;
   if (o->nb != 0 && (o->nb < 16 || o->nb > 64 || (o->nb % 16) != 0)) return -1;
   if (o->chunk < 0) return -1;
   if (o->flags & ~(LSMS_PERSISTENT | LSMS_GRAPH)) return -1;
@@ -73,6 +75,19 @@ size_t slot_elems(const lsms_problem* p) {
   const size_t n = kk * (size_t)p->max_liz;
   return n * n;
 }
+
+bool mixed(const lsms_opts* o) { return o && o->precision == LSMS_PREC_FP32_IR; }
+
+// Bytes of one instance slot: the FP64 matrix (256-byte aligned), then the
+// buffers of the precision form.
+size_t m_bytes(const lsms_problem* p) { return align256(slot_elems(p) * 16); }
+
+size_t slot_bytes(const lsms_problem* p, const lsms_opts* o) {
+  return m_bytes(p) + (mixed(o) ? (size_t)lsms_mixed_extra_bytes(to_dev(p)) : 0);
+}
+
+double ir_tol(const lsms_opts* o) { return o->tol > 0.0 ? o->tol : 1e-12; }
+int32_t ir_steps(const lsms_opts* o) { return o->max_refine > 0 ? o->max_refine : 10; }
 
 int bucket_of(int64_t n) { return (int)((n + 127) / 128 < kBuckets ? (n + 127) / 128 : kBuckets - 1); }
 
@@ -117,12 +132,14 @@ struct PersistLayout {
   size_t order_off, slots_off, slot_stride, total;  // bytes
 };
 
-int persist_layout(const lsms_handle_s* h, const lsms_problem* p, PersistLayout* L) {
+int persist_layout(const lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o, PersistLayout* L) {
   const lsms_prob_dev d = to_dev(p);
-  if (lsms_persistent_grid(d, h->device, &L->grid) != hipSuccess) return LSMS_EHIP;
+  const hipError_t e = mixed(o) ? lsms_mixed_persistent_grid(d, h->device, &L->grid)
+                                : lsms_persistent_grid(d, h->device, &L->grid);
+  if (e != hipSuccess) return LSMS_EHIP;
   L->order_off = 256;
   L->slots_off = align256(256 + 4 * (size_t)p->n_inst);
-  L->slot_stride = align256(slot_elems(p) * 16);
+  L->slot_stride = slot_bytes(p, o);
   L->total = L->slots_off + (size_t)L->grid * L->slot_stride;
   return 0;
 }
@@ -134,31 +151,40 @@ int enqueue_solve(lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o, d
   const int32_t nb = panel_width(h, p, o);
   if (o && (o->flags & LSMS_PERSISTENT)) {
     PersistLayout L;
-    if (persist_layout(h, p, &L)) return LSMS_EHIP;
+    if (persist_layout(h, p, o, &L)) return LSMS_EHIP;
     if (work_bytes < L.total) return -7;
     char* w = (char*)work;
     int32_t* counter = (int32_t*)w;
     int32_t* order = (int32_t*)(w + L.order_off);
     if (fill_i32(counter, 0, 1, s) != hipSuccess) return LSMS_EHIP;
     if (lsms_launch_lpt_order(d, order, s) != hipSuccess) return LSMS_EHIP;
-    if (lsms_launch_persistent(d, h->g[p->lmax], order, counter, (double*)(w + L.slots_off),
-                               (int64_t)(L.slot_stride / 16), L.grid, tau00, info, nb, s) != hipSuccess)
-      return LSMS_EHIP;
-    return 0;
+    const hipError_t e =
+        mixed(o) ? lsms_launch_mixed_persistent(d, h->g[p->lmax], order, counter, (unsigned char*)(w + L.slots_off),
+                                                (int64_t)L.slot_stride, (int64_t)m_bytes(p), L.grid, tau00, info, nb,
+                                                ir_tol(o), ir_steps(o), s)
+                 : lsms_launch_persistent(d, h->g[p->lmax], order, counter, (double*)(w + L.slots_off),
+                                          (int64_t)(L.slot_stride / 16), L.grid, tau00, info, nb, s);
+    return e == hipSuccess ? 0 : LSMS_EHIP;
   }
-  const size_t slot_b = slot_elems(p) * 16;
+  // chunked: M slots first, then (precision form) the per-instance extra buffers
+  const size_t mb = m_bytes(p), slot_b = slot_bytes(p, o);
   if (work_bytes < slot_b) return -7;
   int64_t chunk = (int64_t)(work_bytes / slot_b);
   if (o && o->chunk > 0 && o->chunk < chunk) chunk = o->chunk;
+  unsigned char* extra = (unsigned char*)work + (size_t)chunk * mb;
+  const int64_t xslot = (int64_t)(slot_b - mb);
   if (fill_i32(info, 0, p->n_inst, s) != hipSuccess) return LSMS_EHIP;
   for (int64_t i0 = 0; i0 < p->n_inst; i0 += chunk) {
     const int32_t n = (int32_t)(p->n_inst - i0 < chunk ? p->n_inst - i0 : chunk);
-    if (lsms_launch_build(d, h->g[p->lmax], (int32_t)i0, n, (double*)work, nullptr, (int64_t)slot_elems(p), info,
-                          s) != hipSuccess)
+    if (lsms_launch_build(d, h->g[p->lmax], (int32_t)i0, n, (double*)work, nullptr, (int64_t)(mb / 16), info, s) !=
+        hipSuccess)
       return LSMS_EHIP;
-    if (lsms_launch_lu_fp64(d, (int32_t)i0, n, (double*)work, nullptr, (int64_t)slot_elems(p), tau00, info, 1, nb,
-                            s) != hipSuccess)
-      return LSMS_EHIP;
+    const hipError_t e =
+        mixed(o) ? lsms_launch_mixed(d, (int32_t)i0, n, (double*)work, (int64_t)(mb / 16), extra, xslot, tau00, info,
+                                     nb, ir_tol(o), ir_steps(o), s)
+                 : lsms_launch_lu_fp64(d, (int32_t)i0, n, (double*)work, nullptr, (int64_t)(mb / 16), tau00, info, 1,
+                                       nb, s);
+    if (e != hipSuccess) return LSMS_EHIP;
   }
   return 0;
 }
@@ -269,7 +295,7 @@ extern "C" int tau00_batched(lsms_handle_t h, const lsms_problem* p, double* M, 
   if (!h) return -1;
   int r = check_problem(p);
   if (r) return r;
-  if (check_opts(opts)) return -5;
+  if (check_opts(opts) || mixed(opts)) return -5;
   if (p->n_inst == 0) return 0;
   if (!M) return -3;
   if (!m_off) return -4;
@@ -293,12 +319,12 @@ extern "C" int lsms_workspace_size(lsms_handle_t h, const lsms_problem* p, const
   if (opts && (opts->flags & LSMS_PERSISTENT)) {
     (void)hipSetDevice(h->device);
     PersistLayout L;
-    if (persist_layout(h, p, &L)) return LSMS_EHIP;
+    if (persist_layout(h, p, opts, &L)) return LSMS_EHIP;
     *bytes = L.total;
     return 0;
   }
   if (chunk < 1) return -4;
-  *bytes = (size_t)chunk * slot_elems(p) * 16;
+  *bytes = (size_t)chunk * slot_bytes(p, opts);
   return 0;
 }
 
@@ -327,9 +353,9 @@ extern "C" int tau00_solve(lsms_handle_t h, const lsms_problem* p, const lsms_op
     // check the arguments outside the capture (errors must not leave a capture open)
     if (opts->flags & LSMS_PERSISTENT) {
       PersistLayout L;
-      if (persist_layout(h, p, &L)) return LSMS_EHIP;
+      if (persist_layout(h, p, opts, &L)) return LSMS_EHIP;
       if (work_bytes < L.total) return -7;
-    } else if (work_bytes < slot_elems(p) * 16) {
+    } else if (work_bytes < slot_bytes(p, opts)) {
       return -7;
     }
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return LSMS_EHIP;
@@ -385,7 +411,7 @@ extern "C" int lsms_autotune(lsms_handle_t h, const lsms_problem* p, const lsms_
   if (!best_nb) return -9;
   (void)hipSetDevice(h->device);
   hipStream_t s = (hipStream_t)stream;
-  lsms_opts o = opts ? *opts : lsms_opts{LSMS_PREC_FP64, 0, 0, 0};
+  lsms_opts o = opts ? *opts : lsms_opts{LSMS_PREC_FP64, 0, 0, 0, 0, 0, 0.0};
   o.flags &= ~LSMS_GRAPH;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kBuildThreads) void build_kkr_kernel(lsms_prob_dev 
   }
   zd* M = reinterpret_cast<zd*>(Mbase) + (m_off ? m_off[inst] : (int64_t)(inst - i0) * slot);
   build_setup<kBuildThreads>(p, g, inst, sb);
-  build_column<kBuildThreads>(p, inst, j, M, sb);
+  build_column_body<kBuildThreads>(p, inst, j, M, sb);
   if (threadIdx.x == 0 && sb.bad_species) info[inst] = -3;
   else if (threadIdx.x == 0 && sb.bad) info[inst] = -2;
 }

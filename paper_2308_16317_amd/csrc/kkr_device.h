@@ -122,7 +122,7 @@ __device__ void build_setup(const lsms_prob_dev& p, const lsms_gaunt_dev& g, int
 // kk x kk blocks with entry (L, L') of row block i at index L + kk (i + nb L'),
 // so consecutive threads write consecutive rows of one column.
 template <int kNT>
-__device__ void build_column(const lsms_prob_dev& p, int inst, int j, zd* __restrict__ M, BuildSmem& sb) {
+__device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int inst, int j, zd* __restrict__ M, BuildSmem& sb) {
   const int tid = threadIdx.x;
   const int64_t a = p.liz_off[inst];
   const int nliz = (int)(p.liz_off[inst + 1] - a);
@@ -180,6 +180,14 @@ __device__ void build_column(const lsms_prob_dev& p, int inst, int j, zd* __rest
     }
     __syncthreads();
   }
+}
+
+// Out-of-line form for kernels that also eliminate (separate register
+// allocation for the build and the factorisation).
+template <int kNT>
+__device__ __noinline__ void build_column(const lsms_prob_dev& p, int inst, int j, zd* __restrict__ M,
+                                          BuildSmem& sb) {
+  build_column_body<kNT>(p, inst, j, M, sb);
 }
 
 }  // namespace lsms

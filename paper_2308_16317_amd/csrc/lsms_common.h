@@ -59,6 +59,22 @@ __device__ __forceinline__ zd tmat_from_delta(zd d, zd kap) {
 }
 __device__ __forceinline__ bool zfinite(zd a) { return isfinite(a.x) && isfinite(a.y); }
 
+// Complex FP32 counterparts (same names, float2 arguments), used by the
+// FP32 factorisation of the precision form.
+typedef float2 zf;
+__device__ __forceinline__ zf zmake(float r, float i) { return make_float2(r, i); }
+__device__ __forceinline__ zf zmul(zf a, zf b) { return zmake(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ zf zfms(zf a, zf b, zf c) {
+  return zmake(a.x - b.x * c.x + b.y * c.y, a.y - b.x * c.y - b.y * c.x);
+}
+__device__ __forceinline__ float zcabs1(zf a) { return fabsf(a.x) + fabsf(a.y); }
+__device__ __forceinline__ zf zinv(zf a) {
+  const float s = fmaxf(fabsf(a.x), fabsf(a.y));
+  const float ar = a.x / s, ai = a.y / s;
+  const float d = s * (ar * ar + ai * ai);
+  return zmake(ar / d, -ai / d);
+}
+
 __host__ __device__ __forceinline__ int l_of(int L) {
   int l = 0;
   while ((l + 1) * (l + 1) <= L) ++l;
@@ -116,3 +132,18 @@ hipError_t lsms_launch_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& 
                                   int32_t* counter, double* work, int64_t slot, int grid, double* tau00,
                                   int32_t* info, int32_t nb, hipStream_t s);
 hipError_t lsms_prepare_kernels();
+
+// Precision form (FP32 factorisation + FP64 refinement).  extra bytes per
+// instance beyond its FP64 matrix; chunked launch (M at (i-i0)*slot complex
+// elements, extra buffers at extra + (i-i0)*xslot bytes; instances whose info
+// is already nonzero are skipped) and persistent launch (slot_bytes per
+// workgroup, FP64 matrix first, its extra buffers m_bytes in).
+int64_t lsms_mixed_extra_bytes(const lsms_prob_dev& p);
+hipError_t lsms_launch_mixed(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, int64_t slot,
+                             unsigned char* extra, int64_t xslot, double* tau00, int32_t* info, int32_t nb,
+                             double tol, int32_t max_refine, hipStream_t s);
+hipError_t lsms_mixed_persistent_grid(const lsms_prob_dev& p, int device, int* grid);
+hipError_t lsms_launch_mixed_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order,
+                                        int32_t* counter, unsigned char* work, int64_t slot_bytes, int64_t m_bytes,
+                                        int grid, double* tau00, int32_t* info, int32_t nb, double tol,
+                                        int32_t max_refine, hipStream_t s);

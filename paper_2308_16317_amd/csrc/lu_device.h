@@ -1,0 +1,509 @@
+// Building blocks of the blocked complex LU used by the tau00 kernels, generic
+// over the real type R (double for the plain path, float for the
+// factorisation of the precision form).  All of them are called by every
+// thread of a 512-thread workgroup that owns one matrix.
+//
+// Matrix view.  The column-major M buffer is read as the row-major storage of
+// A = M^T; the internal index v runs over the non-central rows first and the
+// central block last: physical row/column phys(v) = v + kk for v < Nd = N - kk
+// and v - Nd for the central block.  Row interchanges of A are contiguous
+// moves and every operand of the trailing update is read in row segments.
+//
+// Pivoting is row partial pivoting restricted to rows below a limit `plim`
+// (Nd while the non-central columns are eliminated; N for the central block
+// of a full factorisation), the pivot being the row that maximises
+// |Re| + |Im|, the lowest such row on ties.
+#pragma once
+
+#include "lsms_common.h"
+
+namespace lsms {
+
+constexpr int kLuThreads = 512;
+constexpr int kLuWaves = kLuThreads / 64;
+constexpr int kNB = 64;   // maximum panel width
+constexpr int kSW = 64;   // trailing-update strip width (columns)
+constexpr int kMaxKK = 25;
+constexpr int kMaxWL = 8;
+
+template <typename R>
+struct Prec;
+
+// v_mfma_f64_16x16x4f64, D = A B + C with A 16x4, B 4x16: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; register r of lane l holds
+// D[4 r + l / 16][l % 16] (measured on gfx950).
+template <>
+struct Prec<double> {
+  typedef double2 C;
+  typedef double V4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V4 mfma(double a, double b, V4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int r, int lq) { return 4 * r + lq; }
+};
+
+// v_mfma_f32_16x16x4f32: same operand layout; register r of lane l holds
+// D[4 (l / 16) + r][l % 16] (measured on gfx950).
+template <>
+struct Prec<float> {
+  typedef float2 C;
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V4 mfma(float a, float b, V4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int r, int lq) { return 4 * lq + r; }
+};
+
+template <typename R>
+struct LuSmem {
+  typedef typename Prec<R>::C C;
+  C X[kNB][kNB];    // inverse of a triangular block
+  C U[kNB][kSW];    // U12 strip; block staging; Gauss-Jordan workspace at the end
+  C rowP[kMaxWL];   // pivot row of a leaf step
+  C rowJ[kMaxWL];
+  zd tz[kMaxKK];
+  zd pinv;
+  R redv[kLuWaves];
+  int redi[kLuWaves];
+  int ipiv[kNB];
+  int info;
+  int bad;
+  int gj_piv;
+};
+
+template <typename C>
+struct Mat {
+  C* base;
+  int64_t N;
+  int Nd, kk;
+  __device__ __forceinline__ int64_t phys(int v) const { return v < Nd ? (int64_t)v + kk : (int64_t)(v - Nd); }
+  __device__ __forceinline__ C* ptr(int r, int c) const { return base + phys(r) * N + phys(c); }
+};
+
+template <typename R>
+__device__ __forceinline__ bool better(R ob, int oi, R b, int i) {
+  return ob > b || (ob == b && oi < i);
+}
+
+// Factorises the leaf columns [lc, lc + kWL) of the panel [c, c + w), rows
+// [lc, N), with the leaf in registers (thread t owns rows lc + t + 512 q).
+// Interchanges are applied at once to the other panel columns in memory.
+// Kept out of line (with the triangle inverses and apply_swaps) so that the
+// register allocator treats the panel phase and the trailing update apart.
+template <typename R, int kR, int kWL>
+__device__ __noinline__ void leaf_factor(const Mat<typename Prec<R>::C>& A, int c, int w, int lc, int plim,
+                                         LuSmem<R>& sh) {
+  typedef typename Prec<R>::C C;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int N = (int)A.N;
+  const int wl = min(kWL, c + w - lc);
+  C a[kR][kWL];
+#pragma unroll
+  for (int q = 0; q < kR; ++q) {
+    const int v = lc + tid + kLuThreads * q;
+    if (v < N) {
+      const C* row = A.ptr(v, lc);
+#pragma unroll
+      for (int k = 0; k < kWL; ++k) a[q][k] = (k < wl) ? row[k] : zmake(R(0), R(0));
+    } else {
+#pragma unroll
+      for (int k = 0; k < kWL; ++k) a[q][k] = zmake(R(0), R(0));
+    }
+  }
+  for (int jj = 0; jj < wl; ++jj) {
+    const int j = lc + jj;
+    R best = R(-1);
+    int bi = j;
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+      const int v = lc + tid + kLuThreads * q;
+      if (v >= j && v < plim) {
+        R x = R(0);
+#pragma unroll
+        for (int k = 0; k < kWL; ++k)
+          if (k == jj) x = zcabs1(a[q][k]);
+        if (x > best || (x == best && v < bi)) {
+          best = x;
+          bi = v;
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const R ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (better(ob, oi, best, bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      sh.redv[wave] = best;
+      sh.redi[wave] = bi;
+    }
+    __syncthreads();
+    best = sh.redv[0];
+    bi = sh.redi[0];
+#pragma unroll
+    for (int q = 1; q < kLuWaves; ++q)
+      if (better(sh.redv[q], sh.redi[q], best, bi)) {
+        best = sh.redv[q];
+        bi = sh.redi[q];
+      }
+    const bool zero = !(best > R(0));
+    if (zero) bi = j;
+    // owners of rows j and bi publish them
+    const int oj = j - lc, ob = bi - lc;
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+      if (oj == tid + kLuThreads * q) {
+#pragma unroll
+        for (int k = 0; k < kWL; ++k) sh.rowJ[k] = a[q][k];
+      }
+      if (ob == tid + kLuThreads * q) {
+#pragma unroll
+        for (int k = 0; k < kWL; ++k) sh.rowP[k] = a[q][k];
+      }
+    }
+    // interchange the rows in the panel columns outside the leaf
+    if (bi != j && tid < w) {
+      const int col = c + tid;
+      if (col < lc || col >= lc + wl) {
+        C* pj = A.ptr(j, col);
+        C* pb = A.ptr(bi, col);
+        const C x = *pj, y = *pb;
+        *pj = y;
+        *pb = x;
+      }
+    }
+    if (tid == 0) {
+      sh.ipiv[j - c] = bi;
+      if (zero && best == R(0) && sh.info == 0) sh.info = j + 1;
+    }
+    __syncthreads();
+    if (bi != j) {
+#pragma unroll
+      for (int q = 0; q < kR; ++q) {
+        if (oj == tid + kLuThreads * q) {
+#pragma unroll
+          for (int k = 0; k < kWL; ++k) a[q][k] = sh.rowP[k];
+        }
+        if (ob == tid + kLuThreads * q) {
+#pragma unroll
+          for (int k = 0; k < kWL; ++k) a[q][k] = sh.rowJ[k];
+        }
+      }
+    }
+    if (!zero) {
+      C piv = zmake(R(0), R(0));
+#pragma unroll
+      for (int k = 0; k < kWL; ++k)
+        if (k == jj) piv = sh.rowP[k];
+      const C inv = zinv(piv);
+#pragma unroll
+      for (int q = 0; q < kR; ++q) {
+        const int v = lc + tid + kLuThreads * q;
+        if (v > j && v < N) {
+          C l = zmake(R(0), R(0));
+#pragma unroll
+          for (int k = 0; k < kWL; ++k)
+            if (k == jj) l = zmul(a[q][k], inv);
+#pragma unroll
+          for (int k = 0; k < kWL; ++k) {
+            if (k == jj) a[q][k] = l;
+            else if (k > jj) a[q][k] = zfms(a[q][k], l, sh.rowP[k]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kR; ++q) {
+    const int v = lc + tid + kLuThreads * q;
+    if (v < N) {
+      C* row = A.ptr(v, lc);
+#pragma unroll
+      for (int k = 0; k < kWL; ++k)
+        if (k < wl) row[k] = a[q][k];
+    }
+  }
+  __syncthreads();
+}
+
+// X = inverse of the unit lower triangular s x s block of A at (r0, r0),
+// staged first in sh.U; zero outside [0, s)^2.  Eight lanes per column: lane
+// p of a column accumulates the terms k = p (mod 8) of each row's dot product.
+template <typename R>
+__device__ __noinline__ void invert_unit_lower(const Mat<typename Prec<R>::C>& A, int r0, int s, LuSmem<R>& sh) {
+  typedef typename Prec<R>::C C;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kNB * kNB; q += kLuThreads) {
+    const int i = q / kNB, k = q % kNB;
+    sh.U[i][k] = (i < s && k < i) ? *A.ptr(r0 + i, r0 + k) : zmake(R(0), R(0));
+  }
+  __syncthreads();
+  const int j = tid >> 3, p = tid & 7;  // column j (0..63), part p
+  C xr[kNB / 8];
+#pragma unroll
+  for (int m = 0; m < kNB / 8; ++m) xr[m] = zmake(R(0), R(0));
+  if (j < s) {
+#pragma unroll
+    for (int m = 0; m < kNB / 8; ++m)
+      if (p + 8 * m == j) xr[m] = zmake(R(1), R(0));
+    for (int i = j + 1; i < s; ++i) {
+      R sr = R(0), si = R(0);
+#pragma unroll
+      for (int m = 0; m < kNB / 8; ++m) {
+        const int k = p + 8 * m;
+        if (k >= j && k < i) {
+          const C l = sh.U[i][k];
+          sr += l.x * xr[m].x - l.y * xr[m].y;
+          si += l.x * xr[m].y + l.y * xr[m].x;
+        }
+      }
+      sr += __shfl_xor(sr, 1);
+      si += __shfl_xor(si, 1);
+      sr += __shfl_xor(sr, 2);
+      si += __shfl_xor(si, 2);
+      sr += __shfl_xor(sr, 4);
+      si += __shfl_xor(si, 4);
+#pragma unroll
+      for (int m = 0; m < kNB / 8; ++m)
+        if (p + 8 * m == i) xr[m] = zmake(-sr, -si);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kNB / 8; ++m) sh.X[p + 8 * m][j] = xr[m];
+  __syncthreads();
+}
+
+// X = inverse of the upper triangular s x s block of A at (r0, r0) (non-unit
+// diagonal), staged first in sh.U; zero outside [0, s)^2.  Column j of X
+// solves U x = e_j from the bottom: x_j = 1/U_jj, x_i = -(sum_{k=i+1..j}
+// U_ik x_k) / U_ii for i < j; eight lanes per column as in invert_unit_lower.
+template <typename R>
+__device__ __noinline__ void invert_upper(const Mat<typename Prec<R>::C>& A, int r0, int s, LuSmem<R>& sh) {
+  typedef typename Prec<R>::C C;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kNB * kNB; q += kLuThreads) {
+    const int i = q / kNB, k = q % kNB;
+    sh.U[i][k] = (i < s && k < s && k >= i) ? *A.ptr(r0 + i, r0 + k) : zmake(R(0), R(0));
+  }
+  __syncthreads();
+  const int j = tid >> 3, p = tid & 7;
+  C xr[kNB / 8];
+#pragma unroll
+  for (int m = 0; m < kNB / 8; ++m) xr[m] = zmake(R(0), R(0));
+  if (j < s) {
+    const C dj = zinv(sh.U[j][j]);
+#pragma unroll
+    for (int m = 0; m < kNB / 8; ++m)
+      if (p + 8 * m == j) xr[m] = dj;
+    for (int i = j - 1; i >= 0; --i) {
+      R sr = R(0), si = R(0);
+#pragma unroll
+      for (int m = 0; m < kNB / 8; ++m) {
+        const int k = p + 8 * m;
+        if (k > i && k <= j) {
+          const C u = sh.U[i][k];
+          sr += u.x * xr[m].x - u.y * xr[m].y;
+          si += u.x * xr[m].y + u.y * xr[m].x;
+        }
+      }
+      sr += __shfl_xor(sr, 1);
+      si += __shfl_xor(si, 1);
+      sr += __shfl_xor(sr, 2);
+      si += __shfl_xor(si, 2);
+      sr += __shfl_xor(sr, 4);
+      si += __shfl_xor(si, 4);
+      const C xi = zmul(zmake(-sr, -si), zinv(sh.U[i][i]));
+#pragma unroll
+      for (int m = 0; m < kNB / 8; ++m)
+        if (p + 8 * m == i) xr[m] = xi;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kNB / 8; ++m) sh.X[p + 8 * m][j] = xr[m];
+  __syncthreads();
+}
+
+// U = X * A(r0 .. r0+s-1, s0 .. s0+sw-1) into sh.U rows 0..63 (rows >= s are
+// zero), and, if `store`, also into those rows of A.  Sixteen 16x16 output
+// tiles, two per wave.
+template <typename R>
+__device__ void trsm_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw, bool store,
+                           LuSmem<R>& sh) {
+  typedef typename Prec<R>::C C;
+  typedef typename Prec<R>::V4 V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int rt = wave & 3;            // row tile
+  const int ct0 = 2 * (wave >> 2);    // first of two column tiles
+  V4 ar[2], ai[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    ar[t] = V4{R(0), R(0), R(0), R(0)};
+    ai[t] = V4{R(0), R(0), R(0), R(0)};
+  }
+  const int row = 16 * rt + li;
+  const int kend = min(s, 16 * rt + 16);  // X is lower triangular
+  for (int kb = 0; kb < kend; kb += 4) {
+    const int k = kb + lk;
+    const C x = sh.X[row][k];
+    const R xr = (k < s) ? x.x : R(0);
+    const R xi = (k < s) ? x.y : R(0);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int col = 16 * (ct0 + t) + li;
+      C b = zmake(R(0), R(0));
+      if (k < s && col < sw) b = *A.ptr(r0 + k, s0 + col);
+      ar[t] = Prec<R>::mfma(xr, b.x, ar[t]);
+      ar[t] = Prec<R>::mfma(-xi, b.y, ar[t]);
+      ai[t] = Prec<R>::mfma(xr, b.y, ai[t]);
+      ai[t] = Prec<R>::mfma(xi, b.x, ai[t]);
+    }
+  }
+  __syncthreads();  // earlier readers of sh.U are done
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * rt + Prec<R>::drow(r, lk), col = 16 * (ct0 + t) + li;
+      const C u = zmake(ar[t][r], ai[t][r]);
+      sh.U[i][col] = u;
+      if (store && i < s && col < sw) *A.ptr(r0 + i, s0 + col) = u;
+    }
+  __syncthreads();
+}
+
+// A(v, s0 + j) -= sum_{k < s} A(v, r0 + k) U[k][j] for v in [r0 + s, N),
+// j < sw.  Each wave owns blocks of 16 rows x 64 columns (four MFMA tiles);
+// MFMA step kb uses k = kb + lane/16.
+template <typename R>
+__device__ void update_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
+                             const LuSmem<R>& sh) {
+  typedef typename Prec<R>::C C;
+  typedef typename Prec<R>::V4 V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int N = (int)A.N;
+  const int rstart = r0 + s;
+  const int ncs = (sw + 15) >> 4;
+  for (int rb = rstart + 16 * wave; rb < N; rb += 16 * kLuWaves) {
+    V4 accr[4], acci[4];
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs) {
+      accr[cs] = V4{R(0), R(0), R(0), R(0)};
+      acci[cs] = V4{R(0), R(0), R(0), R(0)};
+    }
+    const int va = rb + li;
+    const bool rok = va < N;
+    const C* arow = A.base + A.phys(rok ? va : rstart) * A.N + A.phys(r0);
+#pragma unroll 4
+    for (int kb = 0; kb < s; kb += 4) {
+      const int k = kb + lq;
+      const C a = (rok && k < s) ? arow[k] : zmake(R(0), R(0));
+      C b[4];
+#pragma unroll
+      for (int cs = 0; cs < 4; ++cs) b[cs] = sh.U[k & (kNB - 1)][16 * cs + li];
+#pragma unroll
+      for (int cs = 0; cs < 4; ++cs) {
+        if (cs < ncs) {
+          accr[cs] = Prec<R>::mfma(a.x, b[cs].x, accr[cs]);
+          accr[cs] = Prec<R>::mfma(-a.y, b[cs].y, accr[cs]);
+          acci[cs] = Prec<R>::mfma(a.x, b[cs].y, acci[cs]);
+          acci[cs] = Prec<R>::mfma(a.y, b[cs].x, acci[cs]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = rb + Prec<R>::drow(r, lq);
+      if (v >= N) continue;
+      C* crow = A.base + A.phys(v) * A.N;
+#pragma unroll
+      for (int cs = 0; cs < 4; ++cs) {
+        const int col = 16 * cs + li;
+        if (col < sw) {
+          C* p = crow + A.phys(s0 + col);
+          const C cv = *p;
+          *p = zmake(cv.x - accr[cs][r], cv.y - acci[cs][r]);
+        }
+      }
+    }
+  }
+}
+
+// Row interchanges of the panel [c, c + w) applied to the columns [c0, c1).
+// Each thread owns whole columns, so the interchanges are applied in order
+// per thread.
+template <typename R>
+__device__ __noinline__ void apply_swaps(const Mat<typename Prec<R>::C>& A, int c, int w, int c0, int c1,
+                                         const LuSmem<R>& sh) {
+  typedef typename Prec<R>::C C;
+  for (int jj = 0; jj < w; ++jj) {
+    const int p = sh.ipiv[jj], r = c + jj;
+    if (p == r) continue;
+    C* rr = A.base + A.phys(r) * A.N;
+    C* rp = A.base + A.phys(p) * A.N;
+    for (int u = c0 + threadIdx.x; u < c1; u += kLuThreads) {
+      const int64_t pu = A.phys(u);
+      const C x = rr[pu], y = rp[pu];
+      rr[pu] = y;
+      rp[pu] = x;
+    }
+  }
+}
+
+// Recursive panel factorisation of columns [c, c + w): leaves of kWL columns
+// in registers; after each leaf the completed block of the recursion updates
+// its sibling block (triangular solve and product on MFMA).  With store_u the
+// upper-triangular part of the panel is kept in A.
+template <typename R, int kR, int kWL>
+__device__ void panel_factor(const Mat<typename Prec<R>::C>& A, int c, int w, int plim, bool store_u,
+                             LuSmem<R>& sh) {
+  const int nleaf = (w + kWL - 1) / kWL;
+  for (int i = 0; i < nleaf; ++i) {
+    const int lc = c + kWL * i;
+    leaf_factor<R, kR, kWL>(A, c, w, lc, plim, sh);
+    const int s = kWL << __builtin_ctz(i + 1);
+    const int start = lc + kWL - s;
+    const int t0 = lc + kWL;
+    const int tw = min(s, c + w - t0);
+    if (tw > 0) {
+      invert_unit_lower<R>(A, start, s, sh);
+      trsm_strip<R>(A, start, s, t0, tw, store_u, sh);
+      update_strip<R>(A, start, s, t0, tw, sh);
+      __syncthreads();
+    }
+  }
+}
+
+// Blocked right-looking elimination of the columns [c_begin, ncols) of the
+// N x N matrix: panels of nb columns with pivot rows below plim, interchanges
+// applied to every column right of the panel (the columns left of a panel
+// keep the row order of their own elimination step), the U part written back
+// when store_u, and the panel pivots stored at ipiv_out[column] (if non-null).
+// Ends after a barrier.
+template <typename R, int kR, int kWL>
+__device__ void eliminate(const Mat<typename Prec<R>::C>& A, int c_begin, int ncols, int plim, int nb,
+                          bool store_u, int32_t* ipiv_out, LuSmem<R>& sh) {
+  const int N = (int)A.N;
+  for (int c = c_begin; c < ncols; c += nb) {
+    const int w = min(nb, ncols - c);
+    panel_factor<R, kR, kWL>(A, c, w, plim, store_u, sh);
+    apply_swaps<R>(A, c, w, c + w, N, sh);
+    if (ipiv_out && threadIdx.x < w) ipiv_out[c + threadIdx.x] = sh.ipiv[threadIdx.x];
+    __syncthreads();
+    if (c + w < N) {
+      invert_unit_lower<R>(A, c, w, sh);
+      for (int s0 = c + w; s0 < N; s0 += kSW) {
+        const int sw = min(kSW, N - s0);
+        trsm_strip<R>(A, c, w, s0, sw, store_u, sh);
+        update_strip<R>(A, c, w, s0, sw, sh);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace lsms

@@ -34,385 +34,26 @@
 // Finally S_A is inverted by Gauss-Jordan with partial pivoting.
 #include "kkr_device.h"
 #include "lsms_common.h"
+#include "lu_device.h"
 
 using namespace lsms;
 
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-constexpr int kThreads = 512;
-constexpr int kWaves = kThreads / 64;
-constexpr int kNB = 64;   // maximum panel width
-constexpr int kSW = 64;   // trailing-update strip width (columns)
-constexpr int kMaxKK = 25;
-constexpr int kMaxWL = 8;
-
-struct LuSmem {
-  zd X[kNB][kNB];    // inverse of a unit lower triangular block
-  zd U[kNB][kSW];    // U12 strip; L staging; Gauss-Jordan workspace at the end
-  zd rowP[kMaxWL];   // pivot row of a leaf step
-  zd rowJ[kMaxWL];
-  zd tz[kMaxKK];
-  zd pinv;
-  double redv[kWaves];
-  int redi[kWaves];
-  int ipiv[kNB];
-  int info;
-  int bad;
-  int gj_piv;
-};
-
-struct Mat {
-  zd* base;
-  int64_t N;
-  int Nd, kk;
-  __device__ __forceinline__ int64_t phys(int v) const { return v < Nd ? (int64_t)v + kk : (int64_t)(v - Nd); }
-  __device__ __forceinline__ zd* ptr(int r, int c) const { return base + phys(r) * N + phys(c); }
-};
-
-// v_mfma_f64_16x16x4f64, D = A B + C with A 16x4, B 4x16: lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; register r of lane l holds
-// D[4 r + l / 16][l % 16].
-__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ bool better(double ob, int oi, double b, int i) {
-  return ob > b || (ob == b && oi < i);
-}
-
-// ------------------------------------------------------------ leaf
-// Factorises the leaf columns [lc, lc + kWL) of the panel [c, c + w), rows
-// [lc, N), with the leaf in registers.  Interchanges are applied at once to
-// the other panel columns in memory.
-// Kept out of line (with invert_unit_lower and apply_swaps) so that the
-// register allocator treats the panel phase and the trailing update apart.
-template <int kR, int kWL>
-__device__ __noinline__ void leaf_factor(const Mat& A, int c, int w, int lc, LuSmem& sh) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int N = (int)A.N, Nd = A.Nd;
-  const int wl = min(kWL, c + w - lc);
-  zd a[kR][kWL];
-#pragma unroll
-  for (int q = 0; q < kR; ++q) {
-    const int v = lc + tid + kThreads * q;
-    if (v < N) {
-      const zd* row = A.ptr(v, lc);
-#pragma unroll
-      for (int k = 0; k < kWL; ++k) a[q][k] = (k < wl) ? row[k] : zmake(0.0, 0.0);
-    } else {
-#pragma unroll
-      for (int k = 0; k < kWL; ++k) a[q][k] = zmake(0.0, 0.0);
-    }
-  }
-  for (int jj = 0; jj < wl; ++jj) {
-    const int j = lc + jj;
-    double best = -1.0;
-    int bi = j;
-#pragma unroll
-    for (int q = 0; q < kR; ++q) {
-      const int v = lc + tid + kThreads * q;
-      if (v >= j && v < Nd) {
-        double x = 0.0;
-#pragma unroll
-        for (int k = 0; k < kWL; ++k)
-          if (k == jj) x = zcabs1(a[q][k]);
-        if (x > best || (x == best && v < bi)) {
-          best = x;
-          bi = v;
-        }
-      }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (better(ob, oi, best, bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      sh.redv[wave] = best;
-      sh.redi[wave] = bi;
-    }
-    __syncthreads();
-    best = sh.redv[0];
-    bi = sh.redi[0];
-#pragma unroll
-    for (int q = 1; q < kWaves; ++q)
-      if (better(sh.redv[q], sh.redi[q], best, bi)) {
-        best = sh.redv[q];
-        bi = sh.redi[q];
-      }
-    const bool zero = !(best > 0.0);
-    if (zero) bi = j;
-    // owners of rows j and bi publish them
-    const int oj = j - lc, ob = bi - lc;
-#pragma unroll
-    for (int q = 0; q < kR; ++q) {
-      if (oj == tid + kThreads * q) {
-#pragma unroll
-        for (int k = 0; k < kWL; ++k) sh.rowJ[k] = a[q][k];
-      }
-      if (ob == tid + kThreads * q) {
-#pragma unroll
-        for (int k = 0; k < kWL; ++k) sh.rowP[k] = a[q][k];
-      }
-    }
-    // interchange the rows in the panel columns outside the leaf
-    if (bi != j && tid < w) {
-      const int col = c + tid;
-      if (col < lc || col >= lc + wl) {
-        zd* pj = A.ptr(j, col);
-        zd* pb = A.ptr(bi, col);
-        const zd x = *pj, y = *pb;
-        *pj = y;
-        *pb = x;
-      }
-    }
-    if (tid == 0) {
-      sh.ipiv[j - c] = bi;
-      if (zero && best == 0.0 && sh.info == 0) sh.info = j + 1;
-    }
-    __syncthreads();
-    if (bi != j) {
-#pragma unroll
-      for (int q = 0; q < kR; ++q) {
-        if (oj == tid + kThreads * q) {
-#pragma unroll
-          for (int k = 0; k < kWL; ++k) a[q][k] = sh.rowP[k];
-        }
-        if (ob == tid + kThreads * q) {
-#pragma unroll
-          for (int k = 0; k < kWL; ++k) a[q][k] = sh.rowJ[k];
-        }
-      }
-    }
-    if (!zero) {
-      zd piv = zmake(0.0, 0.0);
-#pragma unroll
-      for (int k = 0; k < kWL; ++k)
-        if (k == jj) piv = sh.rowP[k];
-      const zd inv = zinv(piv);
-#pragma unroll
-      for (int q = 0; q < kR; ++q) {
-        const int v = lc + tid + kThreads * q;
-        if (v > j && v < N) {
-          zd l = zmake(0.0, 0.0);
-#pragma unroll
-          for (int k = 0; k < kWL; ++k)
-            if (k == jj) l = zmul(a[q][k], inv);
-#pragma unroll
-          for (int k = 0; k < kWL; ++k) {
-            if (k == jj) a[q][k] = l;
-            else if (k > jj) a[q][k] = zfms(a[q][k], l, sh.rowP[k]);
-          }
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < kR; ++q) {
-    const int v = lc + tid + kThreads * q;
-    if (v < N) {
-      zd* row = A.ptr(v, lc);
-#pragma unroll
-      for (int k = 0; k < kWL; ++k)
-        if (k < wl) row[k] = a[q][k];
-    }
-  }
-  __syncthreads();
-}
-
-// X = inverse of the unit lower triangular s x s block of A at (r0, r0),
-// staged first in sh.U; zero outside [0, s)^2.  Eight lanes per column: lane
-// p of a column accumulates the terms k = p (mod 8) of each row's dot product.
-__device__ __noinline__ void invert_unit_lower(const Mat& A, int r0, int s, LuSmem& sh) {
-  const int tid = threadIdx.x;
-  for (int q = tid; q < kNB * kNB; q += kThreads) {
-    const int i = q / kNB, k = q % kNB;
-    sh.U[i][k] = (i < s && k < i) ? *A.ptr(r0 + i, r0 + k) : zmake(0.0, 0.0);
-  }
-  __syncthreads();
-  const int j = tid >> 3, p = tid & 7;  // column j (0..63), part p
-  zd xr[kNB / 8];
-#pragma unroll
-  for (int m = 0; m < kNB / 8; ++m) xr[m] = zmake(0.0, 0.0);
-  if (j < s) {
-#pragma unroll
-    for (int m = 0; m < kNB / 8; ++m)
-      if (p + 8 * m == j) xr[m] = zmake(1.0, 0.0);
-    for (int i = j + 1; i < s; ++i) {
-      double sr = 0.0, si = 0.0;
-#pragma unroll
-      for (int m = 0; m < kNB / 8; ++m) {
-        const int k = p + 8 * m;
-        if (k >= j && k < i) {
-          const zd l = sh.U[i][k];
-          sr += l.x * xr[m].x - l.y * xr[m].y;
-          si += l.x * xr[m].y + l.y * xr[m].x;
-        }
-      }
-      sr += __shfl_xor(sr, 1);
-      si += __shfl_xor(si, 1);
-      sr += __shfl_xor(sr, 2);
-      si += __shfl_xor(si, 2);
-      sr += __shfl_xor(sr, 4);
-      si += __shfl_xor(si, 4);
-#pragma unroll
-      for (int m = 0; m < kNB / 8; ++m)
-        if (p + 8 * m == i) xr[m] = zmake(-sr, -si);
-    }
-  }
-#pragma unroll
-  for (int m = 0; m < kNB / 8; ++m) sh.X[p + 8 * m][j] = xr[m];
-  __syncthreads();
-}
-
-// U = X * A(r0 .. r0+s-1, s0 .. s0+sw-1) into sh.U rows 0..63 (rows >= s are
-// zero).  Sixteen 16x16 output tiles, two per wave.
-__device__ void trsm_strip(const Mat& A, int r0, int s, int s0, int sw, LuSmem& sh) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int rt = wave & 3;            // row tile
-  const int ct0 = 2 * (wave >> 2);    // first of two column tiles
-  d4 ar[2], ai[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    ar[t] = d4{0.0, 0.0, 0.0, 0.0};
-    ai[t] = d4{0.0, 0.0, 0.0, 0.0};
-  }
-  const int row = 16 * rt + li;
-  const int kend = min(s, 16 * rt + 16);  // X is lower triangular
-  for (int kb = 0; kb < kend; kb += 4) {
-    const int k = kb + lk;
-    const zd x = sh.X[row][k];
-    const double xr = (k < s) ? x.x : 0.0;
-    const double xi = (k < s) ? x.y : 0.0;
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int col = 16 * (ct0 + t) + li;
-      zd b = zmake(0.0, 0.0);
-      if (k < s && col < sw) b = *A.ptr(r0 + k, s0 + col);
-      ar[t] = mfma(xr, b.x, ar[t]);
-      ar[t] = mfma(-xi, b.y, ar[t]);
-      ai[t] = mfma(xr, b.y, ai[t]);
-      ai[t] = mfma(xi, b.x, ai[t]);
-    }
-  }
-  __syncthreads();  // earlier readers of sh.U are done
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) sh.U[16 * rt + 4 * r + lk][16 * (ct0 + t) + li] = zmake(ar[t][r], ai[t][r]);
-  __syncthreads();
-}
-
-// A(v, s0 + j) -= sum_{k < s} A(v, r0 + k) U[k][j] for v in [r0 + s, N),
-// j < sw.  Each wave owns blocks of 16 rows x 64 columns (four MFMA tiles);
-// MFMA step kb uses k = kb + lane/16.
-__device__ void update_strip(const Mat& A, int r0, int s, int s0, int sw, const LuSmem& sh) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lq = lane >> 4;
-  const int N = (int)A.N;
-  const int rstart = r0 + s;
-  const int ncs = (sw + 15) >> 4;
-  for (int rb = rstart + 16 * wave; rb < N; rb += 16 * kWaves) {
-    d4 accr[4], acci[4];
-#pragma unroll
-    for (int cs = 0; cs < 4; ++cs) {
-      accr[cs] = d4{0.0, 0.0, 0.0, 0.0};
-      acci[cs] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-    const int va = rb + li;
-    const bool rok = va < N;
-    const zd* arow = A.base + A.phys(rok ? va : rstart) * A.N + A.phys(r0);
-#pragma unroll 4
-    for (int kb = 0; kb < s; kb += 4) {
-      const int k = kb + lq;
-      const zd a = (rok && k < s) ? arow[k] : zmake(0.0, 0.0);
-      zd b[4];
-#pragma unroll
-      for (int cs = 0; cs < 4; ++cs) b[cs] = sh.U[k & (kNB - 1)][16 * cs + li];
-#pragma unroll
-      for (int cs = 0; cs < 4; ++cs) {
-        if (cs < ncs) {
-          accr[cs] = mfma(a.x, b[cs].x, accr[cs]);
-          accr[cs] = mfma(-a.y, b[cs].y, accr[cs]);
-          acci[cs] = mfma(a.x, b[cs].y, acci[cs]);
-          acci[cs] = mfma(a.y, b[cs].x, acci[cs]);
-        }
-      }
-    }
-    // C -= acc ; register r of lane (li, lq) holds row 4*r + lq, column li of each tile
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int v = rb + 4 * r + lq;
-      if (v >= N) continue;
-      zd* crow = A.base + A.phys(v) * A.N;
-#pragma unroll
-      for (int cs = 0; cs < 4; ++cs) {
-        const int col = 16 * cs + li;
-        if (col < sw) {
-          zd* p = crow + A.phys(s0 + col);
-          const zd cv = *p;
-          *p = zmake(cv.x - accr[cs][r], cv.y - acci[cs][r]);
-        }
-      }
-    }
-  }
-}
-
-// Row interchanges of the panel applied to the columns [c0, N).  Each thread
-// owns whole columns, so the interchanges are applied in order per thread.
-__device__ __noinline__ void apply_swaps(const Mat& A, int c, int w, int c0, const LuSmem& sh) {
-  const int N = (int)A.N;
-  for (int jj = 0; jj < w; ++jj) {
-    const int p = sh.ipiv[jj], r = c + jj;
-    if (p == r) continue;
-    zd* rr = A.base + A.phys(r) * A.N;
-    zd* rp = A.base + A.phys(p) * A.N;
-    for (int u = c0 + threadIdx.x; u < N; u += kThreads) {
-      const int64_t pu = A.phys(u);
-      const zd x = rr[pu], y = rp[pu];
-      rr[pu] = y;
-      rp[pu] = x;
-    }
-  }
-}
-
-template <int kR, int kWL>
-__device__ void panel_factor(const Mat& A, int c, int w, LuSmem& sh) {
-  const int nleaf = (w + kWL - 1) / kWL;
-  for (int i = 0; i < nleaf; ++i) {
-    const int lc = c + kWL * i;
-    leaf_factor<kR, kWL>(A, c, w, lc, sh);
-    // the completed block of the recursion updates its sibling block
-    const int s = kWL << __builtin_ctz(i + 1);
-    const int start = lc + kWL - s;
-    const int t0 = lc + kWL;
-    const int tw = min(s, c + w - t0);
-    if (tw > 0) {
-      invert_unit_lower(A, start, s, sh);
-      trsm_strip(A, start, s, t0, tw, sh);
-      update_strip(A, start, s, t0, tw, sh);
-      __syncthreads();
-    }
-  }
-}
+constexpr int kThreads = kLuThreads;
+typedef LuSmem<double> LuSmemD;
 
 // Eliminates one instance whose matrix is at `base` and writes its tau00 and
 // info.  All threads of the workgroup call it; it ends after a barrier.
 template <int kR, int kWL>
 __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, double* __restrict__ tau00,
-                            int32_t* __restrict__ info, int nb, LuSmem& sh) {
+                            int32_t* __restrict__ info, int nb, LuSmemD& sh) {
   const int tid = threadIdx.x;
   const int kk = p.kk;
   const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
   const int N = kk * nliz, Nd = N - kk;
   zd* tout = reinterpret_cast<zd*>(tau00) + (int64_t)inst * kk * kk;
-  Mat A;
+  Mat<zd> A;
   A.base = base;
   A.N = N;
   A.Nd = Nd;
@@ -422,20 +63,7 @@ __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, double* 
     sh.bad = 0;
   }
   __syncthreads();
-
-  for (int c = 0; c < Nd; c += nb) {
-    const int w = min(nb, Nd - c);
-    panel_factor<kR, kWL>(A, c, w, sh);
-    apply_swaps(A, c, w, c + w, sh);
-    __syncthreads();
-    invert_unit_lower(A, c, w, sh);
-    for (int s0 = c + w; s0 < N; s0 += kSW) {
-      const int sw = min(kSW, N - s0);
-      trsm_strip(A, c, w, s0, sw, sh);
-      update_strip(A, c, w, s0, sw, sh);
-    }
-    __syncthreads();
-  }
+  eliminate<double, kR, kWL>(A, 0, Nd, Nd, nb, false, nullptr, sh);
 
   // Gauss-Jordan inverse of S_A (kk x kk, physical rows/cols 0..kk-1) in sh.U
   zd(*G)[2 * kMaxKK] = reinterpret_cast<zd(*)[2 * kMaxKK]>(&sh.U[0][0]);
@@ -486,7 +114,7 @@ __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, double* 
   for (int q = tid; q < kk * kk; q += kThreads) {
     const int L = q % kk, Lp = q / kk;
     zd v = zmul(G[Lp][kk + L], tmat_from_delta(dl[l_of(Lp)], kap));
-    if (info0 != 0) v = zmake(NAN, NAN);
+    if (info0 != 0) v = zmake((double)NAN, (double)NAN);
     if (!zfinite(v)) sh.bad = 1;
     tout[q] = v;
   }
@@ -506,7 +134,7 @@ __device__ __forceinline__ bool instance_invalid(const lsms_prob_dev& p, int ins
 
 __device__ __forceinline__ void fill_nan(const lsms_prob_dev& p, int inst, double* tau00) {
   zd* tout = reinterpret_cast<zd*>(tau00) + (int64_t)inst * p.kk * p.kk;
-  for (int q = threadIdx.x; q < p.kk * p.kk; q += kThreads) tout[q] = zmake(NAN, NAN);
+  for (int q = threadIdx.x; q < p.kk * p.kk; q += kThreads) tout[q] = zmake((double)NAN, (double)NAN);
 }
 
 template <int kR, int kWL>
@@ -516,7 +144,7 @@ __global__ __launch_bounds__(kThreads) void lu_schur_fp64_kernel(lsms_prob_dev p
                                                                 int32_t* __restrict__ info, int keep_info,
                                                                 int nb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  LuSmem& sh = *reinterpret_cast<LuSmem*>(smem_raw);
+  LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
   const int inst = i0 + blockIdx.x;
   const bool invalid = instance_invalid<kR>(p, inst);
   if ((keep_info && info[inst] != 0) || invalid) {
@@ -558,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void tau00_persistent_kernel(lsms_prob_de
                                                                    double* __restrict__ tau00,
                                                                    int32_t* __restrict__ info, int nb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  LuSmem& sh = *reinterpret_cast<LuSmem*>(smem_raw);
+  LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
   BuildSmem& sb = *reinterpret_cast<BuildSmem*>(smem_raw);  // used before sh, never at the same time
   __shared__ int next;
   zd* M = reinterpret_cast<zd*>(work) + (int64_t)blockIdx.x * slot;
@@ -585,10 +213,468 @@ __global__ __launch_bounds__(kThreads) void tau00_persistent_kernel(lsms_prob_de
   }
 }
 
+// ======================================================================
+// Precision form: FP32 factorisation, FP64 iterative refinement.
+//
+// Y = A_int^{-1} E_c (E_c: the unit vectors of the central rows) holds
+// [M^{-1}]_{00}^T in its central rows.  A copy of A in complex FP32 is
+// factorised completely (non-central columns with pivots among the
+// non-central rows, then the central block with pivots among the central
+// rows), keeping L, U and the pivots.  Then Y_0 = A32^{-1} E_c and, until the
+// correction of the central rows is below tol relative to them,
+//   R = E_c - A Y   (FP64, the FP64 matrix is never modified)
+//   D = A32^{-1} R  (FP32 forward/backward solves on MFMA)
+//   Y = Y + D       (FP64)
+// (mixed-precision iterative refinement with the residual in the working
+// precision).  An instance that does not converge in max_refine steps, or
+// whose FP32 factorisation meets an exactly zero pivot, is recomputed by the
+// FP64 Schur path on its unmodified FP64 matrix and flagged in info (bit 8).
+// ======================================================================
+
+constexpr int kInfoIrFallback = 256;
+
+struct MixedBufs {
+  zf* A32;        // N x N FP32 factors, same physical layout as M
+  zf* z;          // N x kp FP32 right-hand sides / corrections, internal rows
+  zd* Y;          // N x kp FP64 solution, internal rows
+  int32_t* ipiv;  // N pivot rows
+  int kp;         // 16 or 32: kk rounded up to a multiple of 16
+};
+
+struct MixedSmem {
+  LuSmem<float> f;
+  zf part[2][kNB][32];  // split-K partial sums of the backward solve
+  double red[2][kLuWaves];
+  int flag;
+};
+
+// z[v][j] (v in [r0, r0 + s), j < kp) = X * z[r0 .. r0 + s) with X = sh.X (s x s):
+// up to eight 16x16 tiles, one per wave; the result also goes to sh.U.
+__device__ void tri_apply(const MixedBufs& b, int r0, int s, LuSmem<float>& sh) {
+  typedef Prec<float>::V4 V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int nct = b.kp / 16;
+  const int rt = wave & 3, ct = wave >> 2;
+  V4 ar = V4{0.f, 0.f, 0.f, 0.f}, ai = V4{0.f, 0.f, 0.f, 0.f};
+  const bool act = ct < nct;
+  if (act) {
+    for (int kb = 0; kb < s; kb += 4) {
+      const int k = kb + lq;
+      const zf x = sh.X[16 * rt + li][k];
+      const zf y = (k < s) ? b.z[(int64_t)(r0 + k) * b.kp + 16 * ct + li] : zmake(0.f, 0.f);
+      const float xr = (k < s) ? x.x : 0.f, xi = (k < s) ? x.y : 0.f;
+      ar = Prec<float>::mfma(xr, y.x, ar);
+      ar = Prec<float>::mfma(-xi, y.y, ar);
+      ai = Prec<float>::mfma(xr, y.y, ai);
+      ai = Prec<float>::mfma(xi, y.x, ai);
+    }
+  }
+  __syncthreads();  // every wave has read z[r0 ..] and sh.X
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * rt + Prec<float>::drow(r, lq);
+      const zf v = zmake(ar[r], ai[r]);
+      sh.U[i][16 * ct + li] = v;
+      if (i < s) b.z[(int64_t)(r0 + i) * b.kp + 16 * ct + li] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// z[v] -= sum_{k < s} A(v, r0 + k) sh.U[k] for v in [v0, N): 16-row blocks per wave.
+__device__ void rhs_update(const Mat<zf>& A, const MixedBufs& b, int r0, int s, int v0, const LuSmem<float>& sh) {
+  typedef Prec<float>::V4 V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int N = (int)A.N, nct = b.kp / 16;
+  for (int rb = v0 + 16 * wave; rb < N; rb += 16 * kLuWaves) {
+    V4 ar[2], ai[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      ar[t] = V4{0.f, 0.f, 0.f, 0.f};
+      ai[t] = V4{0.f, 0.f, 0.f, 0.f};
+    }
+    const int va = rb + li;
+    const bool rok = va < N;
+    const zf* arow = A.base + A.phys(rok ? va : v0) * A.N + A.phys(r0);
+    for (int kb = 0; kb < s; kb += 4) {
+      const int k = kb + lq;
+      const zf a = (rok && k < s) ? arow[k] : zmake(0.f, 0.f);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        if (t < nct) {
+          const zf u = sh.U[k & (kNB - 1)][16 * t + li];
+          ar[t] = Prec<float>::mfma(a.x, u.x, ar[t]);
+          ar[t] = Prec<float>::mfma(-a.y, u.y, ar[t]);
+          ai[t] = Prec<float>::mfma(a.x, u.y, ai[t]);
+          ai[t] = Prec<float>::mfma(a.y, u.x, ai[t]);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (t >= nct) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int v = rb + Prec<float>::drow(r, lq);
+        if (v < N) {
+          zf* pz = b.z + (int64_t)v * b.kp + 16 * t + li;
+          const zf c = *pz;
+          *pz = zmake(c.x - ar[t][r], c.y - ai[t][r]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// z := A32^{-1} z with the panel structure of the factorisation: forward with
+// the unit lower factor (each panel's interchanges applied just before its
+// columns are used, since earlier columns of L keep their own row order),
+// then backward with the upper factor.
+__device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, MixedSmem& ms) {
+  typedef Prec<float>::V4 V4;
+  LuSmem<float>& sh = ms.f;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int N = (int)A.N, Nd = A.Nd, nct = b.kp / 16;
+  // panels: [0, Nd) in steps of nb, then [Nd, N)
+  const int npan = (Nd + nb - 1) / nb + 1;
+  for (int pi = 0; pi < npan; ++pi) {
+    const int c = pi + 1 < npan ? pi * nb : Nd;
+    const int w = pi + 1 < npan ? min(nb, Nd - c) : N - Nd;
+    if (w <= 0) continue;
+    if (tid < b.kp) {
+      for (int jj = 0; jj < w; ++jj) {
+        const int pr = b.ipiv[c + jj];
+        if (pr != c + jj) {
+          zf* a0 = b.z + (int64_t)(c + jj) * b.kp + tid;
+          zf* a1 = b.z + (int64_t)pr * b.kp + tid;
+          const zf x = *a0, y = *a1;
+          *a0 = y;
+          *a1 = x;
+        }
+      }
+    }
+    __syncthreads();
+    invert_unit_lower<float>(A, c, w, sh);
+    tri_apply(b, c, w, sh);
+    if (c + w < N) rhs_update(A, b, c, w, c + w, sh);
+  }
+  for (int pi = npan - 1; pi >= 0; --pi) {
+    const int c = pi + 1 < npan ? pi * nb : Nd;
+    const int w = pi + 1 < npan ? min(nb, Nd - c) : N - Nd;
+    if (w <= 0) continue;
+    // part = U(c .. c+w, c+w .. N) z(c+w .. N), split over k between wave halves
+    const int ntile = 4 * nct, nsplit = kLuWaves / ntile;
+    const int tile = wave % ntile, split = wave / ntile;
+    const int rt = tile & 3, ct = tile >> 2;
+    const int k0 = c + w, klen = N - k0;
+    const int kchunk = ((klen + nsplit - 1) / nsplit + 3) & ~3;
+    const int ka = k0 + split * kchunk, kz = min(N, ka + kchunk);
+    V4 ar = V4{0.f, 0.f, 0.f, 0.f}, ai = V4{0.f, 0.f, 0.f, 0.f};
+    const int row = c + 16 * rt + li;
+    const bool rok = 16 * rt + li < w;
+    const zf* urow = A.base + A.phys(rok ? row : c) * A.N;
+    for (int kb = ka; kb < kz; kb += 4) {
+      const int k = kb + lq;
+      const bool kok = k < kz;
+      const zf a = (rok && kok) ? urow[A.phys(k)] : zmake(0.f, 0.f);
+      const zf y = kok ? b.z[(int64_t)k * b.kp + 16 * ct + li] : zmake(0.f, 0.f);
+      ar = Prec<float>::mfma(a.x, y.x, ar);
+      ar = Prec<float>::mfma(-a.y, y.y, ar);
+      ai = Prec<float>::mfma(a.x, y.y, ai);
+      ai = Prec<float>::mfma(a.y, y.x, ai);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      ms.part[split][16 * rt + Prec<float>::drow(r, lq)][16 * ct + li] = zmake(ar[r], ai[r]);
+    invert_upper<float>(A, c, w, sh);  // starts and ends with a barrier
+    for (int q = tid; q < kNB * 32; q += kLuThreads) {
+      const int i = q / 32, j = q % 32;
+      zf v = zmake(0.f, 0.f);
+      if (i < w && j < b.kp) {
+        const zf zc = b.z[(int64_t)(c + i) * b.kp + j];
+        zf acc = ms.part[0][i][j];
+        if (nsplit > 1) acc = zmake(acc.x + ms.part[1][i][j].x, acc.y + ms.part[1][i][j].y);
+        v = zmake(zc.x - acc.x, zc.y - acc.y);
+      }
+      if (j < kSW) sh.U[i][j] = v;
+    }
+    __syncthreads();
+    // z(c .. c+w) = X_u * sh.U
+    V4 br = V4{0.f, 0.f, 0.f, 0.f}, bi = V4{0.f, 0.f, 0.f, 0.f};
+    const int rt2 = wave & 3, ct2 = wave >> 2;
+    const bool act = ct2 < nct;
+    if (act) {
+      for (int kb = 0; kb < w; kb += 4) {
+        const int k = kb + lq;
+        const zf x = sh.X[16 * rt2 + li][k];
+        const zf y = sh.U[k][16 * ct2 + li];
+        const float xr = (k < w) ? x.x : 0.f, xi = (k < w) ? x.y : 0.f;
+        br = Prec<float>::mfma(xr, y.x, br);
+        br = Prec<float>::mfma(-xi, y.y, br);
+        bi = Prec<float>::mfma(xr, y.y, bi);
+        bi = Prec<float>::mfma(xi, y.x, bi);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * rt2 + Prec<float>::drow(r, lq);
+        if (i < w) b.z[(int64_t)(c + i) * b.kp + 16 * ct2 + li] = zmake(br[r], bi[r]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// z = E_c - A64 Y in FP32 (rows of the FP64 matrix times the FP64 solution).
+__device__ void residual(const Mat<zd>& A, const MixedBufs& b) {
+  typedef Prec<double>::V4 V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int N = (int)A.N, Nd = A.Nd, nct = b.kp / 16, kk = A.kk;
+  for (int rb = 16 * wave; rb < N; rb += 16 * kLuWaves) {
+    V4 ar[2], ai[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      ar[t] = V4{0.0, 0.0, 0.0, 0.0};
+      ai[t] = V4{0.0, 0.0, 0.0, 0.0};
+    }
+    const int va = rb + li;
+    const bool rok = va < N;
+    const zd* arow = A.base + A.phys(rok ? va : 0) * A.N;
+    for (int kb = 0; kb < N; kb += 4) {
+      const int k = kb + lq;
+      const bool kok = k < N;
+      const zd a = (rok && kok) ? arow[A.phys(k)] : zmake(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        if (t < nct) {
+          const zd y = kok ? b.Y[(int64_t)k * b.kp + 16 * t + li] : zmake(0.0, 0.0);
+          ar[t] = Prec<double>::mfma(a.x, y.x, ar[t]);
+          ar[t] = Prec<double>::mfma(-a.y, y.y, ar[t]);
+          ai[t] = Prec<double>::mfma(a.x, y.y, ai[t]);
+          ai[t] = Prec<double>::mfma(a.y, y.x, ai[t]);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (t >= nct) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int v = rb + Prec<double>::drow(r, lq);
+        const int j = 16 * t + li;
+        if (v < N) {
+          const double e = (j < kk && v == Nd + j) ? 1.0 : 0.0;
+          b.z[(int64_t)v * b.kp + j] = zmake((float)(e - ar[t][r]), (float)(-ai[t][r]));
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Precision-form tau00 of one instance.  A64 is the FP64 matrix (left
+// unmodified unless the FP64 fallback runs).  Ends after a barrier.
+template <int kR, int kWL>
+__device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd* A64, const MixedBufs& b, double* tau00,
+                               int32_t* info, int nb, double tol, int max_refine, unsigned char* smem) {
+  MixedSmem& ms = *reinterpret_cast<MixedSmem*>(smem);
+  LuSmem<float>& sh = ms.f;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kk = p.kk;
+  const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
+  const int N = kk * nliz, Nd = N - kk;
+  Mat<zd> A;
+  A.base = A64;
+  A.N = N;
+  A.Nd = Nd;
+  A.kk = kk;
+  Mat<zf> F;
+  F.base = b.A32;
+  F.N = N;
+  F.Nd = Nd;
+  F.kk = kk;
+  for (int64_t q = tid; q < (int64_t)N * N; q += kLuThreads) {
+    const zd x = A64[q];
+    b.A32[q] = zmake((float)x.x, (float)x.y);
+  }
+  if (tid == 0) sh.info = 0;
+  __syncthreads();
+  eliminate<float, kR, kWL>(F, 0, Nd, Nd, nb, true, b.ipiv, sh);
+  eliminate<float, kR, kWL>(F, Nd, N, N, nb, true, b.ipiv, sh);
+  bool ok = __builtin_amdgcn_readfirstlane(sh.info) == 0;
+  if (ok) {
+    for (int q = tid; q < N * b.kp; q += kLuThreads) {
+      const int v = q / b.kp, j = q % b.kp;
+      b.z[q] = zmake((j < kk && v == Nd + j) ? 1.f : 0.f, 0.f);
+    }
+    __syncthreads();
+    solve_f32(F, b, nb, ms);
+    for (int q = tid; q < N * b.kp; q += kLuThreads) {
+      const zf x = b.z[q];
+      b.Y[q] = zmake((double)x.x, (double)x.y);
+    }
+    __syncthreads();
+    bool conv = false;
+    for (int it = 0; it < max_refine && !conv; ++it) {
+      residual(A, b);
+      solve_f32(F, b, nb, ms);
+      double dn = 0.0, yn = 0.0;
+      for (int q = tid; q < N * b.kp; q += kLuThreads) {
+        const int v = q / b.kp, j = q % b.kp;
+        const zf d = b.z[q];
+        zd y = b.Y[q];
+        y = zmake(y.x + (double)d.x, y.y + (double)d.y);
+        b.Y[q] = y;
+        if (v >= Nd && j < kk) {
+          dn += (double)d.x * d.x + (double)d.y * d.y;
+          yn += y.x * y.x + y.y * y.y;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        dn += __shfl_xor(dn, off);
+        yn += __shfl_xor(yn, off);
+      }
+      if (lane == 0) {
+        ms.red[0][wave] = dn;
+        ms.red[1][wave] = yn;
+      }
+      __syncthreads();
+      dn = 0.0;
+      yn = 0.0;
+#pragma unroll
+      for (int q = 0; q < kLuWaves; ++q) {
+        dn += ms.red[0][q];
+        yn += ms.red[1][q];
+      }
+      conv = __builtin_amdgcn_readfirstlane((int)(dn <= tol * tol * yn)) != 0;
+      __syncthreads();
+    }
+    ok = conv;
+  }
+  if (ok) {
+    const int e = p.e_idx[inst];
+    const zd kap = zsqrt(reinterpret_cast<const zd*>(p.energy)[e]);
+    const int s0 = min(max(p.species[p.liz_off[inst]], 0), p.n_species - 1);
+    const zd* dl = reinterpret_cast<const zd*>(p.delta) + ((int64_t)s0 * p.n_energy + e) * (p.lmax + 1);
+    zd* tout = reinterpret_cast<zd*>(tau00) + (int64_t)inst * kk * kk;
+    if (tid == 0) ms.flag = 0;
+    __syncthreads();
+    for (int q = tid; q < kk * kk; q += kLuThreads) {
+      const int L = q % kk, Lp = q / kk;
+      // [M^{-1}]_00(L, L') = Y(Nd + L', L)
+      const zd v = zmul(b.Y[(int64_t)(Nd + Lp) * b.kp + L], tmat_from_delta(dl[l_of(Lp)], kap));
+      if (!zfinite(v)) ms.flag = 1;
+      tout[q] = v;
+    }
+    __syncthreads();
+    if (tid == 0) info[inst] = ms.flag ? -1 : 0;
+    __syncthreads();
+  } else {
+    lu_instance<kR, kWL>(p, inst, A64, tau00, info, nb, *reinterpret_cast<LuSmemD*>(smem));
+    if (tid == 0 && info[inst] == 0) info[inst] = kInfoIrFallback;
+    __syncthreads();
+  }
+}
+
+// LDS of the precision-form kernels: the FP32 elimination, the FP64 fallback
+// and (persistent form) the build use the same bytes one after the other.
+size_t mixed_smem_bytes() {
+  size_t b = sizeof(MixedSmem) > sizeof(LuSmemD) ? sizeof(MixedSmem) : sizeof(LuSmemD);
+  return b > sizeof(BuildSmem) ? b : sizeof(BuildSmem);
+}
+
+// Per-instance buffers of the precision form inside a slot of `bytes` bytes
+// laid out as [FP32 matrix | z | Y | pivots], each 256-byte aligned, for
+// matrices up to nmax.
+__host__ __device__ inline int64_t mixed_extra_bytes(int64_t nmax, int kp) {
+  const int64_t a = ((nmax * nmax * 8) + 255) & ~(int64_t)255;
+  const int64_t z = ((nmax * kp * 8) + 255) & ~(int64_t)255;
+  const int64_t y = ((nmax * kp * 16) + 255) & ~(int64_t)255;
+  const int64_t pv = ((nmax * 4) + 255) & ~(int64_t)255;
+  return a + z + y + pv;
+}
+
+__device__ inline MixedBufs mixed_bufs(unsigned char* base, int64_t nmax, int kp) {
+  MixedBufs b;
+  const int64_t a = ((nmax * nmax * 8) + 255) & ~(int64_t)255;
+  const int64_t z = ((nmax * kp * 8) + 255) & ~(int64_t)255;
+  const int64_t y = ((nmax * kp * 16) + 255) & ~(int64_t)255;
+  b.A32 = reinterpret_cast<zf*>(base);
+  b.z = reinterpret_cast<zf*>(base + a);
+  b.Y = reinterpret_cast<zd*>(base + a + z);
+  b.ipiv = reinterpret_cast<int32_t*>(base + a + z + y);
+  b.kp = kp;
+  return b;
+}
+
+// Chunked form: one workgroup per instance of the pass; M_i (FP64) at
+// M + (i - i0) * slot, its precision-form buffers at extra + (i - i0) * xslot.
+template <int kR, int kWL>
+__global__ __launch_bounds__(kThreads) void tau00_mixed_kernel(lsms_prob_dev p, int i0, double* __restrict__ Mb,
+                                                              int64_t slot, unsigned char* __restrict__ extra,
+                                                              int64_t xslot, double* __restrict__ tau00,
+                                                              int32_t* __restrict__ info, int nb, double tol,
+                                                              int max_refine) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int inst = i0 + blockIdx.x;
+  const bool invalid = instance_invalid<kR>(p, inst);
+  if (info[inst] != 0 || invalid) {
+    fill_nan(p, inst, tau00);
+    if (invalid && threadIdx.x == 0) info[inst] = -3;
+    return;
+  }
+  const int kp = p.kk > 16 ? 32 : 16;
+  const MixedBufs b = mixed_bufs(extra + (int64_t)blockIdx.x * xslot, (int64_t)p.kk * p.max_liz, kp);
+  mixed_instance<kR, kWL>(p, inst, reinterpret_cast<zd*>(Mb) + (int64_t)blockIdx.x * slot, b, tau00, info, nb,
+                          tol, max_refine, smem_raw);
+}
+
+// Persistent form, as tau00_persistent_kernel with the precision form per
+// instance; slot bytes per workgroup: FP64 matrix then the extra buffers.
+template <int kR, int kWL>
+__global__ __launch_bounds__(kThreads) void tau00_mixed_persistent_kernel(
+    lsms_prob_dev p, lsms_gaunt_dev g, const int32_t* __restrict__ order, int n, int32_t* __restrict__ counter,
+    unsigned char* __restrict__ work, int64_t slot_bytes, int64_t m_bytes, double* __restrict__ tau00,
+    int32_t* __restrict__ info, int nb, double tol, int max_refine) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  BuildSmem& sb = *reinterpret_cast<BuildSmem*>(smem_raw);
+  __shared__ int next;
+  unsigned char* base = work + (int64_t)blockIdx.x * slot_bytes;
+  zd* M = reinterpret_cast<zd*>(base);
+  const int kp = p.kk > 16 ? 32 : 16;
+  const MixedBufs b = mixed_bufs(base + m_bytes, (int64_t)p.kk * p.max_liz, kp);
+  __syncthreads();
+  int k = pop_instance(counter, &next);
+  while (k < n) {
+    const int inst = __builtin_amdgcn_readfirstlane(order ? order[k] : k);
+    int status = __builtin_amdgcn_readfirstlane(instance_invalid<kR>(p, inst) ? -3 : 0);
+    if (status == 0) {
+      const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
+      build_setup<kThreads>(p, g, inst, sb);
+      for (int j = 0; j < nliz; ++j) build_column<kThreads>(p, inst, j, M, sb);
+      status = __builtin_amdgcn_readfirstlane(sb.bad_species ? -3 : (sb.bad ? -2 : 0));
+      __syncthreads();
+    }
+    if (status == 0) {
+      mixed_instance<kR, kWL>(p, inst, M, b, tau00, info, nb, tol, max_refine, smem_raw);
+    } else {
+      fill_nan(p, inst, tau00);
+      if (threadIdx.x == 0) info[inst] = status;
+    }
+    __syncthreads();
+    k = pop_instance(counter, &next);
+  }
+}
+
 template <int kR, int kWL>
 hipError_t launch(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, const int64_t* m_off, int64_t slot,
                   double* tau00, int32_t* info, int keep_info, int32_t nb, hipStream_t s) {
-  const size_t smem = sizeof(LuSmem);
+  const size_t smem = sizeof(LuSmemD);
   hipLaunchKernelGGL((lu_schur_fp64_kernel<kR, kWL>), dim3(n), dim3(kThreads), smem, s, p, i0, M, m_off, slot,
                      tau00, info, keep_info, nb);
   return hipGetLastError();
@@ -598,9 +684,28 @@ template <int kR, int kWL>
 hipError_t launch_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order, int32_t n,
                              int32_t* counter, double* work, int64_t slot, int grid, double* tau00, int32_t* info,
                              int32_t nb, hipStream_t s) {
-  const size_t smem = sizeof(LuSmem) > sizeof(BuildSmem) ? sizeof(LuSmem) : sizeof(BuildSmem);
+  const size_t smem = sizeof(LuSmemD) > sizeof(BuildSmem) ? sizeof(LuSmemD) : sizeof(BuildSmem);
   hipLaunchKernelGGL((tau00_persistent_kernel<kR, kWL>), dim3(grid), dim3(kThreads), smem, s, p, g, order, n,
                      counter, work, slot, tau00, info, nb);
+  return hipGetLastError();
+}
+
+template <int kR, int kWL>
+hipError_t launch_mixed(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, int64_t slot,
+                        unsigned char* extra, int64_t xslot, double* tau00, int32_t* info, int32_t nb, double tol,
+                        int32_t max_refine, hipStream_t s) {
+  hipLaunchKernelGGL((tau00_mixed_kernel<kR, kWL>), dim3(n), dim3(kThreads), mixed_smem_bytes(), s, p, i0, M, slot,
+                     extra, xslot, tau00, info, nb, tol, max_refine);
+  return hipGetLastError();
+}
+
+template <int kR, int kWL>
+hipError_t launch_mixed_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order,
+                                   int32_t* counter, unsigned char* work, int64_t slot_bytes, int64_t m_bytes,
+                                   int grid, double* tau00, int32_t* info, int32_t nb, double tol,
+                                   int32_t max_refine, hipStream_t s) {
+  hipLaunchKernelGGL((tau00_mixed_persistent_kernel<kR, kWL>), dim3(grid), dim3(kThreads), mixed_smem_bytes(), s,
+                     p, g, order, p.n_inst, counter, work, slot_bytes, m_bytes, tau00, info, nb, tol, max_refine);
   return hipGetLastError();
 }
 
@@ -656,7 +761,7 @@ hipError_t lsms_persistent_grid(const lsms_prob_dev& p, int device, int* grid) {
   int cus = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
-  const size_t smem = sizeof(LuSmem) > sizeof(BuildSmem) ? sizeof(LuSmem) : sizeof(BuildSmem);
+  const size_t smem = sizeof(LuSmemD) > sizeof(BuildSmem) ? sizeof(LuSmemD) : sizeof(BuildSmem);
   int per_cu = 0;
   const int64_t nmax = (int64_t)p.kk * p.max_liz;
   if (nmax <= kThreads * 5)
@@ -681,12 +786,61 @@ hipError_t lsms_launch_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& 
 // Dynamic LDS limits of every elimination kernel; called once per device
 // (at handle creation) so that no attribute call happens inside a capture.
 hipError_t lsms_prepare_kernels() {
-  const int a = (int)sizeof(LuSmem);
-  const int b = (int)(sizeof(LuSmem) > sizeof(BuildSmem) ? sizeof(LuSmem) : sizeof(BuildSmem));
+  const int a = (int)sizeof(LuSmemD);
+  const int b = (int)(sizeof(LuSmemD) > sizeof(BuildSmem) ? sizeof(LuSmemD) : sizeof(BuildSmem));
+  const int m = (int)mixed_smem_bytes();
   const hipFuncAttribute attr = hipFuncAttributeMaxDynamicSharedMemorySize;
   hipError_t e;
+  if ((e = hipFuncSetAttribute((const void*)tau00_mixed_kernel<5, 4>, attr, m)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)tau00_mixed_kernel<8, 4>, attr, m)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)tau00_mixed_persistent_kernel<5, 4>, attr, m)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)tau00_mixed_persistent_kernel<8, 4>, attr, m)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)lu_schur_fp64_kernel<5, 4>, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)lu_schur_fp64_kernel<8, 4>, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)tau00_persistent_kernel<5, 4>, attr, b)) != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)tau00_persistent_kernel<8, 4>, attr, b);
+}
+
+int64_t lsms_mixed_extra_bytes(const lsms_prob_dev& p) {
+  return mixed_extra_bytes((int64_t)p.kk * p.max_liz, p.kk > 16 ? 32 : 16);
+}
+
+hipError_t lsms_launch_mixed(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, int64_t slot,
+                             unsigned char* extra, int64_t xslot, double* tau00, int32_t* info, int32_t nb, double tol,
+                             int32_t max_refine, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  if (nmax <= kThreads * 5)
+    return launch_mixed<5, 4>(p, i0, n, M, slot, extra, xslot, tau00, info, nb, tol, max_refine, s);
+  return launch_mixed<8, 4>(p, i0, n, M, slot, extra, xslot, tau00, info, nb, tol, max_refine, s);
+}
+
+hipError_t lsms_mixed_persistent_grid(const lsms_prob_dev& p, int device, int* grid) {
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  if (nmax <= kThreads * 5)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_mixed_persistent_kernel<5, 4>, kThreads,
+                                                     mixed_smem_bytes());
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_mixed_persistent_kernel<8, 4>, kThreads,
+                                                     mixed_smem_bytes());
+  if (e != hipSuccess) return e;
+  *grid = cus * (per_cu > 0 ? per_cu : 1);
+  return hipSuccess;
+}
+
+hipError_t lsms_launch_mixed_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order,
+                                        int32_t* counter, unsigned char* work, int64_t slot_bytes, int64_t m_bytes,
+                                        int grid, double* tau00, int32_t* info, int32_t nb, double tol,
+                                        int32_t max_refine, hipStream_t s) {
+  if (p.n_inst <= 0) return hipSuccess;
+  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  if (nmax <= kThreads * 5)
+    return launch_mixed_persistent<5, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, tau00, info, nb, tol,
+                                         max_refine, s);
+  return launch_mixed_persistent<8, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, tau00, info, nb, tol,
+                                       max_refine, s);
 }

@@ -44,9 +44,15 @@ class Opts(ctypes.Structure):
         ("nb", ctypes.c_int32),
         ("chunk", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("max_refine", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("tol", ctypes.c_double),
     ]
 
 
+PREC_FP64 = 0
+PREC_FP32_IR = 1
+INFO_FP64_FALLBACK = 256
 PERSISTENT = 1
 GRAPH = 2
 

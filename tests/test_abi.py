@@ -30,8 +30,21 @@ def test_struct_layouts():
     from paper_2308_16317_amd import lsms
 
     assert ctypes.sizeof(lsms._Problem) == 6 * 4 + 6 * 8
-    assert ctypes.sizeof(lsms.Opts) == 4 * 4
-    assert [f[0] for f in lsms.Opts._fields_] == ["precision", "nb", "chunk", "flags"]
+    assert ctypes.sizeof(lsms.Opts) == 6 * 4 + 8
+    assert [f[0] for f in lsms.Opts._fields_] == ["precision", "nb", "chunk", "flags", "max_refine", "reserved",
+                                                  "tol"]
+
+
+def test_header_constants_match_binding():
+    from paper_2308_16317_amd import lsms
+
+    src = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(LSMS_\w+)\s+\(?(-?\d+)\)?", src))
+    assert int(defs["LSMS_PREC_FP64"]) == lsms.PREC_FP64
+    assert int(defs["LSMS_PREC_FP32_IR"]) == lsms.PREC_FP32_IR
+    assert int(defs["LSMS_INFO_FP64_FALLBACK"]) == lsms.INFO_FP64_FALLBACK
+    assert int(defs["LSMS_PERSISTENT"]) == lsms.PERSISTENT
+    assert int(defs["LSMS_GRAPH"]) == lsms.GRAPH
 
 
 def test_null_handle_rejected_without_gpu():
