@@ -326,12 +326,37 @@ __device__ __noinline__ void invert_upper(const Mat<typename Prec<R>::C>& A, int
   __syncthreads();
 }
 
+// Loads the B operands of one 16-deep chunk of trsm_strip: lane (li, lk)
+// takes rows k = kc + 4 lk + j (j < 4) of its two columns, zero outside
+// k < s and the strip.
+template <typename C>
+__device__ __forceinline__ void trsm_load_chunk(const Mat<C>& A, int r0, int s, int kc, int lk,
+                                                const int64_t (&bcol)[2], const bool (&cok)[2], C (&dst)[2][4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = kc + 4 * lk + j;
+    const bool kok = k < s;
+    const C* rowp = A.base + A.phys(r0 + (kok ? k : 0)) * A.N;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      C b;
+      b.x = 0;
+      b.y = 0;
+      if (kok && cok[t]) b = rowp[bcol[t]];
+      dst[t][j] = b;
+    }
+  }
+}
+
 // U = X * A(r0 .. r0+s-1, s0 .. s0+sw-1) into sh.U rows 0..63 (rows >= s are
 // zero), and, if `store`, also into those rows of A.  Sixteen 16x16 output
-// tiles, two per wave.
+// tiles, two per wave.  The reduction runs in chunks of 16 (lane (li, lk)
+// supplies k = kc + 4 lk + j at MFMA step j), the next chunk being loaded
+// while the current one is multiplied; X is lower triangular, so row tile rt
+// stops at k = 16 rt + 16.
 template <typename R>
-__device__ void trsm_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw, bool store,
-                           LuSmem<R>& sh) {
+__device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
+                                        bool store, LuSmem<R>& sh) {
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -344,22 +369,38 @@ __device__ void trsm_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, int
     ar[t] = V4{R(0), R(0), R(0), R(0)};
     ai[t] = V4{R(0), R(0), R(0), R(0)};
   }
-  const int row = 16 * rt + li;
-  const int kend = min(s, 16 * rt + 16);  // X is lower triangular
-  for (int kb = 0; kb < kend; kb += 4) {
-    const int k = kb + lk;
-    const C x = sh.X[row][k];
-    const R xr = (k < s) ? x.x : R(0);
-    const R xi = (k < s) ? x.y : R(0);
+  int64_t bcol[2];
+  bool cok[2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int col = 16 * (ct0 + t) + li;
-      C b = zmake(R(0), R(0));
-      if (k < s && col < sw) b = *A.ptr(r0 + k, s0 + col);
-      ar[t] = Prec<R>::mfma(xr, b.x, ar[t]);
-      ar[t] = Prec<R>::mfma(-xi, b.y, ar[t]);
-      ai[t] = Prec<R>::mfma(xr, b.y, ai[t]);
-      ai[t] = Prec<R>::mfma(xi, b.x, ai[t]);
+  for (int t = 0; t < 2; ++t) {
+    const int col = 16 * (ct0 + t) + li;
+    cok[t] = col < sw;
+    bcol[t] = A.phys(s0 + min(col, sw - 1));
+  }
+  const int row = 16 * rt + li;
+  const int kend = min(s, 16 * rt + 16);
+  C bn[2][4];
+  if (kend > 0) trsm_load_chunk(A, r0, s, 0, lk, bcol, cok, bn);
+  for (int kc = 0; kc < kend; kc += 16) {
+    C b[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[t][j] = bn[t][j];
+    if (kc + 16 < kend) trsm_load_chunk(A, r0, s, kc + 16, lk, bcol, cok, bn);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = kc + 4 * lk + j;
+      const C x = sh.X[row][k & (kNB - 1)];
+      const R xr = (k < s) ? x.x : R(0);
+      const R xi = (k < s) ? x.y : R(0);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        ar[t] = Prec<R>::mfma(xr, b[t][j].x, ar[t]);
+        ar[t] = Prec<R>::mfma(-xi, b[t][j].y, ar[t]);
+        ai[t] = Prec<R>::mfma(xr, b[t][j].y, ai[t]);
+        ai[t] = Prec<R>::mfma(xi, b[t][j].x, ai[t]);
+      }
     }
   }
   __syncthreads();  // earlier readers of sh.U are done
@@ -376,42 +417,96 @@ __device__ void trsm_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, int
 }
 
 // A(v, s0 + j) -= sum_{k < s} A(v, r0 + k) U[k][j] for v in [r0 + s, N),
-// j < sw.  Each wave owns blocks of 16 rows x 64 columns (four MFMA tiles);
-// MFMA step kb uses k = kb + lane/16.
-template <typename R>
-__device__ void update_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
-                             const LuSmem<R>& sh) {
+// j < sw <= 16 NCS.  Each wave owns blocks of 16 rows x 16 NCS columns (NCS
+// MFMA tiles) whose accumulators start from the loaded block of A.  The
+// reduction runs in chunks of 16: in a chunk starting at kc, lane (li, lq)
+// supplies k = kc + 4 lq + j at MFMA step j, so that it reads four
+// consecutive entries of its row.  Loads run one chunk ahead: the next chunk
+// of the row block, or, during its last chunk, the next row block's
+// accumulator block and first chunk.  The LDS operand rows U[k] are zero for
+// k >= s.
+template <typename R, int NCS>
+__device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
+                                            const LuSmem<R>& sh) {
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int N = (int)A.N;
   const int rstart = r0 + s;
-  const int ncs = (sw + 15) >> 4;
-  for (int rb = rstart + 16 * wave; rb < N; rb += 16 * kLuWaves) {
-    V4 accr[4], acci[4];
+  const int64_t pr0 = A.phys(r0) + 4 * lq;
+  int64_t ccol[NCS];
+  bool cok[NCS];
 #pragma unroll
-    for (int cs = 0; cs < 4; ++cs) {
-      accr[cs] = V4{R(0), R(0), R(0), R(0)};
-      acci[cs] = V4{R(0), R(0), R(0), R(0)};
+  for (int cs = 0; cs < NCS; ++cs) {
+    cok[cs] = 16 * cs + li < sw;
+    ccol[cs] = A.phys(s0 + min(16 * cs + li, sw - 1));
+  }
+  int rb = rstart + 16 * wave;
+  if (rb >= N) return;
+  C cn[NCS][4], an[4];
+  // accumulator block of row block q: rows q + drow(r, lq)
+  auto load_c = [&](int q) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = q + Prec<R>::drow(r, lq);
+      const C* crow = A.base + A.phys(v < N ? v : rstart) * A.N;
+#pragma unroll
+      for (int cs = 0; cs < NCS; ++cs) {
+        C cv;
+        cv.x = 0;
+        cv.y = 0;
+        if (v < N && cok[cs]) cv = crow[ccol[cs]];
+        cn[cs][r] = cv;
+      }
     }
-    const int va = rb + li;
-    const bool rok = va < N;
-    const C* arow = A.base + A.phys(rok ? va : rstart) * A.N + A.phys(r0);
-#pragma unroll 4
-    for (int kb = 0; kb < s; kb += 4) {
-      const int k = kb + lq;
-      const C a = (rok && k < s) ? arow[k] : zmake(R(0), R(0));
-      C b[4];
+  };
+  // chunk kc of the L operand of row block q: row q + li, k = kc + 4 lq + j
+  auto load_a = [&](int q, int kc) {
+    const int va = q + li;
+    const C* arow = A.base + A.phys(va < N ? va : rstart) * A.N + pr0 + kc;
 #pragma unroll
-      for (int cs = 0; cs < 4; ++cs) b[cs] = sh.U[k & (kNB - 1)][16 * cs + li];
+    for (int j = 0; j < 4; ++j) {
+      C av;
+      av.x = 0;
+      av.y = 0;
+      if (va < N && kc + 4 * lq + j < s) av = arow[j];
+      an[j] = av;
+    }
+  };
+  load_c(rb);
+  load_a(rb, 0);
+  for (; rb < N; rb += 16 * kLuWaves) {
+    const int rn = rb + 16 * kLuWaves;
+    V4 accr[NCS], acci[NCS];
 #pragma unroll
-      for (int cs = 0; cs < 4; ++cs) {
-        if (cs < ncs) {
-          accr[cs] = Prec<R>::mfma(a.x, b[cs].x, accr[cs]);
-          accr[cs] = Prec<R>::mfma(-a.y, b[cs].y, accr[cs]);
-          acci[cs] = Prec<R>::mfma(a.x, b[cs].y, acci[cs]);
-          acci[cs] = Prec<R>::mfma(a.y, b[cs].x, acci[cs]);
+    for (int cs = 0; cs < NCS; ++cs)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        accr[cs][r] = cn[cs][r].x;
+        acci[cs][r] = cn[cs][r].y;
+      }
+    for (int kc = 0; kc < s; kc += 16) {
+      C a[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[j] = an[j];
+      if (kc + 16 < s) {
+        load_a(rb, kc + 16);
+      } else if (rn < N) {
+        load_c(rn);
+        load_a(rn, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = (kc + 4 * lq + j) & (kNB - 1);
+        const R nx = -a[j].x, ny = -a[j].y;
+#pragma unroll
+        for (int cs = 0; cs < NCS; ++cs) {
+          const C b = sh.U[k][16 * cs + li];
+          accr[cs] = Prec<R>::mfma(nx, b.x, accr[cs]);
+          accr[cs] = Prec<R>::mfma(a[j].y, b.y, accr[cs]);
+          acci[cs] = Prec<R>::mfma(nx, b.y, acci[cs]);
+          acci[cs] = Prec<R>::mfma(ny, b.x, acci[cs]);
         }
       }
     }
@@ -421,16 +516,21 @@ __device__ void update_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, i
       if (v >= N) continue;
       C* crow = A.base + A.phys(v) * A.N;
 #pragma unroll
-      for (int cs = 0; cs < 4; ++cs) {
-        const int col = 16 * cs + li;
-        if (col < sw) {
-          C* p = crow + A.phys(s0 + col);
-          const C cv = *p;
-          *p = zmake(cv.x - accr[cs][r], cv.y - acci[cs][r]);
-        }
-      }
+      for (int cs = 0; cs < NCS; ++cs)
+        if (cok[cs]) crow[ccol[cs]] = zmake(accr[cs][r], acci[cs][r]);
     }
   }
+}
+
+// A(v, s0 + j) -= sum_{k < s} A(v, r0 + k) U[k][j] for v in [r0 + s, N),
+// j < sw <= 64, with U = sh.U.
+template <typename R>
+__device__ __noinline__ void update_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
+                                          const LuSmem<R>& sh) {
+  if (sw > 48) update_rows<R, 4>(A, r0, s, s0, sw, sh);
+  else if (sw > 32) update_rows<R, 3>(A, r0, s, s0, sw, sh);
+  else if (sw > 16) update_rows<R, 2>(A, r0, s, s0, sw, sh);
+  else update_rows<R, 1>(A, r0, s, s0, sw, sh);
 }
 
 // Row interchanges of the panel [c, c + w) applied to the columns [c0, c1).
