@@ -24,6 +24,22 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+
+# HBM bytes per instance moved by the fused kernel (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, each scaled by the counts of a plain copy of known size), valid
+# only for the kernel sources whose hash is given; null otherwise.
+TRAFFIC_PER_INSTANCE = {("fp64", "4fb2f07e9ebdcc6f"): 2.99e9}
+KERNEL_SOURCES = ("kkr_device.h", "lu_device.h", "lu_fp64.hip", "lsms_common.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2308_16317_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 METRIC = "τ00 solves/s at N=2160, 1e-10 rel: mixed/batched vs plain FP64; TFLOP/s vs peak"
 
 
@@ -175,6 +191,8 @@ def main():
     lu_flops = [float(np.sum(8.0 / 3.0 * (Nc.double().cpu().numpy()) ** 3)) for (_, _, _, Nc) in events]
     ach = float(np.sum(lu_flops) / (np.sum(lu_ms) * 1e-3) / 1e12)
     peak = FP32_PEAK_TFLOPS if args.precision == "fp32ir" else FP64_PEAK_TFLOPS
+    per_inst = TRAFFIC_PER_INSTANCE.get((args.precision, kernel_source_hash()))
+    traffic = None if (per_inst is None or args.mode == "chunked") else per_inst * chunk
     form = ("complex FP32 LU + FP64 iterative refinement to 1e-12 (FP64 fallback per instance)"
             if args.precision == "fp32ir" else "complex FP64 LU/Schur")
     out = {
@@ -197,7 +215,7 @@ def main():
                    "fp64_fallbacks": fallback},
         "tflops": flops_step / (ms * 1e-3) / 1e12,
         "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                     "frac": ach / peak, "traffic": None,
+                     "frac": ach / peak, "traffic": traffic,
                      "kernel": kernel, "ms_per_launch": float(np.mean(lu_ms)),
                      "instances_per_launch": chunk},
     }

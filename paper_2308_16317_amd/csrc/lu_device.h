@@ -66,6 +66,9 @@ struct LuSmem {
   R redv[kLuWaves];
   int redi[kLuWaves];
   int ipiv[kNB];
+  int lrow[2 * kMaxWL];  // rows touched by a leaf's interchanges
+  int lsrc[2 * kMaxWL];  // lrow[q] receives the old content of lrow[lsrc[q]]
+  int lcnt;
   int info;
   int bad;
   int gj_piv;
@@ -164,17 +167,6 @@ __device__ __noinline__ void leaf_factor(const Mat<typename Prec<R>::C>& A, int 
         for (int k = 0; k < kWL; ++k) sh.rowP[k] = a[q][k];
       }
     }
-    // interchange the rows in the panel columns outside the leaf
-    if (bi != j && tid < w) {
-      const int col = c + tid;
-      if (col < lc || col >= lc + wl) {
-        C* pj = A.ptr(j, col);
-        C* pb = A.ptr(bi, col);
-        const C x = *pj, y = *pb;
-        *pj = y;
-        *pb = x;
-      }
-    }
     if (tid == 0) {
       sh.ipiv[j - c] = bi;
       if (zero && best == R(0) && sh.info == 0) sh.info = j + 1;
@@ -216,6 +208,35 @@ __device__ __noinline__ void leaf_factor(const Mat<typename Prec<R>::C>& A, int 
       }
     }
   }
+  // The leaf's interchanges, composed into one permutation of at most 2 wl
+  // rows, applied to the other columns of the panel: every touched row is
+  // loaded first, then stored in its final place.
+  if (tid == 0) {
+    int n = 0;
+    for (int jj = 0; jj < wl; ++jj) {
+      const int r0 = lc + jj, r1 = sh.ipiv[lc + jj - c];
+      if (r0 == r1) continue;
+      int i0 = -1, i1 = -1;
+      for (int q = 0; q < n; ++q) {
+        if (sh.lrow[q] == r0) i0 = q;
+        if (sh.lrow[q] == r1) i1 = q;
+      }
+      if (i0 < 0) {
+        sh.lrow[n] = r0;
+        sh.lsrc[n] = n;
+        i0 = n++;
+      }
+      if (i1 < 0) {
+        sh.lrow[n] = r1;
+        sh.lsrc[n] = n;
+        i1 = n++;
+      }
+      const int t = sh.lsrc[i0];
+      sh.lsrc[i0] = sh.lsrc[i1];
+      sh.lsrc[i1] = t;
+    }
+    sh.lcnt = n;
+  }
 #pragma unroll
   for (int q = 0; q < kR; ++q) {
     const int v = lc + tid + kLuThreads * q;
@@ -224,6 +245,26 @@ __device__ __noinline__ void leaf_factor(const Mat<typename Prec<R>::C>& A, int 
 #pragma unroll
       for (int k = 0; k < kWL; ++k)
         if (k < wl) row[k] = a[q][k];
+    }
+  }
+  __syncthreads();
+  const int n = sh.lcnt;
+  if (n > 0 && tid < w && (c + tid < lc || c + tid >= lc + wl)) {
+    const int col = c + tid;
+    C v[2 * kWL];
+#pragma unroll
+    for (int q = 0; q < 2 * kWL; ++q)
+      if (q < n) v[q] = *A.ptr(sh.lrow[q], col);
+#pragma unroll
+    for (int q = 0; q < 2 * kWL; ++q) {
+      if (q < n) {
+        const int sidx = sh.lsrc[q];
+        C x = v[0];
+#pragma unroll
+        for (int r = 1; r < 2 * kWL; ++r)
+          if (sidx == r) x = v[r];
+        *A.ptr(sh.lrow[q], col) = x;
+      }
     }
   }
   __syncthreads();

@@ -283,51 +283,94 @@ __device__ void tri_apply(const MixedBufs& b, int r0, int s, LuSmem<float>& sh) 
   __syncthreads();
 }
 
-// z[v] -= sum_{k < s} A(v, r0 + k) sh.U[k] for v in [v0, N): 16-row blocks per wave.
-__device__ void rhs_update(const Mat<zf>& A, const MixedBufs& b, int r0, int s, int v0, const LuSmem<float>& sh) {
+// z[v] -= sum_{k < s} A(v, r0 + k) sh.U[k] for v in [v0, N): 16-row blocks
+// per wave, accumulators starting from the loaded block of z; the reduction
+// in chunks of 16 (lane (li, lq) supplies k = kc + 4 lq + j at MFMA step j),
+// loads one chunk (or, in the last chunk, the next row block) ahead.
+template <int NCT>
+__device__ void rhs_update_rows(const Mat<zf>& A, const MixedBufs& b, int r0, int s, int v0,
+                                const LuSmem<float>& sh) {
   typedef Prec<float>::V4 V4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
-  const int N = (int)A.N, nct = b.kp / 16;
-  for (int rb = v0 + 16 * wave; rb < N; rb += 16 * kLuWaves) {
-    V4 ar[2], ai[2];
+  const int N = (int)A.N;
+  const int64_t pr0 = A.phys(r0) + 4 * lq;
+  int rb = v0 + 16 * wave;
+  if (rb < N) {
+    zf cn[NCT][4], an[4];
+    auto load_c = [&](int q) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      ar[t] = V4{0.f, 0.f, 0.f, 0.f};
-      ai[t] = V4{0.f, 0.f, 0.f, 0.f};
-    }
-    const int va = rb + li;
-    const bool rok = va < N;
-    const zf* arow = A.base + A.phys(rok ? va : v0) * A.N + A.phys(r0);
-    for (int kb = 0; kb < s; kb += 4) {
-      const int k = kb + lq;
-      const zf a = (rok && k < s) ? arow[k] : zmake(0.f, 0.f);
+      for (int r = 0; r < 4; ++r) {
+        const int v = q + Prec<float>::drow(r, lq);
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        if (t < nct) {
-          const zf u = sh.U[k & (kNB - 1)][16 * t + li];
-          ar[t] = Prec<float>::mfma(a.x, u.x, ar[t]);
-          ar[t] = Prec<float>::mfma(-a.y, u.y, ar[t]);
-          ai[t] = Prec<float>::mfma(a.x, u.y, ai[t]);
-          ai[t] = Prec<float>::mfma(a.y, u.x, ai[t]);
+        for (int t = 0; t < NCT; ++t) {
+          zf cv = zmake(0.f, 0.f);
+          if (v < N) cv = b.z[(int64_t)v * b.kp + 16 * t + li];
+          cn[t][r] = cv;
         }
       }
-    }
+    };
+    auto load_a = [&](int q, int kc) {
+      const int va = q + li;
+      const zf* arow = A.base + A.phys(va < N ? va : v0) * A.N + pr0 + kc;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      if (t >= nct) continue;
+      for (int j = 0; j < 4; ++j) {
+        zf av = zmake(0.f, 0.f);
+        if (va < N && kc + 4 * lq + j < s) av = arow[j];
+        an[j] = av;
+      }
+    };
+    load_c(rb);
+    load_a(rb, 0);
+    for (; rb < N; rb += 16 * kLuWaves) {
+      const int rn = rb + 16 * kLuWaves;
+      V4 ar[NCT], ai[NCT];
+#pragma unroll
+      for (int t = 0; t < NCT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          ar[t][r] = cn[t][r].x;
+          ai[t][r] = cn[t][r].y;
+        }
+      for (int kc = 0; kc < s; kc += 16) {
+        zf a[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[j] = an[j];
+        if (kc + 16 < s) {
+          load_a(rb, kc + 16);
+        } else if (rn < N) {
+          load_c(rn);
+          load_a(rn, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = (kc + 4 * lq + j) & (kNB - 1);
+          const float nx = -a[j].x, ny = -a[j].y;
+#pragma unroll
+          for (int t = 0; t < NCT; ++t) {
+            const zf u = sh.U[k][16 * t + li];
+            ar[t] = Prec<float>::mfma(nx, u.x, ar[t]);
+            ar[t] = Prec<float>::mfma(a[j].y, u.y, ar[t]);
+            ai[t] = Prec<float>::mfma(nx, u.y, ai[t]);
+            ai[t] = Prec<float>::mfma(ny, u.x, ai[t]);
+          }
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int v = rb + Prec<float>::drow(r, lq);
-        if (v < N) {
-          zf* pz = b.z + (int64_t)v * b.kp + 16 * t + li;
-          const zf c = *pz;
-          *pz = zmake(c.x - ar[t][r], c.y - ai[t][r]);
-        }
+        if (v >= N) continue;
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) b.z[(int64_t)v * b.kp + 16 * t + li] = zmake(ar[t][r], ai[t][r]);
       }
     }
   }
   __syncthreads();
+}
+
+__device__ void rhs_update(const Mat<zf>& A, const MixedBufs& b, int r0, int s, int v0, const LuSmem<float>& sh) {
+  if (b.kp > 16) rhs_update_rows<2>(A, b, r0, s, v0, sh);
+  else rhs_update_rows<1>(A, b, r0, s, v0, sh);
 }
 
 // z := A32^{-1} z with the panel structure of the factorisation: forward with
@@ -429,40 +472,68 @@ __device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, MixedSme
   }
 }
 
-// z = E_c - A64 Y in FP32 (rows of the FP64 matrix times the FP64 solution).
-__device__ void residual(const Mat<zd>& A, const MixedBufs& b) {
+// z = E_c - A64 Y in FP32 (rows of the FP64 matrix times the FP64 solution),
+// one 16-row block per wave at a time.  The reduction over k runs in chunks
+// of 16 (lane (li, lq) supplies k = kc + 4 lq + j at MFMA step j, four
+// consecutive entries of its matrix row) with the next chunk's operands
+// loaded while the current one is multiplied.
+template <int NCT>
+__device__ void residual_rows(const Mat<zd>& A, const MixedBufs& b) {
   typedef Prec<double>::V4 V4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
-  const int N = (int)A.N, Nd = A.Nd, nct = b.kp / 16, kk = A.kk;
+  const int N = (int)A.N, Nd = A.Nd, kk = A.kk;
   for (int rb = 16 * wave; rb < N; rb += 16 * kLuWaves) {
-    V4 ar[2], ai[2];
+    V4 ar[NCT], ai[NCT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NCT; ++t) {
       ar[t] = V4{0.0, 0.0, 0.0, 0.0};
       ai[t] = V4{0.0, 0.0, 0.0, 0.0};
     }
     const int va = rb + li;
     const bool rok = va < N;
     const zd* arow = A.base + A.phys(rok ? va : 0) * A.N;
-    for (int kb = 0; kb < N; kb += 4) {
-      const int k = kb + lq;
-      const bool kok = k < N;
-      const zd a = (rok && kok) ? arow[A.phys(k)] : zmake(0.0, 0.0);
+    // A(va, k) for k < Nd is at arow[kk + k], for k >= Nd at arow[k - Nd]
+    zd an[4], yn[NCT][4];
+    auto load = [&](int kc) {
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        if (t < nct) {
-          const zd y = kok ? b.Y[(int64_t)k * b.kp + 16 * t + li] : zmake(0.0, 0.0);
-          ar[t] = Prec<double>::mfma(a.x, y.x, ar[t]);
-          ar[t] = Prec<double>::mfma(-a.y, y.y, ar[t]);
-          ai[t] = Prec<double>::mfma(a.x, y.y, ai[t]);
-          ai[t] = Prec<double>::mfma(a.y, y.x, ai[t]);
+      for (int j = 0; j < 4; ++j) {
+        const int k = kc + 4 * lq + j;
+        const bool kok = k < N;
+        zd av = zmake(0.0, 0.0);
+        if (rok && kok) av = arow[A.phys(k)];
+        an[j] = av;
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+          zd y = zmake(0.0, 0.0);
+          if (kok) y = b.Y[(int64_t)k * b.kp + 16 * t + li];
+          yn[t][j] = y;
+        }
+      }
+    };
+    load(0);
+    for (int kc = 0; kc < N; kc += 16) {
+      zd a[4], y[NCT][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        a[j] = an[j];
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) y[t][j] = yn[t][j];
+      }
+      if (kc + 16 < N) load(kc + 16);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+          ar[t] = Prec<double>::mfma(a[j].x, y[t][j].x, ar[t]);
+          ar[t] = Prec<double>::mfma(-a[j].y, y[t][j].y, ar[t]);
+          ai[t] = Prec<double>::mfma(a[j].x, y[t][j].y, ai[t]);
+          ai[t] = Prec<double>::mfma(a[j].y, y[t][j].x, ai[t]);
         }
       }
     }
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      if (t >= nct) continue;
+    for (int t = 0; t < NCT; ++t) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int v = rb + Prec<double>::drow(r, lq);
@@ -475,6 +546,11 @@ __device__ void residual(const Mat<zd>& A, const MixedBufs& b) {
     }
   }
   __syncthreads();
+}
+
+__device__ void residual(const Mat<zd>& A, const MixedBufs& b) {
+  if (b.kp > 16) residual_rows<2>(A, b);
+  else residual_rows<1>(A, b);
 }
 
 // Precision-form tau00 of one instance.  A64 is the FP64 matrix (left
@@ -520,6 +596,7 @@ __device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd
     }
     __syncthreads();
     bool conv = false;
+    double dprev = 0.0;
     for (int it = 0; it < max_refine && !conv; ++it) {
       residual(A, b);
       solve_f32(F, b, nb, ms);
@@ -551,7 +628,13 @@ __device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd
         dn += ms.red[0][q];
         yn += ms.red[1][q];
       }
-      conv = __builtin_amdgcn_readfirstlane((int)(dn <= tol * tol * yn)) != 0;
+      // converged when the correction is below tol, or when the contraction
+      // seen over the last two steps (at most 1/2) predicts that the next
+      // correction is: |d_k|^2 / |d_{k-1}| <= tol |Y|
+      const bool small = dn <= tol * tol * yn;
+      const bool predicted = it > 0 && dn <= 0.25 * dprev && dn * dn <= tol * tol * yn * dprev;
+      conv = __builtin_amdgcn_readfirstlane((int)(small || predicted)) != 0;
+      dprev = dn;
       __syncthreads();
     }
     ok = conv;
