@@ -95,8 +95,9 @@ typedef struct {
 
 typedef struct {
     int32_t precision;   /* LSMS_PREC_FP64 or LSMS_PREC_FP32_IR                         */
-    int32_t nb;          /* panel width of the LU, 0 = tuned value (lsms_autotune) or 64;
-                            otherwise 16..64, a multiple of 16                          */
+    int32_t nb;          /* panel width of the LU, 0 = tuned value (lsms_autotune) or 128;
+                            otherwise 16..128, a multiple of 16 (tau00_batched uses at
+                            most 64)                                                    */
     int32_t chunk;       /* tau00_solve without LSMS_PERSISTENT: instances per pass,
                             0 = as many as fit                                          */
     int32_t flags;       /* LSMS_PERSISTENT | LSMS_GRAPH                                */
@@ -170,9 +171,11 @@ int tau00_batched(lsms_handle_t h, const lsms_problem *p, double *M, const int64
  * 256-byte-aligned slot per resident workgroup of the persistent kernel (one
  * per compute unit), plus a work counter and the instance order (4 bytes per
  * instance).  A slot holds the FP64 matrix, n^2 * 16 bytes for
- * n = kk*max_liz; with LSMS_PREC_FP32_IR also its FP32 copy (n^2 * 8), the
- * FP32 and FP64 right-hand sides (n * kp * 24, kp = 16 or 32) and the pivots
- * (n * 4), each 256-byte aligned. */
+ * n = kk*max_liz, and the inverses of the two diagonal blocks of a panel
+ * wider than 64 (2 * 64 * 64 * 16 bytes); with LSMS_PREC_FP32_IR also the
+ * matrix's FP32 copy (n^2 * 8), the FP32 and FP64 right-hand sides
+ * (n * kp * 24, kp = 16 or 32) and the pivots (n * 4); each part 256-byte
+ * aligned. */
 int lsms_workspace_size(lsms_handle_t h, const lsms_problem *p, const lsms_opts *opts, int32_t chunk,
                         size_t *bytes);
 
@@ -192,7 +195,7 @@ int tau00_solve(lsms_handle_t h, const lsms_problem *p, const lsms_opts *opts, d
                 void *work, size_t work_bytes, void *stream);
 
 /* Autotuner: times tau00_solve (with opts->flags) on the problem for panel
- * widths nb = 16, 32, 48, 64 after one warm-up each, stores the fastest as
+ * widths nb = 32, 64, 96, 128 after one warm-up each, stores the fastest as
  * the handle's panel width for matrices of this problem's size bucket
  * (kk*max_liz rounded up to 128), returns it in *best_nb and the four
  * timings (ms, in the order above) in ms_out[4] (host).  Synchronises the

@@ -62,7 +62,7 @@ int check_opts(const lsms_opts* o) {
   if (o->precision != LSMS_PREC_FP64 && o->precision != LSMS_PREC_FP32_IR) return -1;
   if (o->max_refine < 0 || o->max_refine > 100 || o->reserved != 0) return -1;
   if (!(o->tol == 0.0 || (o->tol >= 1e-15 && o->tol <= 1e-3))) return -1;
-  if (o->nb != 0 && (o->nb < 16 || o->nb > 64 || (o->nb % 16) != 0)) return -1;
+  if (o->nb != 0 && (o->nb < 16 || o->nb > 128 || (o->nb % 16) != 0)) return -1;
   if (o->chunk < 0) return -1;
   if (o->flags & ~(LSMS_PERSISTENT | LSMS_GRAPH)) return -1;
   return 0;
@@ -79,11 +79,12 @@ size_t slot_elems(const lsms_problem* p) {
 bool mixed(const lsms_opts* o) { return o && o->precision == LSMS_PREC_FP32_IR; }
 
 // Bytes of one instance slot: the FP64 matrix (256-byte aligned), then the
-// buffers of the precision form.
+// two 64 x 64 blocks of wide panels (FP64 form) or the buffers of the
+// precision form (which include those blocks).
 size_t m_bytes(const lsms_problem* p) { return align256(slot_elems(p) * 16); }
 
 size_t slot_bytes(const lsms_problem* p, const lsms_opts* o) {
-  return m_bytes(p) + (mixed(o) ? (size_t)lsms_mixed_extra_bytes(to_dev(p)) : 0);
+  return m_bytes(p) + (mixed(o) ? (size_t)lsms_mixed_extra_bytes(to_dev(p)) : (size_t)kLsmsXgBytes);
 }
 
 double ir_tol(const lsms_opts* o) { return o->tol > 0.0 ? o->tol : 1e-12; }
@@ -124,7 +125,7 @@ namespace {
 int32_t panel_width(const lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o) {
   if (o && o->nb) return o->nb;
   const int32_t t = h->tuned_nb[bucket_of((int64_t)(p->lmax + 1) * (p->lmax + 1) * p->max_liz)];
-  return t ? t : 64;
+  return t ? t : 128;
 }
 
 struct PersistLayout {
@@ -163,10 +164,11 @@ int enqueue_solve(lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o, d
                                                 (int64_t)L.slot_stride, (int64_t)m_bytes(p), L.grid, tau00, info, nb,
                                                 ir_tol(o), ir_steps(o), s)
                  : lsms_launch_persistent(d, h->g[p->lmax], order, counter, (double*)(w + L.slots_off),
-                                          (int64_t)(L.slot_stride / 16), L.grid, tau00, info, nb, s);
+                                          (int64_t)(L.slot_stride / 16), (int64_t)(m_bytes(p) / 16), L.grid,
+                                          tau00, info, nb, s);
     return e == hipSuccess ? 0 : LSMS_EHIP;
   }
-  // chunked: M slots first, then (precision form) the per-instance extra buffers
+  // chunked: M slots first, then the per-instance extra buffers
   const size_t mb = m_bytes(p), slot_b = slot_bytes(p, o);
   if (work_bytes < slot_b) return -7;
   int64_t chunk = (int64_t)(work_bytes / slot_b);
@@ -182,8 +184,8 @@ int enqueue_solve(lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o, d
     const hipError_t e =
         mixed(o) ? lsms_launch_mixed(d, (int32_t)i0, n, (double*)work, (int64_t)(mb / 16), extra, xslot, tau00, info,
                                      nb, ir_tol(o), ir_steps(o), s)
-                 : lsms_launch_lu_fp64(d, (int32_t)i0, n, (double*)work, nullptr, (int64_t)(mb / 16), tau00, info, 1,
-                                       nb, s);
+                 : lsms_launch_lu_fp64(d, (int32_t)i0, n, (double*)work, nullptr, (int64_t)(mb / 16), (double*)extra,
+                                       xslot / 16, tau00, info, 1, nb, s);
     if (e != hipSuccess) return LSMS_EHIP;
   }
   return 0;
@@ -303,7 +305,7 @@ extern "C" int tau00_batched(lsms_handle_t h, const lsms_problem* p, double* M, 
   if (!info) return -7;
   (void)hipSetDevice(h->device);
   const lsms_prob_dev d = to_dev(p);
-  if (lsms_launch_lu_fp64(d, 0, p->n_inst, M, m_off, 0, tau00, info, 0, panel_width(h, p, opts),
+  if (lsms_launch_lu_fp64(d, 0, p->n_inst, M, m_off, 0, nullptr, 0, tau00, info, 0, panel_width(h, p, opts),
                           (hipStream_t)stream) != hipSuccess)
     return LSMS_EHIP;
   return 0;
@@ -396,7 +398,7 @@ extern "C" int tau00_solve(lsms_handle_t h, const lsms_problem* p, const lsms_op
 extern "C" int lsms_set_tuned_nb(lsms_handle_t h, int32_t n, int32_t nb) {
   if (!h) return -1;
   if (n < 1 || n > 4096) return -2;
-  if (nb < 16 || nb > 64 || nb % 16) return -3;
+  if (nb < 16 || nb > 128 || nb % 16) return -3;
   h->tuned_nb[bucket_of(n)] = nb;
   return 0;
 }
@@ -416,8 +418,8 @@ extern "C" int lsms_autotune(lsms_handle_t h, const lsms_problem* p, const lsms_
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  const int32_t cand[4] = {16, 32, 48, 64};
-  int32_t best = 64;
+  const int32_t cand[4] = {32, 64, 96, 128};
+  int32_t best = 128;
   float best_ms = 0.0f;
   for (int c = 0; c < 4; ++c) {
     o.nb = cand[c];

@@ -117,20 +117,25 @@ hipError_t lsms_launch_build(const lsms_prob_dev& p, const lsms_gaunt_dev& g, in
                              hipStream_t s);
 
 // FP64 LU / Schur elimination and tau00 for instances [i0, i0 + n); M
-// addressing as lsms_launch_build.  If keep_info, instances whose info is
-// already nonzero are skipped (tau00 filled with NaN).
+// addressing as lsms_launch_build.  xgb (or null): per-instance room for two
+// 64 x 64 complex blocks at xgb + (i - i0) * xstride complex elements, needed
+// for panels wider than 64 (without it panels are at most 64 wide).  If
+// keep_info, instances whose info is already nonzero are skipped (tau00
+// filled with NaN).
+constexpr int64_t kLsmsXgBytes = 2 * 64 * 64 * 16;
 hipError_t lsms_launch_lu_fp64(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M,
-                               const int64_t* m_off, int64_t slot, double* tau00, int32_t* info,
-                               int keep_info, int32_t nb, hipStream_t s);
+                               const int64_t* m_off, int64_t slot, double* xgb, int64_t xstride,
+                               double* tau00, int32_t* info, int keep_info, int32_t nb, hipStream_t s);
 
 // Persistent fused path: instance order (largest LIZ first), resident grid
 // size, and the fused build + elimination launch.  `counter` must be zero at
-// launch; slot is the per-workgroup matrix slot in complex elements.
+// launch; slot is the per-workgroup slot in complex elements, the matrix
+// first and (xoff > 0) the two 64 x 64 blocks xoff elements in.
 hipError_t lsms_launch_lpt_order(const lsms_prob_dev& p, int32_t* order, hipStream_t s);
 hipError_t lsms_persistent_grid(const lsms_prob_dev& p, int device, int* grid);
 hipError_t lsms_launch_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order,
-                                  int32_t* counter, double* work, int64_t slot, int grid, double* tau00,
-                                  int32_t* info, int32_t nb, hipStream_t s);
+                                  int32_t* counter, double* work, int64_t slot, int64_t xoff, int grid,
+                                  double* tau00, int32_t* info, int32_t nb, hipStream_t s);
 hipError_t lsms_prepare_kernels();
 
 // Precision form (FP32 factorisation + FP64 refinement).  extra bytes per

@@ -21,8 +21,9 @@ namespace lsms {
 
 constexpr int kLuThreads = 512;
 constexpr int kLuWaves = kLuThreads / 64;
-constexpr int kNB = 64;   // maximum panel width
-constexpr int kSW = 64;   // trailing-update strip width (columns)
+constexpr int kNB = 64;         // triangular blocks and LDS tiles
+constexpr int kSW = 64;         // trailing-update strip width (columns)
+constexpr int kPanelMax = 128;  // maximum panel width (two triangular blocks)
 constexpr int kMaxKK = 25;
 constexpr int kMaxWL = 8;
 
@@ -59,13 +60,14 @@ struct LuSmem {
   typedef typename Prec<R>::C C;
   C X[kNB][kNB];    // inverse of a triangular block
   C U[kNB][kSW];    // U12 strip; block staging; Gauss-Jordan workspace at the end
+                    // (X and U together: the 128-row U12 strip of a wide panel)
   C rowP[kMaxWL];   // pivot row of a leaf step
   C rowJ[kMaxWL];
   zd tz[kMaxKK];
   zd pinv;
   R redv[kLuWaves];
   int redi[kLuWaves];
-  int ipiv[kNB];
+  int ipiv[kPanelMax];
   int lrow[2 * kMaxWL];  // rows touched by a leaf's interchanges
   int lsrc[2 * kMaxWL];  // lrow[q] receives the old content of lrow[lsrc[q]]
   int lcnt;
@@ -82,6 +84,14 @@ struct Mat {
   __device__ __forceinline__ int64_t phys(int v) const { return v < Nd ? (int64_t)v + kk : (int64_t)(v - Nd); }
   __device__ __forceinline__ C* ptr(int r, int c) const { return base + phys(r) * N + phys(c); }
 };
+
+// The 128 x kSW view of sh.X and sh.U (contiguous), holding the U12 strip
+// of a panel wider than kNB.
+template <typename R>
+__device__ __forceinline__ typename Prec<R>::C (*ustrip2(LuSmem<R>& sh))[kSW] {
+  static_assert(sizeof(sh.X) == kNB * kSW * sizeof(typename Prec<R>::C), "X rows must match U rows");
+  return reinterpret_cast<typename Prec<R>::C(*)[kSW]>(&sh.X[0][0]);
+}
 
 template <typename R>
 __device__ __forceinline__ bool better(R ob, int oi, R b, int i) {
@@ -367,6 +377,168 @@ __device__ __noinline__ void invert_upper(const Mat<typename Prec<R>::C>& A, int
   __syncthreads();
 }
 
+// U12 of a panel of w in (64, 128] columns for the strip [s0, s0 + sw):
+//   U_a = X_a A(c .. c+63, strip),
+//   U_b = X_b (A(c+64 .. c+w-1, strip) - L(c+64 .. c+w-1, c .. c+63) U_a),
+// X_a and X_b being the inverses of the two unit lower diagonal blocks
+// (64 x 64 each, row-major at xg and xg + 64*64, zero outside their blocks).
+// The result goes to the 128-row view of sh.X and sh.U (rows >= w zero) and,
+// if `store`, to A.  Sixteen output tiles per 64-row half, two per wave.
+template <typename R>
+__device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& A, int c, int w, int s0, int sw,
+                                         bool store, const typename Prec<R>::C* __restrict__ xg, LuSmem<R>& sh) {
+  typedef typename Prec<R>::C C;
+  typedef typename Prec<R>::V4 V4;
+  C(*U2)[kSW] = ustrip2(sh);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int rt = wave & 3, ct0 = 2 * (wave >> 2);
+  const int row = 16 * rt + li;
+  const int wb = w - kNB;  // rows of the second block
+  int64_t bcol[2];
+  bool cok[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int col = 16 * (ct0 + t) + li;
+    cok[t] = col < sw;
+    bcol[t] = A.phys(s0 + min(col, sw - 1));
+  }
+  V4 ar[2], ai[2];
+  // U_a = X_a B, B[k][col] = A(c + k, s0 + col)
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    ar[t] = V4{R(0), R(0), R(0), R(0)};
+    ai[t] = V4{R(0), R(0), R(0), R(0)};
+  }
+  {
+    const int kend = 16 * rt + 16;
+    C bn[2][4];
+    trsm_load_chunk(A, c, kNB, 0, lk, bcol, cok, bn);
+    for (int kc = 0; kc < kend; kc += 16) {
+      C b[2][4], x[4];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[t][j] = bn[t][j];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] = xg[row * kNB + kc + 4 * lk + j];
+      if (kc + 16 < kend) trsm_load_chunk(A, c, kNB, kc + 16, lk, bcol, cok, bn);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          ar[t] = Prec<R>::mfma(x[j].x, b[t][j].x, ar[t]);
+          ar[t] = Prec<R>::mfma(-x[j].y, b[t][j].y, ar[t]);
+          ai[t] = Prec<R>::mfma(x[j].x, b[t][j].y, ai[t]);
+          ai[t] = Prec<R>::mfma(x[j].y, b[t][j].x, ai[t]);
+        }
+    }
+  }
+  __syncthreads();  // earlier readers of the strip are done
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * rt + Prec<R>::drow(r, lk), col = 16 * (ct0 + t) + li;
+      const C u = zmake(ar[t][r], ai[t][r]);
+      U2[i][col] = u;
+      if (store && col < sw) *A.ptr(c + i, s0 + col) = u;
+    }
+  __syncthreads();
+  // T = A(c + 64 + i, strip) - L(c + 64 + i, c .. c+63) U_a, rows i < wb
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * rt + Prec<R>::drow(r, lk);
+      C v;
+      v.x = 0;
+      v.y = 0;
+      if (i < wb && cok[t]) v = A.base[A.phys(c + kNB + i) * A.N + bcol[t]];
+      ar[t][r] = v.x;
+      ai[t][r] = v.y;
+    }
+  {
+    const bool rok = row < wb;
+    const C* lrow = A.base + A.phys(c + kNB + (rok ? row : 0)) * A.N + A.phys(c) + 4 * lk;
+    for (int kc = 0; kc < kNB; kc += 16) {
+      C l[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        C v;
+        v.x = 0;
+        v.y = 0;
+        if (rok) v = lrow[kc + j];
+        l[j] = v;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = kc + 4 * lk + j;
+        const R nx = -l[j].x, ny = -l[j].y;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const C u = U2[k][16 * (ct0 + t) + li];
+          ar[t] = Prec<R>::mfma(nx, u.x, ar[t]);
+          ar[t] = Prec<R>::mfma(l[j].y, u.y, ar[t]);
+          ai[t] = Prec<R>::mfma(nx, u.y, ai[t]);
+          ai[t] = Prec<R>::mfma(ny, u.x, ai[t]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * rt + Prec<R>::drow(r, lk), col = 16 * (ct0 + t) + li;
+      U2[kNB + i][col] = zmake(ar[t][r], ai[t][r]);
+    }
+  __syncthreads();
+  // U_b = X_b T
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    ar[t] = V4{R(0), R(0), R(0), R(0)};
+    ai[t] = V4{R(0), R(0), R(0), R(0)};
+  }
+  {
+    const int kend = min(wb, 16 * rt + 16);
+    const C* xb = xg + kNB * kNB;
+    for (int kc = 0; kc < kend; kc += 16) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = kc + 4 * lk + j;
+        const C x = xb[row * kNB + k];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const C b = U2[kNB + k][16 * (ct0 + t) + li];
+          ar[t] = Prec<R>::mfma(x.x, b.x, ar[t]);
+          ar[t] = Prec<R>::mfma(-x.y, b.y, ar[t]);
+          ai[t] = Prec<R>::mfma(x.x, b.y, ai[t]);
+          ai[t] = Prec<R>::mfma(x.y, b.x, ai[t]);
+        }
+      }
+    }
+  }
+  __syncthreads();  // T fully read
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * rt + Prec<R>::drow(r, lk), col = 16 * (ct0 + t) + li;
+      const C u = zmake(ar[t][r], ai[t][r]);
+      U2[kNB + i][col] = u;
+      if (store && i < wb && col < sw) *A.ptr(c + kNB + i, s0 + col) = u;
+    }
+  __syncthreads();
+}
+
+// Copies sh.X (after invert_unit_lower) to the 64 x 64 row-major block at dst.
+template <typename R>
+__device__ __forceinline__ void save_x(const LuSmem<R>& sh, typename Prec<R>::C* __restrict__ dst) {
+  for (int q = threadIdx.x; q < kNB * kNB; q += kLuThreads) dst[q] = sh.X[q / kNB][q % kNB];
+  __syncthreads();
+}
+
 // Loads the B operands of one 16-deep chunk of trsm_strip: lane (li, lk)
 // takes rows k = kc + 4 lk + j (j < 4) of its two columns, zero outside
 // k < s and the strip.
@@ -468,7 +640,7 @@ __device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& A, int r
 // k >= s.
 template <typename R, int NCS>
 __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
-                                            const LuSmem<R>& sh) {
+                                            const typename Prec<R>::C (*Ub)[kSW]) {
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -539,11 +711,11 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int k = (kc + 4 * lq + j) & (kNB - 1);
+        const int k = (kc + 4 * lq + j) & (kPanelMax - 1);
         const R nx = -a[j].x, ny = -a[j].y;
 #pragma unroll
         for (int cs = 0; cs < NCS; ++cs) {
-          const C b = sh.U[k][16 * cs + li];
+          const C b = Ub[k][16 * cs + li];
           accr[cs] = Prec<R>::mfma(nx, b.x, accr[cs]);
           accr[cs] = Prec<R>::mfma(a[j].y, b.y, accr[cs]);
           acci[cs] = Prec<R>::mfma(nx, b.y, acci[cs]);
@@ -563,15 +735,112 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
   }
 }
 
-// A(v, s0 + j) -= sum_{k < s} A(v, r0 + k) U[k][j] for v in [r0 + s, N),
-// j < sw <= 64, with U = sh.U.
+// As update_rows for narrow strips (the sibling updates of the recursive
+// panel, reductions of at most 32 there): each wave takes RB row blocks at a
+// time (row blocks rb + 16 kLuWaves i, i < RB) and issues all their loads
+// together, so that a narrow update is not bound by one memory latency per
+// 16 rows; lane (li, lq) supplies k = kc + lq + 4 j at step j, so that a
+// reduction of s needs only ceil(s / 4) MFMA steps.
+template <typename R, int NCS, int RB>
+__device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0,
+                                                  int sw, const typename Prec<R>::C (*Ub)[kSW]) {
+  typedef typename Prec<R>::C C;
+  typedef typename Prec<R>::V4 V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int N = (int)A.N;
+  const int rstart = r0 + s;
+  const int64_t pr0 = A.phys(r0) + 4 * lq;
+  constexpr int kStep = 16 * kLuWaves;
+  int64_t ccol[NCS];
+  bool cok[NCS];
+#pragma unroll
+  for (int cs = 0; cs < NCS; ++cs) {
+    cok[cs] = 16 * cs + li < sw;
+    ccol[cs] = A.phys(s0 + min(16 * cs + li, sw - 1));
+  }
+  for (int rb = rstart + 16 * wave; rb < N; rb += RB * kStep) {
+    V4 accr[RB][NCS], acci[RB][NCS];
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int v = rb + b * kStep + Prec<R>::drow(r, lq);
+        const C* crow = A.base + A.phys(v < N ? v : rstart) * A.N;
+#pragma unroll
+        for (int cs = 0; cs < NCS; ++cs) {
+          C cv;
+          cv.x = 0;
+          cv.y = 0;
+          if (v < N && cok[cs]) cv = crow[ccol[cs]];
+          accr[b][cs][r] = cv.x;
+          acci[b][cs][r] = cv.y;
+        }
+      }
+    const C* arow[RB];
+    bool rok[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int va = rb + b * kStep + li;
+      rok[b] = va < N;
+      arow[b] = A.base + A.phys(rok[b] ? va : rstart) * A.N + pr0;
+    }
+    for (int kc = 0; kc < s; kc += 16) {
+      // k = kc + lq + 4 j here, so that MFMA steps past the end of a short
+      // reduction are skipped
+      const int nj = min(4, (s - kc + 3) >> 2);
+      C a[RB][4];
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          C av;
+          av.x = 0;
+          av.y = 0;
+          if (rok[b] && kc + lq + 4 * j < s) av = arow[b][kc + 4 * j - 3 * lq];
+          a[b][j] = av;
+        }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j >= nj) break;
+        const int k = (kc + lq + 4 * j) & (kPanelMax - 1);
+#pragma unroll
+        for (int cs = 0; cs < NCS; ++cs) {
+          const C u = Ub[k][16 * cs + li];
+#pragma unroll
+          for (int b = 0; b < RB; ++b) {
+            const R nx = -a[b][j].x, ny = -a[b][j].y;
+            accr[b][cs] = Prec<R>::mfma(nx, u.x, accr[b][cs]);
+            accr[b][cs] = Prec<R>::mfma(a[b][j].y, u.y, accr[b][cs]);
+            acci[b][cs] = Prec<R>::mfma(nx, u.y, acci[b][cs]);
+            acci[b][cs] = Prec<R>::mfma(ny, u.x, acci[b][cs]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int v = rb + b * kStep + Prec<R>::drow(r, lq);
+        if (v >= N) continue;
+        C* crow = A.base + A.phys(v) * A.N;
+#pragma unroll
+        for (int cs = 0; cs < NCS; ++cs)
+          if (cok[cs]) crow[ccol[cs]] = zmake(accr[b][cs][r], acci[b][cs][r]);
+      }
+  }
+}
+
+// A(v, s0 + j) -= sum_{k < s} A(v, r0 + k) Ub[k][j] for v in [r0 + s, N),
+// j < sw <= 64, s <= 128 (Ub in LDS, rows k >= s zero).
 template <typename R>
 __device__ __noinline__ void update_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
-                                          const LuSmem<R>& sh) {
-  if (sw > 48) update_rows<R, 4>(A, r0, s, s0, sw, sh);
-  else if (sw > 32) update_rows<R, 3>(A, r0, s, s0, sw, sh);
-  else if (sw > 16) update_rows<R, 2>(A, r0, s, s0, sw, sh);
-  else update_rows<R, 1>(A, r0, s, s0, sw, sh);
+                                          const typename Prec<R>::C (*Ub)[kSW]) {
+  if (sw > 48) update_rows<R, 4>(A, r0, s, s0, sw, Ub);
+  else if (sw > 32) update_rows<R, 3>(A, r0, s, s0, sw, Ub);
+  else if (sw > 16) update_rows_multi<R, 2, 2>(A, r0, s, s0, sw, Ub);
+  else update_rows_multi<R, 1, 4>(A, r0, s, s0, sw, Ub);
 }
 
 // Row interchanges of the panel [c, c + w) applied to the columns [c0, c1).
@@ -613,22 +882,25 @@ __device__ void panel_factor(const Mat<typename Prec<R>::C>& A, int c, int w, in
     if (tw > 0) {
       invert_unit_lower<R>(A, start, s, sh);
       trsm_strip<R>(A, start, s, t0, tw, store_u, sh);
-      update_strip<R>(A, start, s, t0, tw, sh);
+      update_strip<R>(A, start, s, t0, tw, sh.U);
       __syncthreads();
     }
   }
 }
 
 // Blocked right-looking elimination of the columns [c_begin, ncols) of the
-// N x N matrix: panels of nb columns with pivot rows below plim, interchanges
-// applied to every column right of the panel (the columns left of a panel
-// keep the row order of their own elimination step), the U part written back
-// when store_u, and the panel pivots stored at ipiv_out[column] (if non-null).
-// Ends after a barrier.
+// N x N matrix: panels of nb <= 128 columns with pivot rows below plim,
+// interchanges applied to every column right of the panel (the columns left
+// of a panel keep the row order of their own elimination step), the U part
+// written back when store_u, and the panel pivots stored at ipiv_out[column]
+// (if non-null).  A panel wider than 64 needs xg, room for two 64 x 64
+// blocks (the inverses of its diagonal blocks); without xg panels are at most
+// 64 wide.  Ends after a barrier.
 template <typename R, int kR, int kWL>
 __device__ void eliminate(const Mat<typename Prec<R>::C>& A, int c_begin, int ncols, int plim, int nb,
-                          bool store_u, int32_t* ipiv_out, LuSmem<R>& sh) {
+                          bool store_u, int32_t* ipiv_out, typename Prec<R>::C* xg, LuSmem<R>& sh) {
   const int N = (int)A.N;
+  if (!xg) nb = min(nb, kNB);
   for (int c = c_begin; c < ncols; c += nb) {
     const int w = min(nb, ncols - c);
     panel_factor<R, kR, kWL>(A, c, w, plim, store_u, sh);
@@ -636,11 +908,23 @@ __device__ void eliminate(const Mat<typename Prec<R>::C>& A, int c_begin, int nc
     if (ipiv_out && threadIdx.x < w) ipiv_out[c + threadIdx.x] = sh.ipiv[threadIdx.x];
     __syncthreads();
     if (c + w < N) {
-      invert_unit_lower<R>(A, c, w, sh);
-      for (int s0 = c + w; s0 < N; s0 += kSW) {
-        const int sw = min(kSW, N - s0);
-        trsm_strip<R>(A, c, w, s0, sw, store_u, sh);
-        update_strip<R>(A, c, w, s0, sw, sh);
+      if (w <= kNB) {
+        invert_unit_lower<R>(A, c, w, sh);
+        for (int s0 = c + w; s0 < N; s0 += kSW) {
+          const int sw = min(kSW, N - s0);
+          trsm_strip<R>(A, c, w, s0, sw, store_u, sh);
+          update_strip<R>(A, c, w, s0, sw, sh.U);
+        }
+      } else {
+        invert_unit_lower<R>(A, c, kNB, sh);
+        save_x<R>(sh, xg);
+        invert_unit_lower<R>(A, c + kNB, w - kNB, sh);
+        save_x<R>(sh, xg + kNB * kNB);
+        for (int s0 = c + w; s0 < N; s0 += kSW) {
+          const int sw = min(kSW, N - s0);
+          trsm2_strip<R>(A, c, w, s0, sw, store_u, xg, sh);
+          update_strip<R>(A, c, w, s0, sw, ustrip2(sh));
+        }
       }
     }
     __syncthreads();

@@ -46,7 +46,7 @@ typedef LuSmem<double> LuSmemD;
 // Eliminates one instance whose matrix is at `base` and writes its tau00 and
 // info.  All threads of the workgroup call it; it ends after a barrier.
 template <int kR, int kWL>
-__device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, double* __restrict__ tau00,
+__device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, double* __restrict__ tau00,
                             int32_t* __restrict__ info, int nb, LuSmemD& sh) {
   const int tid = threadIdx.x;
   const int kk = p.kk;
@@ -63,7 +63,7 @@ __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, double* 
     sh.bad = 0;
   }
   __syncthreads();
-  eliminate<double, kR, kWL>(A, 0, Nd, Nd, nb, false, nullptr, sh);
+  eliminate<double, kR, kWL>(A, 0, Nd, Nd, nb, false, nullptr, xg, sh);
 
   // Gauss-Jordan inverse of S_A (kk x kk, physical rows/cols 0..kk-1) in sh.U
   zd(*G)[2 * kMaxKK] = reinterpret_cast<zd(*)[2 * kMaxKK]>(&sh.U[0][0]);
@@ -140,6 +140,7 @@ __device__ __forceinline__ void fill_nan(const lsms_prob_dev& p, int inst, doubl
 template <int kR, int kWL>
 __global__ __launch_bounds__(kThreads) void lu_schur_fp64_kernel(lsms_prob_dev p, int i0, double* __restrict__ Mb,
                                                                 const int64_t* __restrict__ m_off, int64_t slot,
+                                                                double* __restrict__ xgb, int64_t xstride,
                                                                 double* __restrict__ tau00,
                                                                 int32_t* __restrict__ info, int keep_info,
                                                                 int nb) {
@@ -153,7 +154,8 @@ __global__ __launch_bounds__(kThreads) void lu_schur_fp64_kernel(lsms_prob_dev p
     return;
   }
   zd* base = reinterpret_cast<zd*>(Mb) + (m_off ? m_off[inst] : (int64_t)(inst - i0) * slot);
-  lu_instance<kR, kWL>(p, inst, base, tau00, info, nb, sh);
+  zd* xg = xgb ? reinterpret_cast<zd*>(xgb) + (int64_t)(inst - i0) * xstride : nullptr;
+  lu_instance<kR, kWL>(p, inst, base, xg, tau00, info, nb, sh);
 }
 
 // Next instance index from the device counter, the same for every thread of
@@ -183,13 +185,14 @@ __global__ __launch_bounds__(kThreads) void tau00_persistent_kernel(lsms_prob_de
                                                                    const int32_t* __restrict__ order, int n,
                                                                    int32_t* __restrict__ counter,
                                                                    double* __restrict__ work, int64_t slot,
-                                                                   double* __restrict__ tau00,
+                                                                   int64_t xoff, double* __restrict__ tau00,
                                                                    int32_t* __restrict__ info, int nb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
   BuildSmem& sb = *reinterpret_cast<BuildSmem*>(smem_raw);  // used before sh, never at the same time
   __shared__ int next;
   zd* M = reinterpret_cast<zd*>(work) + (int64_t)blockIdx.x * slot;
+  zd* xg = xoff ? M + xoff : nullptr;
   __syncthreads();
   int k = pop_instance(counter, &next);
   while (k < n) {
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void tau00_persistent_kernel(lsms_prob_de
       __syncthreads();
     }
     if (status == 0) {
-      lu_instance<kR, kWL>(p, inst, M, tau00, info, nb, sh);
+      lu_instance<kR, kWL>(p, inst, M, xg, tau00, info, nb, sh);
     } else {
       fill_nan(p, inst, tau00);
       if (threadIdx.x == 0) info[inst] = status;
@@ -238,6 +241,7 @@ struct MixedBufs {
   zf* z;          // N x kp FP32 right-hand sides / corrections, internal rows
   zd* Y;          // N x kp FP64 solution, internal rows
   int32_t* ipiv;  // N pivot rows
+  zd* xg;         // two 64 x 64 blocks (FP64, or FP32 in the first half) for wide panels
   int kp;         // 16 or 32: kk rounded up to a multiple of 16
 };
 
@@ -375,14 +379,17 @@ __device__ void rhs_update(const Mat<zf>& A, const MixedBufs& b, int r0, int s, 
 
 // z := A32^{-1} z with the panel structure of the factorisation: forward with
 // the unit lower factor (each panel's interchanges applied just before its
-// columns are used, since earlier columns of L keep their own row order),
-// then backward with the upper factor.
+// columns are used, since earlier columns of L keep their own row order; a
+// panel wider than 64 is then taken in 64-column blocks, its own L being in
+// the panel's final row order), then backward with the upper factor in
+// 64-row blocks.
 __device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, MixedSmem& ms) {
   typedef Prec<float>::V4 V4;
   LuSmem<float>& sh = ms.f;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int N = (int)A.N, Nd = A.Nd, nct = b.kp / 16;
+  if (!b.xg) nb = min(nb, kNB);
   // panels: [0, Nd) in steps of nb, then [Nd, N)
   const int npan = (Nd + nb - 1) / nb + 1;
   for (int pi = 0; pi < npan; ++pi) {
@@ -402,13 +409,17 @@ __device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, MixedSme
       }
     }
     __syncthreads();
-    invert_unit_lower<float>(A, c, w, sh);
-    tri_apply(b, c, w, sh);
-    if (c + w < N) rhs_update(A, b, c, w, c + w, sh);
+    for (int c2 = c; c2 < c + w; c2 += kNB) {
+      const int w2 = min(kNB, c + w - c2);
+      invert_unit_lower<float>(A, c2, w2, sh);
+      tri_apply(b, c2, w2, sh);
+      if (c2 + w2 < N) rhs_update(A, b, c2, w2, c2 + w2, sh);
+    }
   }
-  for (int pi = npan - 1; pi >= 0; --pi) {
-    const int c = pi + 1 < npan ? pi * nb : Nd;
-    const int w = pi + 1 < npan ? min(nb, Nd - c) : N - Nd;
+  const int nblk = (Nd + kNB - 1) / kNB + 1;
+  for (int pi = nblk - 1; pi >= 0; --pi) {
+    const int c = pi + 1 < nblk ? pi * kNB : Nd;
+    const int w = pi + 1 < nblk ? min(kNB, Nd - c) : N - Nd;
     if (w <= 0) continue;
     // part = U(c .. c+w, c+w .. N) z(c+w .. N), split over k between wave halves
     const int ntile = 4 * nct, nsplit = kLuWaves / ntile;
@@ -580,8 +591,8 @@ __device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd
   }
   if (tid == 0) sh.info = 0;
   __syncthreads();
-  eliminate<float, kR, kWL>(F, 0, Nd, Nd, nb, true, b.ipiv, sh);
-  eliminate<float, kR, kWL>(F, Nd, N, N, nb, true, b.ipiv, sh);
+  eliminate<float, kR, kWL>(F, 0, Nd, Nd, nb, true, b.ipiv, reinterpret_cast<zf*>(b.xg), sh);
+  eliminate<float, kR, kWL>(F, Nd, N, N, nb, true, b.ipiv, reinterpret_cast<zf*>(b.xg), sh);
   bool ok = __builtin_amdgcn_readfirstlane(sh.info) == 0;
   if (ok) {
     for (int q = tid; q < N * b.kp; q += kLuThreads) {
@@ -658,7 +669,7 @@ __device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd
     if (tid == 0) info[inst] = ms.flag ? -1 : 0;
     __syncthreads();
   } else {
-    lu_instance<kR, kWL>(p, inst, A64, tau00, info, nb, *reinterpret_cast<LuSmemD*>(smem));
+    lu_instance<kR, kWL>(p, inst, A64, b.xg, tau00, info, nb, *reinterpret_cast<LuSmemD*>(smem));
     if (tid == 0 && info[inst] == 0) info[inst] = kInfoIrFallback;
     __syncthreads();
   }
@@ -671,15 +682,16 @@ size_t mixed_smem_bytes() {
   return b > sizeof(BuildSmem) ? b : sizeof(BuildSmem);
 }
 
-// Per-instance buffers of the precision form inside a slot of `bytes` bytes
-// laid out as [FP32 matrix | z | Y | pivots], each 256-byte aligned, for
+// Per-instance buffers of the precision form laid out as
+// [FP32 matrix | z | Y | pivots | X blocks], each 256-byte aligned, for
 // matrices up to nmax.
+constexpr int64_t kXgBytes = 2 * kNB * kNB * 16;
 __host__ __device__ inline int64_t mixed_extra_bytes(int64_t nmax, int kp) {
   const int64_t a = ((nmax * nmax * 8) + 255) & ~(int64_t)255;
   const int64_t z = ((nmax * kp * 8) + 255) & ~(int64_t)255;
   const int64_t y = ((nmax * kp * 16) + 255) & ~(int64_t)255;
   const int64_t pv = ((nmax * 4) + 255) & ~(int64_t)255;
-  return a + z + y + pv;
+  return a + z + y + pv + kXgBytes;
 }
 
 __device__ inline MixedBufs mixed_bufs(unsigned char* base, int64_t nmax, int kp) {
@@ -691,6 +703,7 @@ __device__ inline MixedBufs mixed_bufs(unsigned char* base, int64_t nmax, int kp
   b.z = reinterpret_cast<zf*>(base + a);
   b.Y = reinterpret_cast<zd*>(base + a + z);
   b.ipiv = reinterpret_cast<int32_t*>(base + a + z + y);
+  b.xg = reinterpret_cast<zd*>(base + a + z + y + (((nmax * 4) + 255) & ~(int64_t)255));
   b.kp = kp;
   return b;
 }
@@ -756,20 +769,21 @@ __global__ __launch_bounds__(kThreads) void tau00_mixed_persistent_kernel(
 
 template <int kR, int kWL>
 hipError_t launch(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, const int64_t* m_off, int64_t slot,
-                  double* tau00, int32_t* info, int keep_info, int32_t nb, hipStream_t s) {
+                  double* xgb, int64_t xstride, double* tau00, int32_t* info, int keep_info, int32_t nb,
+                  hipStream_t s) {
   const size_t smem = sizeof(LuSmemD);
   hipLaunchKernelGGL((lu_schur_fp64_kernel<kR, kWL>), dim3(n), dim3(kThreads), smem, s, p, i0, M, m_off, slot,
-                     tau00, info, keep_info, nb);
+                     xgb, xstride, tau00, info, keep_info, nb);
   return hipGetLastError();
 }
 
 template <int kR, int kWL>
 hipError_t launch_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order, int32_t n,
-                             int32_t* counter, double* work, int64_t slot, int grid, double* tau00, int32_t* info,
-                             int32_t nb, hipStream_t s) {
+                             int32_t* counter, double* work, int64_t slot, int64_t xoff, int grid, double* tau00,
+                             int32_t* info, int32_t nb, hipStream_t s) {
   const size_t smem = sizeof(LuSmemD) > sizeof(BuildSmem) ? sizeof(LuSmemD) : sizeof(BuildSmem);
   hipLaunchKernelGGL((tau00_persistent_kernel<kR, kWL>), dim3(grid), dim3(kThreads), smem, s, p, g, order, n,
-                     counter, work, slot, tau00, info, nb);
+                     counter, work, slot, xoff, tau00, info, nb);
   return hipGetLastError();
 }
 
@@ -823,12 +837,13 @@ __global__ __launch_bounds__(1024) void lpt_order_kernel(const int64_t* __restri
 // Leaf rows per thread kR bounds N <= 512 kR: kR = 5 covers N <= 2560 and
 // kR = 8 covers N <= 4096; leaves are 4 columns wide.
 hipError_t lsms_launch_lu_fp64(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, const int64_t* m_off,
-                               int64_t slot, double* tau00, int32_t* info, int keep_info, int32_t nb,
-                               hipStream_t s) {
+                               int64_t slot, double* xgb, int64_t xstride, double* tau00, int32_t* info,
+                               int keep_info, int32_t nb, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t nmax = (int64_t)p.kk * p.max_liz;
-  if (nmax <= kThreads * 5) return launch<5, 4>(p, i0, n, M, m_off, slot, tau00, info, keep_info, nb, s);
-  return launch<8, 4>(p, i0, n, M, m_off, slot, tau00, info, keep_info, nb, s);
+  if (nmax <= kThreads * 5)
+    return launch<5, 4>(p, i0, n, M, m_off, slot, xgb, xstride, tau00, info, keep_info, nb, s);
+  return launch<8, 4>(p, i0, n, M, m_off, slot, xgb, xstride, tau00, info, keep_info, nb, s);
 }
 
 hipError_t lsms_launch_lpt_order(const lsms_prob_dev& p, int32_t* order, hipStream_t s) {
@@ -857,13 +872,13 @@ hipError_t lsms_persistent_grid(const lsms_prob_dev& p, int device, int* grid) {
 }
 
 hipError_t lsms_launch_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order,
-                                  int32_t* counter, double* work, int64_t slot, int grid, double* tau00,
-                                  int32_t* info, int32_t nb, hipStream_t s) {
+                                  int32_t* counter, double* work, int64_t slot, int64_t xoff, int grid,
+                                  double* tau00, int32_t* info, int32_t nb, hipStream_t s) {
   if (p.n_inst <= 0) return hipSuccess;
   const int64_t nmax = (int64_t)p.kk * p.max_liz;
   if (nmax <= kThreads * 5)
-    return launch_persistent<5, 4>(p, g, order, p.n_inst, counter, work, slot, grid, tau00, info, nb, s);
-  return launch_persistent<8, 4>(p, g, order, p.n_inst, counter, work, slot, grid, tau00, info, nb, s);
+    return launch_persistent<5, 4>(p, g, order, p.n_inst, counter, work, slot, xoff, grid, tau00, info, nb, s);
+  return launch_persistent<8, 4>(p, g, order, p.n_inst, counter, work, slot, xoff, grid, tau00, info, nb, s);
 }
 
 // Dynamic LDS limits of every elimination kernel; called once per device

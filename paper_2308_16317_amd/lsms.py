@@ -267,7 +267,7 @@ def autotune(h: Handle, prob: Problem, work: torch.Tensor, opts: Opts | None = N
     _check(lib().lsms_autotune(h.ptr, ctypes.byref(ps), ctypes.byref(o), _ptr(tau), _ptr(info), _ptr(work),
                                work.numel() * work.element_size(), _stream(), ctypes.byref(best), ms),
            "lsms_autotune")
-    return int(best.value), dict(zip((16, 32, 48, 64), list(ms)))
+    return int(best.value), dict(zip((32, 64, 96, 128), list(ms)))
 
 
 def set_tuned_nb(h: Handle, n: int, nb: int):

@@ -145,7 +145,7 @@ def test_tau00_batched_config1_all(P, h):
     assert err.max() <= TOL_TAU
 
 
-@pytest.mark.parametrize("nb,chunk", [(0, 0), (16, 7), (32, 50), (48, 1)])
+@pytest.mark.parametrize("nb,chunk", [(0, 0), (16, 7), (32, 50), (48, 1), (96, 5), (128, 0)])
 def test_tau00_solve_config1_nb_chunk(P, h, nb, chunk):
     w = inputs.config1()
     ref, _ = oracle_tau_cached("cfg1", w)
@@ -183,11 +183,12 @@ def test_tau00_config2_full_size_sample(P, h):
     idx = [0 * 32 + 0, 0 * 32 + 16, 0 * 32 + 31, 77 * 32 + 1, 200 * 32 + 30]
     w = inputs.subset(w2, idx)
     ref, rinfo = _oracle_tau(w)
-    tau, info = _solve(P, h, w)
-    assert np.all(info == 0) and np.all(rinfo == 0)
-    err = rel_f(tau, ref)
-    print("config2 sample rel_F", err)
-    assert err.max() <= TOL_TAU
+    for nb in (0, 128):
+        tau, info = _solve(P, h, w, nb=nb)
+        assert np.all(info == 0) and np.all(rinfo == 0)
+        err = rel_f(tau, ref)
+        print("config2 sample rel_F", nb, err)
+        assert err.max() <= TOL_TAU
     # tau00 is complex symmetric
     sym = np.abs(tau - tau.transpose(0, 2, 1)).max(axis=(1, 2)) / np.abs(tau).max(axis=(1, 2))
     assert sym.max() <= TOL_TAU
@@ -288,10 +289,11 @@ def test_persistent_matches_oracle(P, h, which):
     else:
         w = inputs.subset(inputs.config4(n_inst=1024), [5, 6, 7, 8, 700])
         ref, rinfo = _oracle_tau(w)
-    tau, info = _solve_flags(P, h, w, P.PERSISTENT)
-    assert np.all(info == 0) and np.all(rinfo == 0)
-    err = rel_f(tau, ref)
-    assert err.max() <= TOL_TAU, err.max()
+    for nb in (0, 128):
+        tau, info = _solve_flags(P, h, w, P.PERSISTENT, nb=nb)
+        assert np.all(info == 0) and np.all(rinfo == 0)
+        err = rel_f(tau, ref)
+        assert err.max() <= TOL_TAU, (nb, err.max())
 
 
 def test_persistent_error_codes(P, h):
@@ -352,7 +354,7 @@ def test_autotune(P, h):
     opts = P.Opts(0, 0, 0, P.PERSISTENT)
     work = torch.empty(P.workspace_size(h, prob, 0, opts), dtype=torch.uint8, device="cuda")
     best, ms = P.autotune(h, prob, work, opts)
-    assert best in (16, 32, 48, 64) and all(v > 0 for v in ms.values())
+    assert best in (32, 64, 96, 128) and all(v > 0 for v in ms.values())
     tau, info = P.tau00_solve(h, prob, work, opts)
     torch.cuda.synchronize()
     assert np.all(info.cpu().numpy() == 0)

@@ -85,7 +85,7 @@ def test_ir_config1_all(P, h, flags):
     assert (info == 0).mean() >= 0.9
 
 
-@pytest.mark.parametrize("nb,chunk", [(16, 7), (32, 50), (48, 1)])
+@pytest.mark.parametrize("nb,chunk", [(16, 7), (32, 50), (48, 1), (96, 3), (128, 0)])
 def test_ir_panel_widths(P, h, nb, chunk):
     w = inputs.subset(inputs.config1(), np.arange(0, 128, 5))
     ref, _ = oracle.tau00_workload(w)
@@ -116,11 +116,12 @@ def test_ir_config2_full_size_sample(P, h):
     w2 = inputs.config2()
     w = inputs.subset(w2, [0, 16, 31, 77 * 32 + 1, 200 * 32 + 30])
     ref, _ = oracle.tau00_workload(w)
-    tau, info = _solve(P, h, w, flags=P.PERSISTENT)
-    err = rel_f(tau, ref)
-    print("config2 IR rel_F", err, "info", info)
-    assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK))
-    assert err.max() <= TOL_IR
+    for nb in (0, 128):
+        tau, info = _solve(P, h, w, flags=P.PERSISTENT, nb=nb)
+        err = rel_f(tau, ref)
+        print("config2 IR rel_F", nb, err, "info", info)
+        assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK))
+        assert err.max() <= TOL_IR
 
 
 def test_ir_fallback_path(P, h):
