@@ -6,11 +6,13 @@ supercells (positions, species, vacancies, positional noise), the list of
 contour and the square-well phase shifts that stand in for real muffin-tin
 potentials.  It contains no step of the path itself (no LIZ extraction, no
 t-matrix, no structure constants, no factorisation); both the product path
-and the oracle take their inputs from here.
+and the oracle take their inputs from here.  The learned form's initial
+network parameters are seeded inputs too (`mlp_init`).
 """
 
 from .workloads import (  # noqa: F401
     A_LAT,
+    MLP_LAYERS,
     R_MT,
     V0_SPECIES,
     Workload,
@@ -20,6 +22,7 @@ from .workloads import (  # noqa: F401
     config4,
     contour_energies,
     fcc_supercell,
+    mlp_init,
     phase_shift_table,
     square_well_delta,
     subset,

@@ -183,3 +183,21 @@ def subset(w: Workload, idx) -> Workload:
     """The same system restricted to the instances `idx`."""
     idx = np.asarray(idx)
     return dataclasses.replace(w, centre=w.centre[idx], rc=w.rc[idx], e_idx=w.e_idx[idx])
+
+
+# layer widths of the learned form's network (18 features -> 1024 outputs)
+MLP_LAYERS = (18, 256, 256, 256, 1024)
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Initial parameters of the learned form's network as one flat float64
+    vector [W1 b1 W2 b2 W3 b3 W4 b4], W_l of shape [out][in] drawn from
+    N(0, 1/in) (scaled by 0.1 for the output layer), biases zero."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[5])
+    parts = []
+    dims = list(zip(MLP_LAYERS[:-1], MLP_LAYERS[1:]))
+    for l, (i, o) in enumerate(dims):
+        scale = (0.1 if l + 1 == len(dims) else 1.0) / np.sqrt(i)
+        parts.append(rng.standard_normal(o * i) * scale)
+        parts.append(np.zeros(o))
+    return np.concatenate(parts)
