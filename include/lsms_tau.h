@@ -59,6 +59,15 @@ extern "C" {
                                mixed-precision scheme (Carson and Higham, SIAM J. Sci.
                                Comput. 40 (2018) A817); tau00_solve only */
 
+/* info value of tau00_gmres when GMRES did not reach its tolerance and the
+ * instance was solved by the FP64 path */
+#define LSMS_INFO_LU_FALLBACK 512
+
+/* learned form: parameters of the seed network and floats of activations
+ * kept per sample by lsms_mlp_forward */
+#define LSMS_MLP_PARAMS 399616
+#define LSMS_MLP_ACT 2560
+
 /* info bit set by LSMS_PREC_FP32_IR when the refinement did not reach tol
  * within max_refine steps (or the FP32 factorisation met an exactly zero
  * pivot) and the instance was recomputed by the FP64 path */
@@ -206,6 +215,98 @@ int lsms_autotune(lsms_handle_t h, const lsms_problem *p, const lsms_opts *opts,
 /* Sets the handle's panel width for matrices of size n (the bucket of
  * lsms_autotune), e.g. from a cached tuning result. */
 int lsms_set_tuned_nb(lsms_handle_t h, int32_t n, int32_t nb);
+
+/* ---------------------------------------------------------------------------
+ * Learned form.  The paper solves every instance directly (Sec. 3.2); this
+ * form adds a small network that maps an instance's local environment and
+ * energy to an approximation of [M^{-1}]_{00}, which seeds an iterative block
+ * GMRES solve of the same system; the direct FP64 path is the fallback.
+ *
+ * Network: 18 -> 256 -> 256 -> 256 -> 1024, SiLU after the hidden layers,
+ * linear output.  Parameters: one flat float array of LSMS_MLP_PARAMS
+ * entries [W1 b1 W2 b2 W3 b3 W4 b4], W_l row-major [out][in]; the products
+ * use a bf16 copy of it (uint16 bit patterns, same layout) and round the
+ * layer inputs to bf16, with FP32 accumulation.  Outputs per sample: 512
+ * floats for tau00 and 512 for [M^{-1}]_{00} (kk = 16, column-major,
+ * interleaved re/im), both normalised (see lsms_mlp_seed).
+ * -------------------------------------------------------------------------*/
+
+/* Features of each instance (device [n_inst][18] floats): the centre's
+ * species one-hot (species 0 and 1), for the first seven fcc neighbour
+ * shells (ideal radii a_lat*sqrt(k/2)) the fraction of the shell's sites of
+ * species 0 and 1 (each LIZ site counted in the shell nearest in radius;
+ * sites nearest to the eighth shell are not counted), Re E, Im E.  The
+ * problem's LIZ arrays as for tau00_solve (lsms_build_liz output). */
+int lsms_mlp_features(lsms_handle_t h, const lsms_problem *p, double a_lat, float *feat, void *stream);
+
+/* w_bf16 (device, LSMS_MLP_PARAMS uint16) := bf16(params), round to nearest
+ * even. */
+int lsms_mlp_cast(lsms_handle_t h, const float *params, uint16_t *w_bf16, void *stream);
+
+/* Forward pass over n samples: feat device [n][18]; act device [n][LSMS_MLP_ACT]
+ * (pre-activations and activations kept for the backward pass, outputs in
+ * the last 1024 floats of each row); out device [n][1024] or NULL. */
+int lsms_mlp_forward(lsms_handle_t h, const float *params, const uint16_t *w_bf16, const float *feat, int32_t n,
+                     float *out, float *act, void *stream);
+
+/* Backward pass: grad (device, LSMS_MLP_PARAMS floats, overwritten) of
+ * sum(dout * out) for the forward that filled act; the bf16 rounding of the
+ * forward is taken as the identity.  work: device [n][1280] floats. */
+int lsms_mlp_backward(lsms_handle_t h, const uint16_t *w_bf16, const float *feat, const float *act,
+                      const float *dout, int32_t n, float *grad, float *work, void *stream);
+
+/* Mean squared error over `count` floats: *loss (device) = mean (out-target)^2,
+ * dout = its gradient 2 (out - target) / count. */
+int lsms_mlp_mse(lsms_handle_t h, const float *out, const float *target, int64_t count, float *dout, float *loss,
+                 void *stream);
+
+/* AdamW step `step` (1-based) on the FP32 parameters (moments m, v device
+ * floats, zero before step 1), refreshing w_bf16:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * w -= lr (m/(1-b1^step) / (sqrt(v/(1-b2^step)) + eps) + weight_decay w). */
+int lsms_mlp_adamw(lsms_handle_t h, float *params, uint16_t *w_bf16, float *m, float *v, const float *grad, float lr,
+                   float beta1, float beta2, float eps, float weight_decay, int32_t step, void *stream);
+
+/* Seeds for tau00_gmres from network outputs out [n][1024]:
+ * seed[i] (device [n][256] complex, column-major 16 x 16) =
+ * out[i][512 + q] * scale[512 + q] + shift[512 + q] for the 512 floats q
+ * (scale, shift device [1024] floats, the training normalisation). */
+int lsms_mlp_seed(lsms_handle_t h, const float *out, const float *scale, const float *shift, int32_t n,
+                  double *seed, void *stream);
+
+/* Training targets of each instance (device [n_inst][1024] floats) from
+ * tau00 (device [n_inst][256] complex, e.g. tau00_solve's output):
+ * [tau00 | D], D(L, L') = tau00(L, L') / t0_{l(L')} = [M^{-1}]_{00}(L, L')
+ * (0 where t0 vanishes), interleaved re/im, column-major 16 x 16 each.  With
+ * scale and shift (device [1024] floats, both or neither) the targets are
+ * normalised: (x - shift) / scale.  lmax = 3. */
+int lsms_mlp_targets(lsms_handle_t h, const lsms_problem *p, const double *tau00, const float *scale,
+                     const float *shift, float *target, void *stream);
+
+/* Normalisation of targets [n][1024]: shift = column mean, scale = column
+ * standard deviation (1 where it vanishes). */
+int lsms_mlp_norm_stats(lsms_handle_t h, const float *target, int32_t n, float *scale, float *shift, void *stream);
+
+/* Workspace of tau00_gmres: one slot per resident workgroup (the matrix, the
+ * two 64 x 64 blocks of the fallback, the solution, the residual, restart+1
+ * Krylov blocks of n x 16 complex, the block Hessenberg matrix) plus the work
+ * counter and the instance order.  lmax must be 3 (-2 otherwise);
+ * 1 <= restart <= 8 (-3). */
+int lsms_gmres_workspace_size(lsms_handle_t h, const lsms_problem *p, int32_t restart, size_t *bytes);
+
+/* tau00 by block GMRES (lmax = 3): for each instance the fused kernel builds
+ * M as tau00_solve does and solves A Y = E_c (A = M^T, E_c the 16 unit columns
+ * of the central block) with all 16 columns as one block: restarted block
+ * GMRES(restart) from Y_c = seed^T in the central rows (or zero if seed is
+ * NULL) followed by one Jacobi step on the other rows, until
+ * ||E_c - A Y||_F <= tol ||E_c||_F or max_cycles restarts; then
+ * tau00 = Y_c^T diag(t_0).  An instance that does not converge is solved by
+ * the FP64 path (info = LSMS_INFO_LU_FALLBACK).  steps: device [n_inst], block
+ * Arnoldi steps (one product with M each) taken.  seed: device [n_inst][256]
+ * complex approximation of [M^{-1}]_{00} (lsms_mlp_seed) or NULL. */
+int tau00_gmres(lsms_handle_t h, const lsms_problem *p, const double *seed, int32_t restart, int32_t max_cycles,
+                double tol, double *tau00, int32_t *info, int32_t *steps, void *work, size_t work_bytes,
+                void *stream);
 
 #ifdef __cplusplus
 }

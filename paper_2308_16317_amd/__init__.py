@@ -7,6 +7,9 @@ marshals arguments.  PyTorch provides device memory and the current stream.
 from .lsms import (  # noqa: F401
     GRAPH,
     INFO_FP64_FALLBACK,
+    INFO_LU_FALLBACK,
+    MLP_ACT,
+    MLP_PARAMS,
     PERSISTENT,
     PREC_FP32_IR,
     PREC_FP64,
@@ -16,10 +19,21 @@ from .lsms import (  # noqa: F401
     autotune,
     build_kkr,
     build_liz,
+    gmres_workspace_size,
     lib,
+    mlp_adamw,
+    mlp_backward,
+    mlp_cast,
+    mlp_features,
+    mlp_forward,
+    mlp_mse,
+    mlp_norm_stats,
+    mlp_seed,
+    mlp_targets,
     problem_for_workload,
     set_tuned_nb,
     tau00_batched,
+    tau00_gmres,
     tau00_solve,
     workspace_size,
 )

@@ -444,3 +444,196 @@ extern "C" int lsms_autotune(lsms_handle_t h, const lsms_problem* p, const lsms_
   *best_nb = best;
   return 0;
 }
+
+// ---------------------------------------------------------------- learned form
+
+namespace {
+
+struct GmresLayout {
+  int grid;
+  size_t order_off, slots_off, slot_stride, total;
+};
+
+int gmres_layout(const lsms_handle_s* h, const lsms_problem* p, int restart, GmresLayout* L) {
+  const lsms_prob_dev d = to_dev(p);
+  if (lsms_gmres_grid(d, h->device, &L->grid) != hipSuccess) return LSMS_EHIP;
+  L->order_off = 256;
+  L->slots_off = align256(256 + 4 * (size_t)p->n_inst);
+  L->slot_stride = m_bytes(p) + (size_t)lsms_gmres_extra_bytes(d, restart);
+  L->total = L->slots_off + (size_t)L->grid * L->slot_stride;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" int lsms_gmres_workspace_size(lsms_handle_t h, const lsms_problem* p, int32_t restart, size_t* bytes) {
+  if (!h) return -1;
+  int r = check_problem(p);
+  if (r) return r;
+  if (p->lmax != 3) return -2;
+  if (restart < 1 || restart > lsms_gmres_max_restart()) return -3;
+  if (!bytes) return -4;
+  (void)hipSetDevice(h->device);
+  GmresLayout L;
+  if (gmres_layout(h, p, restart, &L)) return LSMS_EHIP;
+  *bytes = L.total;
+  return 0;
+}
+
+extern "C" int tau00_gmres(lsms_handle_t h, const lsms_problem* p, const double* seed, int32_t restart,
+                           int32_t max_cycles, double tol, double* tau00, int32_t* info, int32_t* steps, void* work,
+                           size_t work_bytes, void* stream) {
+  if (!h) return -1;
+  int r = check_problem(p);
+  if (r) return r;
+  if (p->lmax != 3) return -2;
+  if (restart < 1 || restart > lsms_gmres_max_restart()) return -4;
+  if (max_cycles < 0 || max_cycles > 1000) return -5;
+  if (!(tol > 0.0 && tol < 1.0)) return -6;
+  if (p->n_inst == 0) return 0;
+  if (!tau00) return -7;
+  if (!info) return -8;
+  if (!steps) return -9;
+  if (!work) return -10;
+  (void)hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  GmresLayout L;
+  if (gmres_layout(h, p, restart, &L)) return LSMS_EHIP;
+  if (work_bytes < L.total) return -11;
+  const lsms_prob_dev d = to_dev(p);
+  char* w = (char*)work;
+  int32_t* counter = (int32_t*)w;
+  int32_t* order = (int32_t*)(w + L.order_off);
+  if (fill_i32(counter, 0, 1, s) != hipSuccess) return LSMS_EHIP;
+  if (lsms_launch_lpt_order(d, order, s) != hipSuccess) return LSMS_EHIP;
+  if (lsms_launch_gmres(d, h->g[p->lmax], order, counter, (unsigned char*)(w + L.slots_off), (int64_t)L.slot_stride,
+                        (int64_t)m_bytes(p), L.grid, seed, tau00, info, steps, panel_width(h, p, nullptr), tol,
+                        max_cycles, restart, s) != hipSuccess)
+    return LSMS_EHIP;
+  return 0;
+}
+
+extern "C" int lsms_mlp_features(lsms_handle_t h, const lsms_problem* p, double a_lat, float* feat, void* stream) {
+  if (!h) return -1;
+  int r = check_problem(p);
+  if (r) return r;
+  if (!(a_lat > 0.0)) return -3;
+  if (p->n_inst == 0) return 0;
+  if (!feat) return -4;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_mlp_features(to_dev(p), a_lat, feat, (hipStream_t)stream) == hipSuccess ? 0 : LSMS_EHIP;
+}
+
+extern "C" int lsms_mlp_cast(lsms_handle_t h, const float* params, uint16_t* w_bf16, void* stream) {
+  if (!h) return -1;
+  if (!params) return -2;
+  if (!w_bf16) return -3;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_mlp_to_bf16(lsms_mlp_param_count(), params, w_bf16, (hipStream_t)stream) == hipSuccess
+             ? 0
+             : LSMS_EHIP;
+}
+
+extern "C" int lsms_mlp_forward(lsms_handle_t h, const float* params, const uint16_t* w_bf16, const float* feat,
+                                int32_t n, float* out, float* act, void* stream) {
+  if (!h) return -1;
+  if (!params) return -2;
+  if (!w_bf16) return -3;
+  if (n < 0) return -5;
+  if (n == 0) return 0;
+  if (!feat) return -4;
+  if (!act) return -7;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_mlp_forward(params, w_bf16, feat, n, out, act, (hipStream_t)stream) == hipSuccess ? 0
+                                                                                                      : LSMS_EHIP;
+}
+
+extern "C" int lsms_mlp_backward(lsms_handle_t h, const uint16_t* w_bf16, const float* feat, const float* act,
+                                 const float* dout, int32_t n, float* grad, float* work, void* stream) {
+  if (!h) return -1;
+  if (!w_bf16) return -2;
+  if (!feat) return -3;
+  if (!act) return -4;
+  if (!dout) return -5;
+  if (n < 1) return -6;
+  if (!grad) return -7;
+  if (!work) return -8;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_mlp_backward(w_bf16, feat, act, dout, n, grad, work, (hipStream_t)stream) == hipSuccess
+             ? 0
+             : LSMS_EHIP;
+}
+
+extern "C" int lsms_mlp_mse(lsms_handle_t h, const float* out, const float* target, int64_t count, float* dout,
+                            float* loss, void* stream) {
+  if (!h) return -1;
+  if (!out) return -2;
+  if (!target) return -3;
+  if (count < 0) return -4;
+  if (!dout) return -5;
+  if (!loss) return -6;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_mlp_mse(out, target, count, dout, loss, (hipStream_t)stream) == hipSuccess ? 0 : LSMS_EHIP;
+}
+
+extern "C" int lsms_mlp_adamw(lsms_handle_t h, float* params, uint16_t* w_bf16, float* m, float* v,
+                              const float* grad, float lr, float beta1, float beta2, float eps, float weight_decay,
+                              int32_t step, void* stream) {
+  if (!h) return -1;
+  if (!params) return -2;
+  if (!w_bf16) return -3;
+  if (!m) return -4;
+  if (!v) return -5;
+  if (!grad) return -6;
+  if (!(lr >= 0.f)) return -7;
+  if (!(beta1 >= 0.f && beta1 < 1.f)) return -8;
+  if (!(beta2 >= 0.f && beta2 < 1.f)) return -9;
+  if (!(eps > 0.f)) return -10;
+  if (!(weight_decay >= 0.f)) return -11;
+  if (step < 1) return -12;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_mlp_adamw(lsms_mlp_param_count(), params, w_bf16, m, v, grad, lr, beta1, beta2, eps,
+                               weight_decay, step, (hipStream_t)stream) == hipSuccess
+             ? 0
+             : LSMS_EHIP;
+}
+
+extern "C" int lsms_mlp_seed(lsms_handle_t h, const float* out, const float* scale, const float* shift, int32_t n,
+                             double* seed, void* stream) {
+  if (!h) return -1;
+  if (!out) return -2;
+  if (!scale) return -3;
+  if (!shift) return -4;
+  if (n < 0) return -5;
+  if (n == 0) return 0;
+  if (!seed) return -6;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_mlp_seed(n, 16, out, scale, shift, seed, (hipStream_t)stream) == hipSuccess ? 0 : LSMS_EHIP;
+}
+
+extern "C" int lsms_mlp_targets(lsms_handle_t h, const lsms_problem* p, const double* tau00, const float* scale,
+                                const float* shift, float* target, void* stream) {
+  if (!h) return -1;
+  int r = check_problem(p);
+  if (r) return r;
+  if (p->lmax != 3) return -2;
+  if (p->n_inst == 0) return 0;
+  if (!tau00) return -3;
+  if ((scale == nullptr) != (shift == nullptr)) return -4;
+  if (!target) return -6;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_mlp_targets(to_dev(p), tau00, scale, shift, target, (hipStream_t)stream) == hipSuccess
+             ? 0
+             : LSMS_EHIP;
+}
+
+extern "C" int lsms_mlp_norm_stats(lsms_handle_t h, const float* target, int32_t n, float* scale, float* shift,
+                                   void* stream) {
+  if (!h) return -1;
+  if (!target) return -2;
+  if (n < 1) return -3;
+  if (!scale) return -4;
+  if (!shift) return -5;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_mlp_norm_stats(n, target, scale, shift, (hipStream_t)stream) == hipSuccess ? 0 : LSMS_EHIP;
+}

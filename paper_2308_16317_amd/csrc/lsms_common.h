@@ -152,3 +152,33 @@ hipError_t lsms_launch_mixed_persistent(const lsms_prob_dev& p, const lsms_gaunt
                                         int32_t* counter, unsigned char* work, int64_t slot_bytes, int64_t m_bytes,
                                         int grid, double* tau00, int32_t* info, int32_t nb, double tol,
                                         int32_t max_refine, hipStream_t s);
+
+// Learned form, solver: persistent build + block GMRES from a seed (or none)
+// + FP64 Schur fallback, lmax = 3.  Slot: [M (m_bytes) | X blocks | Y | R |
+// V (m + 1 blocks) | H | G].
+int64_t lsms_gmres_extra_bytes(const lsms_prob_dev& p, int m);
+int lsms_gmres_max_restart();
+hipError_t lsms_gmres_grid(const lsms_prob_dev& p, int device, int* grid);
+hipError_t lsms_launch_gmres(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order, int32_t* counter,
+                             unsigned char* work, int64_t slot_bytes, int64_t m_bytes, int grid, const double* seed,
+                             double* tau00, int32_t* info, int32_t* steps, int32_t nb, double tol, int max_cycles,
+                             int m, hipStream_t s);
+
+// Learned form, network (mlp.hip).
+int64_t lsms_mlp_param_count();
+int64_t lsms_mlp_act_floats();
+hipError_t lsms_launch_mlp_features(const lsms_prob_dev& p, double a, float* feat, hipStream_t s);
+hipError_t lsms_launch_mlp_forward(const float* params, const uint16_t* wb, const float* feat, int n, float* out,
+                                   float* act, hipStream_t s);
+hipError_t lsms_launch_mlp_backward(const uint16_t* wb, const float* feat, const float* act, const float* dout,
+                                    int n, float* grad, float* work, hipStream_t s);
+hipError_t lsms_launch_mlp_mse(const float* out, const float* target, int64_t total, float* dout, float* loss,
+                               hipStream_t s);
+hipError_t lsms_launch_mlp_adamw(int64_t n, float* w, uint16_t* wb, float* m, float* v, const float* g, float lr,
+                                 float b1, float b2, float eps, float wd, int step, hipStream_t s);
+hipError_t lsms_launch_mlp_to_bf16(int64_t n, const float* w, uint16_t* wb, hipStream_t s);
+hipError_t lsms_launch_mlp_seed(int n, int kk, const float* out, const float* scale, const float* shift, double* seed,
+                                hipStream_t s);
+hipError_t lsms_launch_mlp_targets(const lsms_prob_dev& p, const double* tau00, const float* scale,
+                                   const float* shift, float* target, hipStream_t s);
+hipError_t lsms_launch_mlp_norm_stats(int n, const float* target, float* scale, float* shift, hipStream_t s);

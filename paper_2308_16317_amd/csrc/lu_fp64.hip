@@ -767,6 +767,510 @@ __global__ __launch_bounds__(kThreads) void tau00_mixed_persistent_kernel(
   }
 }
 
+// ======================================================================
+// Learned form: block GMRES on A Y = E_c (A = M^T, E_c the unit vectors of
+// the central rows, as in the precision form), seeded by an approximation D
+// of [M^{-1}]_{00}, with the FP64 Schur path as the fallback.
+//
+// Seed: Y_c = D^T in the central rows, then Y_r = (E_c - A Y)_r, one Jacobi
+// step on the other rows (exact when the other sites do not scatter among
+// themselves).  Restarted block GMRES(m) with the 16 right-hand sides as one
+// block: block Arnoldi with classical Gram-Schmidt applied twice, each new
+// block orthonormalised by Cholesky QR applied twice, the least-squares
+// problem on the block Hessenberg matrix solved by Householder QR, restarts
+// until ||E_c - A Y||_F <= tol ||E_c||_F (all in FP64).  lmax = 3 only
+// (kk = 16, one 16-column block).
+// ======================================================================
+
+constexpr int kInfoLuFallback = 512;
+constexpr int kGmMaxM = 8;  // block Arnoldi steps per restart, at most
+
+struct GmresBufs {
+  zd* Y;  // N x 16 solution (row-major, internal rows)
+  zd* R;  // N x 16 residual
+  zd* V;  // (m + 1) blocks of N x 16
+  zd* H;  // ((m + 1) 16) x (m 16) block Hessenberg, column-major
+  zd* G;  // ((m + 1) 16) x 16 least-squares right-hand side, column-major
+  zd* Q;  // Householder vectors of the QR of H, 32 per column (16 m columns)
+  double* beta;  // their scale factors
+  int m;
+};
+
+struct GmresSmem {
+  zd h[(kGmMaxM + 1) * 16][16];  // Gram-Schmidt coefficients of one block column
+  zd l[16][16];                  // Cholesky factor, then its inverse
+  zd r[16][16];                  // triangular factor of a block QR
+  zd t[16][16];                  // scratch
+  zd hv[48];                     // Householder vector
+  double red[kLuWaves];
+  double beta;
+  int flag;
+};
+
+__device__ __forceinline__ zd zconj(zd a) { return zmake(a.x, -a.y); }
+
+// out = A X (resid = false) or E_c - A X (resid = true); X, out N x 16
+// row-major.  FP64 MFMA, one 16-row block per wave at a time, the reduction
+// in chunks of 16 loaded one chunk ahead.
+__device__ void gm_amul(const Mat<zd>& A, const zd* __restrict__ X, zd* __restrict__ out, bool resid) {
+  typedef Prec<double>::V4 V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int N = (int)A.N, Nd = A.Nd;
+  for (int rb = 16 * wave; rb < N; rb += 16 * kLuWaves) {
+    V4 ar = V4{0.0, 0.0, 0.0, 0.0}, ai = V4{0.0, 0.0, 0.0, 0.0};
+    const int va = rb + li;
+    const bool rok = va < N;
+    const zd* arow = A.base + A.phys(rok ? va : 0) * A.N;
+    zd an[4], xn[4];
+    auto load = [&](int kc) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = kc + 4 * lq + j;
+        zd av = zmake(0.0, 0.0), xv = zmake(0.0, 0.0);
+        if (k < N) {
+          if (rok) av = arow[A.phys(k)];
+          xv = X[(int64_t)k * 16 + li];
+        }
+        an[j] = av;
+        xn[j] = xv;
+      }
+    };
+    load(0);
+    for (int kc = 0; kc < N; kc += 16) {
+      zd a[4], x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        a[j] = an[j];
+        x[j] = xn[j];
+      }
+      if (kc + 16 < N) load(kc + 16);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        ar = Prec<double>::mfma(a[j].x, x[j].x, ar);
+        ar = Prec<double>::mfma(-a[j].y, x[j].y, ar);
+        ai = Prec<double>::mfma(a[j].x, x[j].y, ai);
+        ai = Prec<double>::mfma(a[j].y, x[j].x, ai);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = rb + Prec<double>::drow(r, lq);
+      if (v < N) {
+        zd o = zmake(ar[r], ai[r]);
+        if (resid) o = zmake(((v == Nd + li) ? 1.0 : 0.0) - o.x, -o.y);
+        out[(int64_t)v * 16 + li] = o;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// gs.h[16 i + a][b] = sum_v conj(V_i[v][a]) W[v][b], i < nb.
+__device__ void gm_gram(const zd* __restrict__ V, int nb, int N, const zd* __restrict__ W, GmresSmem& gs) {
+  for (int q = threadIdx.x; q < nb * 256; q += kLuThreads) {
+    const int i = q >> 8, a = (q >> 4) & 15, b = q & 15;
+    const zd* vi = V + (int64_t)i * N * 16;
+    double sr = 0.0, si = 0.0;
+    for (int v = 0; v < N; ++v) {
+      const zd x = vi[(int64_t)v * 16 + a], y = W[(int64_t)v * 16 + b];
+      sr += x.x * y.x + x.y * y.y;
+      si += x.x * y.y - x.y * y.x;
+    }
+    gs.h[16 * i + a][b] = zmake(sr, si);
+  }
+  __syncthreads();
+}
+
+// W[v][b] -= sum_{i < nb, a} V_i[v][a] gs.h[16 i + a][b].
+__device__ void gm_subtract(const zd* __restrict__ V, int nb, int N, zd* __restrict__ W, const GmresSmem& gs) {
+  for (int q = threadIdx.x; q < N * 16; q += kLuThreads) {
+    const int v = q >> 4, b = q & 15;
+    zd acc = W[q];
+    for (int i = 0; i < nb; ++i) {
+      const zd* vr = V + ((int64_t)i * N + v) * 16;
+#pragma unroll 4
+      for (int a = 0; a < 16; ++a) acc = zfms(acc, vr[a], gs.h[16 * i + a][b]);
+    }
+    W[q] = acc;
+  }
+  __syncthreads();
+}
+
+// W (N x 16) := Q with W = Q R, R upper triangular into gs.r (Cholesky QR
+// applied twice: G = W^H W = L L^H, Q = W L^{-H}, R = L^H).  Returns false
+// when the block is numerically rank deficient (a non-positive pivot).
+__device__ bool gm_cholqr(zd* __restrict__ W, int N, GmresSmem& gs) {
+  const int tid = threadIdx.x;
+  for (int pass = 0; pass < 2; ++pass) {
+    gm_gram(W, 1, N, W, gs);
+    if (tid == 0) {
+      int bad = 0;
+      for (int j = 0; j < 16 && !bad; ++j) {
+        double d = gs.h[j][j].x;
+        for (int k = 0; k < j; ++k) d -= gs.l[j][k].x * gs.l[j][k].x + gs.l[j][k].y * gs.l[j][k].y;
+        if (!(d > 1e-280)) {
+          bad = 1;
+          break;
+        }
+        const double ljj = sqrt(d);
+        gs.l[j][j] = zmake(ljj, 0.0);
+        for (int i = j + 1; i < 16; ++i) {
+          zd acc = gs.h[i][j];
+          for (int k = 0; k < j; ++k) acc = zfms(acc, gs.l[i][k], zconj(gs.l[j][k]));
+          gs.l[i][j] = zscale(acc, 1.0 / ljj);
+        }
+        for (int i = 0; i < j; ++i) gs.l[i][j] = zmake(0.0, 0.0);
+      }
+      if (!bad) {
+        // R := L^H R (R = I before the first pass)
+        for (int i = 0; i < 16; ++i)
+          for (int j = 0; j < 16; ++j) gs.t[i][j] = pass == 0 ? zmake(i == j ? 1.0 : 0.0, 0.0) : gs.r[i][j];
+        for (int i = 0; i < 16; ++i)
+          for (int j = 0; j < 16; ++j) {
+            zd acc = zmake(0.0, 0.0);
+            for (int k = i; k <= j; ++k) acc = zadd(acc, zmul(zconj(gs.l[k][i]), gs.t[k][j]));
+            gs.r[i][j] = j >= i ? acc : zmake(0.0, 0.0);
+          }
+        // L := L^{-1} (forward substitution, column by column, via gs.t)
+        for (int j = 0; j < 16; ++j) {
+          for (int i = 0; i < 16; ++i) gs.t[i][j] = zmake(0.0, 0.0);
+          gs.t[j][j] = zinv(gs.l[j][j]);
+          for (int i = j + 1; i < 16; ++i) {
+            zd acc = zmake(0.0, 0.0);
+            for (int k = j; k < i; ++k) acc = zadd(acc, zmul(gs.l[i][k], gs.t[k][j]));
+            gs.t[i][j] = zmul(zmake(-acc.x, -acc.y), zinv(gs.l[i][i]));
+          }
+        }
+        for (int i = 0; i < 16; ++i)
+          for (int j = 0; j < 16; ++j) gs.l[i][j] = gs.t[i][j];
+      }
+      gs.flag = bad;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(gs.flag)) return false;
+    // W := W L^{-H}: W[v][b] = sum_{a <= b} W[v][a] conj(Linv[b][a])
+    for (int v = tid; v < N; v += kLuThreads) {
+      zd w[16];
+#pragma unroll
+      for (int a = 0; a < 16; ++a) w[a] = W[(int64_t)v * 16 + a];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        zd acc = zmake(0.0, 0.0);
+#pragma unroll
+        for (int a = 0; a <= b; ++a) acc = zadd(acc, zmul(w[a], zconj(gs.l[b][a])));
+        W[(int64_t)v * 16 + b] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// Incremental Householder QR of the block Hessenberg H for the least-squares
+// problem min || G - H y ||: block column j (16 columns, nonzero in rows
+// < 16 (j + 2)) first receives the reflections of the earlier columns, then
+// its own (one per column, at most 32 rows, vectors kept in b.Q), which are
+// also applied to G.  Returns the Frobenius norm of rows 16 (j + 1) ..
+// 16 (j + 2) of Q^H G, the residual norm of the least-squares solution over
+// the first 16 (j + 1) columns.
+__device__ double gm_qr_block(const GmresBufs& b, int ldh, int j, GmresSmem& gs) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // earlier reflections on the new columns (one thread per column, in order)
+  if (tid < 16) {
+    zd* col = b.H + (int64_t)(16 * j + tid) * ldh;
+    for (int c = 0; c < 16 * j; ++c) {
+      const int len = min(16 * (j + 2), 16 * (c / 16 + 2)) - c;
+      const zd* v = b.Q + (int64_t)c * 32;
+      zd acc = zmake(0.0, 0.0);
+      for (int r = 0; r < len; ++r) acc = zadd(acc, zmul(zconj(v[r]), col[c + r]));
+      acc = zscale(acc, b.beta[c]);
+      for (int r = 0; r < len; ++r) col[c + r] = zfms(col[c + r], v[r], acc);
+    }
+  }
+  __syncthreads();
+  for (int c = 16 * j; c < 16 * (j + 1); ++c) {
+    const int len = 16 * (j + 2) - c;
+    if (tid == 0) {
+      const zd* x = b.H + (int64_t)c * ldh + c;
+      double nrm2 = 0.0;
+      for (int r = 0; r < len; ++r) {
+        gs.hv[r] = x[r];
+        nrm2 += x[r].x * x[r].x + x[r].y * x[r].y;
+      }
+      const double nrm = sqrt(nrm2);
+      const zd x0 = gs.hv[0];
+      const double ax0 = sqrt(x0.x * x0.x + x0.y * x0.y);
+      const zd ph = ax0 > 0.0 ? zscale(x0, 1.0 / ax0) : zmake(1.0, 0.0);
+      // v = x + e^{i arg x0} ||x|| e_1, beta = 2 / (v^H v)
+      gs.hv[0] = zadd(x0, zscale(ph, nrm));
+      double vn = 0.0;
+      for (int r = 0; r < len; ++r) vn += gs.hv[r].x * gs.hv[r].x + gs.hv[r].y * gs.hv[r].y;
+      gs.beta = vn > 0.0 ? 2.0 / vn : 0.0;
+      for (int r = 0; r < 32; ++r) b.Q[(int64_t)c * 32 + r] = r < len ? gs.hv[r] : zmake(0.0, 0.0);
+      b.beta[c] = gs.beta;
+    }
+    __syncthreads();
+    // apply to the block's columns c .. 16 (j + 1) - 1 and to the 16 columns of G
+    const int ncol = 16 * (j + 1) - c;
+    for (int q = tid; q < ncol + 16; q += kLuThreads) {
+      zd* col = q < ncol ? b.H + (int64_t)(c + q) * ldh : b.G + (int64_t)(q - ncol) * ldh;
+      zd acc = zmake(0.0, 0.0);
+      for (int r = 0; r < len; ++r) acc = zadd(acc, zmul(zconj(gs.hv[r]), col[c + r]));
+      acc = zscale(acc, gs.beta);
+      for (int r = 0; r < len; ++r) col[c + r] = zfms(col[c + r], gs.hv[r], acc);
+    }
+    __syncthreads();
+  }
+  // residual norm: rows 16 (j + 1) .. 16 (j + 2) of G
+  double sq = 0.0;
+  for (int q = tid; q < 256; q += kLuThreads) {
+    const zd g = b.G[(int64_t)(q & 15) * ldh + 16 * (j + 1) + (q >> 4)];
+    sq += g.x * g.x + g.y * g.y;
+  }
+  for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+  if (lane == 0) gs.red[wave] = sq;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < kLuWaves; ++q) t += gs.red[q];
+  __syncthreads();
+  return sqrt(t);
+}
+
+// y = R^{-1} (Q^H G)[0 .. nc) for the triangular R left in H; y overwrites
+// the first nc rows of G.  Returns false on a zero diagonal.
+__device__ bool gm_backsolve(const GmresBufs& b, int ldh, int nc, GmresSmem& gs) {
+  const int tid = threadIdx.x;
+  if (tid == 0) gs.flag = 0;
+  __syncthreads();
+  if (tid < 16) {
+    zd* g = b.G + (int64_t)tid * ldh;
+    for (int c = nc - 1; c >= 0; --c) {
+      zd acc = g[c];
+      for (int k = c + 1; k < nc; ++k) acc = zfms(acc, b.H[(int64_t)k * ldh + c], g[k]);
+      const zd d = b.H[(int64_t)c * ldh + c];
+      if (d.x == 0.0 && d.y == 0.0) gs.flag = 1;
+      g[c] = zdiv(acc, d);
+    }
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(gs.flag) == 0;
+}
+
+// Frobenius norm of an N x 16 block (all threads get it).
+__device__ double gm_norm(const zd* __restrict__ X, int N, GmresSmem& gs) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double s = 0.0;
+  for (int q = tid; q < N * 16; q += kLuThreads) s += X[q].x * X[q].x + X[q].y * X[q].y;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) gs.red[wave] = s;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < kLuWaves; ++q) t += gs.red[q];
+  __syncthreads();
+  return sqrt(t);
+}
+
+// Block GMRES for one instance; returns true when converged (Y holds the
+// solution) and the number of block Arnoldi steps taken in *steps.
+__device__ __noinline__ bool gmres_solve(const Mat<zd>& A, const GmresBufs& b, const double* seed, double tol,
+                                         int max_cycles, unsigned char* smem, int* steps) {
+  GmresSmem& gs = *reinterpret_cast<GmresSmem*>(smem);
+  const int tid = threadIdx.x;
+  const int N = (int)A.N, Nd = A.Nd, m = b.m;
+  const int ldh = 16 * (m + 1);
+  // initial guess: the seed in the central rows, then one Jacobi step
+  for (int q = tid; q < N * 16; q += kLuThreads) {
+    const int v = q >> 4, c = q & 15;
+    zd y = zmake(0.0, 0.0);
+    if (seed && v >= Nd) y = reinterpret_cast<const zd*>(seed)[c + 16 * (v - Nd)];
+    b.Y[q] = y;
+  }
+  __syncthreads();
+  if (seed) {
+    gm_amul(A, b.Y, b.R, true);
+    for (int q = tid; q < Nd * 16; q += kLuThreads) b.Y[q] = zadd(b.Y[q], b.R[q]);
+    __syncthreads();
+  }
+  const double enorm = 4.0;  // ||E_c||_F with 16 unit columns
+  int it = 0;
+  bool conv = false;
+  for (int cycle = 0;; ++cycle) {
+    gm_amul(A, b.Y, b.R, true);
+    const double rn = gm_norm(b.R, N, gs);
+    if (!(rn == rn)) break;
+    if (rn <= tol * enorm) {
+      conv = true;
+      break;
+    }
+    if (cycle == max_cycles) break;
+    // V_0 R_0 = R
+    for (int q = tid; q < N * 16; q += kLuThreads) b.V[q] = b.R[q];
+    __syncthreads();
+    if (!gm_cholqr(b.V, N, gs)) break;
+    for (int q = tid; q < ldh * 16; q += kLuThreads) {
+      const int r = q % ldh, c = q / ldh;
+      b.G[q] = r < 16 ? gs.r[r][c] : zmake(0.0, 0.0);
+    }
+    for (int q = tid; q < ldh * 16 * m; q += kLuThreads) b.H[q] = zmake(0.0, 0.0);
+    __syncthreads();
+    int jdone = 0;
+    for (int j = 0; j < m; ++j) {
+      zd* Vj = b.V + (int64_t)j * N * 16;
+      zd* W = b.V + (int64_t)(j + 1) * N * 16;
+      gm_amul(A, Vj, W, false);
+      for (int pass = 0; pass < 2; ++pass) {
+        gm_gram(b.V, j + 1, N, W, gs);
+        for (int q = tid; q < (j + 1) * 256; q += kLuThreads) {
+          const int r = q >> 4, c = q & 15;
+          zd* hq = b.H + (int64_t)(16 * j + c) * ldh + r;
+          *hq = zadd(*hq, gs.h[r][c]);
+        }
+        gm_subtract(b.V, j + 1, N, W, gs);
+      }
+      ++it;
+      // a rank-deficient new block means the Krylov space is exhausted: its
+      // part of H stays zero and the least-squares solution is exact
+      const bool ok = gm_cholqr(W, N, gs);
+      if (ok) {
+        for (int q = tid; q < 256; q += kLuThreads) {
+          const int r = q >> 4, c = q & 15;
+          b.H[(int64_t)(16 * j + c) * ldh + 16 * (j + 1) + r] = gs.r[r][c];
+        }
+        __syncthreads();
+      }
+      const double est = gm_qr_block(b, ldh, j, gs);
+      jdone = j + 1;
+      if (!ok || est <= tol * enorm) break;
+    }
+    if (!gm_backsolve(b, ldh, 16 * jdone, gs)) break;
+    // Y += [V_0 .. V_{jdone-1}] y
+    for (int q = tid; q < N * 16; q += kLuThreads) {
+      const int v = q >> 4, c = q & 15;
+      zd acc = b.Y[q];
+      for (int i = 0; i < jdone; ++i) {
+        const zd* vr = b.V + ((int64_t)i * N + v) * 16;
+        const zd* g = b.G + (int64_t)c * ldh + 16 * i;
+        for (int a = 0; a < 16; ++a) acc = zfms(acc, zmake(-vr[a].x, -vr[a].y), g[a]);
+      }
+      b.Y[q] = acc;
+    }
+    __syncthreads();
+  }
+  *steps = it;
+  return conv;
+}
+
+int64_t gmres_extra_bytes(int64_t nmax, int m) {
+  const int64_t blk = ((nmax * 16 * 16) + 255) & ~(int64_t)255;
+  const int64_t h = (((int64_t)16 * (m + 1) * 16 * m * 16) + 255) & ~(int64_t)255;
+  const int64_t g = (((int64_t)16 * (m + 1) * 16 * 16) + 255) & ~(int64_t)255;
+  const int64_t q = (((int64_t)16 * m * 32 * 16) + 255) & ~(int64_t)255;
+  const int64_t bt = (((int64_t)16 * m * 8) + 255) & ~(int64_t)255;
+  return kXgBytes + blk * (2 + m + 1) + h + g + q + bt;
+}
+
+__device__ inline GmresBufs gmres_bufs(unsigned char* base, int64_t nmax, int m) {
+  const int64_t blk = ((nmax * 16 * 16) + 255) & ~(int64_t)255;
+  const int64_t h = (((int64_t)16 * (m + 1) * 16 * m * 16) + 255) & ~(int64_t)255;
+  GmresBufs b;
+  unsigned char* q = base + kXgBytes;
+  b.Y = reinterpret_cast<zd*>(q);
+  b.R = reinterpret_cast<zd*>(q + blk);
+  b.V = reinterpret_cast<zd*>(q + 2 * blk);
+  b.H = reinterpret_cast<zd*>(q + (3 + m) * blk);
+  const int64_t g = (((int64_t)16 * (m + 1) * 16 * 16) + 255) & ~(int64_t)255;
+  const int64_t qv = (((int64_t)16 * m * 32 * 16) + 255) & ~(int64_t)255;
+  b.G = reinterpret_cast<zd*>(q + (3 + m) * blk + h);
+  b.Q = reinterpret_cast<zd*>(q + (3 + m) * blk + h + g);
+  b.beta = reinterpret_cast<double*>(q + (3 + m) * blk + h + g + qv);
+  b.m = m;
+  return b;
+}
+
+size_t gmres_smem_bytes() {
+  size_t b = sizeof(GmresSmem) > sizeof(LuSmemD) ? sizeof(GmresSmem) : sizeof(LuSmemD);
+  return b > sizeof(BuildSmem) ? b : sizeof(BuildSmem);
+}
+
+// Persistent learned-form kernel: build each instance's M in the workgroup's
+// slot ([M | X blocks | GMRES buffers]), run block GMRES from the seed
+// (seed[i]: kk x kk complex column-major approximation of [M^{-1}]_{00}, or
+// none), write tau00 = Y_c^T diag(t0); on failure the FP64 Schur path on the
+// untouched M (info 512).  steps[i]: block Arnoldi steps taken.
+template <int kR, int kWL>
+__global__ __launch_bounds__(kThreads) void tau00_gmres_persistent_kernel(
+    lsms_prob_dev p, lsms_gaunt_dev g, const int32_t* __restrict__ order, int n, int32_t* __restrict__ counter,
+    unsigned char* __restrict__ work, int64_t slot_bytes, int64_t m_bytes, const double* __restrict__ seed,
+    double* __restrict__ tau00, int32_t* __restrict__ info, int32_t* __restrict__ steps, int nb, double tol,
+    int max_cycles, int m) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  BuildSmem& sb = *reinterpret_cast<BuildSmem*>(smem_raw);
+  GmresSmem& gs = *reinterpret_cast<GmresSmem*>(smem_raw);
+  __shared__ int next;
+  unsigned char* base = work + (int64_t)blockIdx.x * slot_bytes;
+  zd* M = reinterpret_cast<zd*>(base);
+  zd* xg = reinterpret_cast<zd*>(base + m_bytes);
+  const GmresBufs bufs = gmres_bufs(base + m_bytes, (int64_t)p.kk * p.max_liz, m);
+  __syncthreads();
+  int k = pop_instance(counter, &next);
+  while (k < n) {
+    const int inst = __builtin_amdgcn_readfirstlane(order ? order[k] : k);
+    int status = __builtin_amdgcn_readfirstlane(instance_invalid<kR>(p, inst) ? -3 : 0);
+    if (status == 0) {
+      const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
+      build_setup<kThreads>(p, g, inst, sb);
+      for (int j = 0; j < nliz; ++j) build_column<kThreads>(p, inst, j, M, sb);
+      status = __builtin_amdgcn_readfirstlane(sb.bad_species ? -3 : (sb.bad ? -2 : 0));
+      __syncthreads();
+    }
+    if (status == 0) {
+      const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
+      Mat<zd> A;
+      A.base = M;
+      A.N = (int64_t)p.kk * nliz;
+      A.Nd = (int)A.N - p.kk;
+      A.kk = p.kk;
+      int nsteps = 0;
+      const bool conv =
+          gmres_solve(A, bufs, seed ? seed + (int64_t)inst * 2 * 256 : nullptr, tol, max_cycles, smem_raw, &nsteps);
+      if (threadIdx.x == 0) steps[inst] = nsteps;
+      if (__builtin_amdgcn_readfirstlane((int)conv)) {
+        const int e = p.e_idx[inst];
+        const zd kap = zsqrt(reinterpret_cast<const zd*>(p.energy)[e]);
+        const int s0 = min(max(p.species[p.liz_off[inst]], 0), p.n_species - 1);
+        const zd* dl = reinterpret_cast<const zd*>(p.delta) + ((int64_t)s0 * p.n_energy + e) * (p.lmax + 1);
+        zd* tout = reinterpret_cast<zd*>(tau00) + (int64_t)inst * 256;
+        if (threadIdx.x == 0) gs.flag = 0;
+        __syncthreads();
+        for (int q = threadIdx.x; q < 256; q += kThreads) {
+          const int L = q % 16, Lp = q / 16;
+          const zd v = zmul(bufs.Y[(int64_t)(A.Nd + Lp) * 16 + L], tmat_from_delta(dl[l_of(Lp)], kap));
+          if (!zfinite(v)) gs.flag = 1;
+          tout[q] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) info[inst] = gs.flag ? -1 : 0;
+        __syncthreads();
+      } else {
+        lu_instance<kR, kWL>(p, inst, M, xg, tau00, info, nb, *reinterpret_cast<LuSmemD*>(smem_raw));
+        if (threadIdx.x == 0 && info[inst] == 0) info[inst] = kInfoLuFallback;
+        __syncthreads();
+      }
+    } else {
+      fill_nan(p, inst, tau00);
+      if (threadIdx.x == 0) {
+        info[inst] = status;
+        steps[inst] = 0;
+      }
+    }
+    __syncthreads();
+    k = pop_instance(counter, &next);
+  }
+}
+
 template <int kR, int kWL>
 hipError_t launch(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, const int64_t* m_off, int64_t slot,
                   double* xgb, int64_t xstride, double* tau00, int32_t* info, int keep_info, int32_t nb,
@@ -803,6 +1307,17 @@ hipError_t launch_mixed_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev&
                                    int32_t max_refine, hipStream_t s) {
   hipLaunchKernelGGL((tau00_mixed_persistent_kernel<kR, kWL>), dim3(grid), dim3(kThreads), mixed_smem_bytes(), s,
                      p, g, order, p.n_inst, counter, work, slot_bytes, m_bytes, tau00, info, nb, tol, max_refine);
+  return hipGetLastError();
+}
+
+template <int kR, int kWL>
+hipError_t launch_gmres(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order, int32_t* counter,
+                        unsigned char* work, int64_t slot_bytes, int64_t m_bytes, int grid, const double* seed,
+                        double* tau00, int32_t* info, int32_t* steps, int32_t nb, double tol, int max_cycles,
+                        int m, hipStream_t s) {
+  hipLaunchKernelGGL((tau00_gmres_persistent_kernel<kR, kWL>), dim3(grid), dim3(kThreads), gmres_smem_bytes(), s, p,
+                     g, order, p.n_inst, counter, work, slot_bytes, m_bytes, seed, tau00, info, steps, nb, tol,
+                     max_cycles, m);
   return hipGetLastError();
 }
 
@@ -884,6 +1399,13 @@ hipError_t lsms_launch_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& 
 // Dynamic LDS limits of every elimination kernel; called once per device
 // (at handle creation) so that no attribute call happens inside a capture.
 hipError_t lsms_prepare_kernels() {
+  const int gsm = (int)gmres_smem_bytes();
+  {
+    const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
+    hipError_t eg;
+    if ((eg = hipFuncSetAttribute((const void*)tau00_gmres_persistent_kernel<5, 4>, at, gsm)) != hipSuccess) return eg;
+    if ((eg = hipFuncSetAttribute((const void*)tau00_gmres_persistent_kernel<8, 4>, at, gsm)) != hipSuccess) return eg;
+  }
   const int a = (int)sizeof(LuSmemD);
   const int b = (int)(sizeof(LuSmemD) > sizeof(BuildSmem) ? sizeof(LuSmemD) : sizeof(BuildSmem));
   const int m = (int)mixed_smem_bytes();
@@ -941,4 +1463,38 @@ hipError_t lsms_launch_mixed_persistent(const lsms_prob_dev& p, const lsms_gaunt
                                          max_refine, s);
   return launch_mixed_persistent<8, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, tau00, info, nb, tol,
                                        max_refine, s);
+}
+
+int64_t lsms_gmres_extra_bytes(const lsms_prob_dev& p, int m) { return gmres_extra_bytes((int64_t)p.kk * p.max_liz, m); }
+
+int lsms_gmres_max_restart() { return kGmMaxM; }
+
+hipError_t lsms_gmres_grid(const lsms_prob_dev& p, int device, int* grid) {
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  if (nmax <= kThreads * 5)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_gmres_persistent_kernel<5, 4>, kThreads,
+                                                     gmres_smem_bytes());
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_gmres_persistent_kernel<8, 4>, kThreads,
+                                                     gmres_smem_bytes());
+  if (e != hipSuccess) return e;
+  *grid = cus * (per_cu > 0 ? per_cu : 1);
+  return hipSuccess;
+}
+
+hipError_t lsms_launch_gmres(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order, int32_t* counter,
+                             unsigned char* work, int64_t slot_bytes, int64_t m_bytes, int grid, const double* seed,
+                             double* tau00, int32_t* info, int32_t* steps, int32_t nb, double tol, int max_cycles,
+                             int m, hipStream_t s) {
+  if (p.n_inst <= 0) return hipSuccess;
+  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  if (nmax <= kThreads * 5)
+    return launch_gmres<5, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, seed, tau00, info, steps, nb,
+                              tol, max_cycles, m, s);
+  return launch_gmres<8, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, seed, tau00, info, steps, nb, tol,
+                            max_cycles, m, s);
 }

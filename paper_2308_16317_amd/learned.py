@@ -1,0 +1,106 @@
+"""Learned form: a small network that maps an instance's local environment
+and energy to an approximation of tau00 and of [M^{-1}]_{00}; the latter
+seeds the block-GMRES solve (`tau00_gmres`), whose fallback is the direct
+FP64 path.
+
+Training data are tau00 values the solver itself produced (`tau00_solve`);
+training runs on the GPU through the library's own kernels (forward,
+backward, MSE, AdamW).  This module only sequences those calls.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import lsms
+
+
+class SeedNet:
+    """The network's parameters (FP32 master, bf16 copy), its AdamW state and
+    the target normalisation."""
+
+    def __init__(self, h: lsms.Handle, init_params):
+        self.h = h
+        p = torch.as_tensor(np.asarray(init_params, dtype=np.float32)).to("cuda")
+        if p.numel() != lsms.MLP_PARAMS:
+            raise ValueError(f"expected {lsms.MLP_PARAMS} parameters, got {p.numel()}")
+        self.params = p.contiguous()
+        self.w_bf16 = torch.empty(lsms.MLP_PARAMS, dtype=torch.int16, device="cuda")
+        lsms.mlp_cast(h, self.params, self.w_bf16)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self.scale = None
+        self.shift = None
+
+    def set_normalisation(self, targets_raw: torch.Tensor):
+        self.scale, self.shift = lsms.mlp_norm_stats(self.h, targets_raw)
+
+    def forward(self, feat: torch.Tensor):
+        return lsms.mlp_forward(self.h, self.params, self.w_bf16, feat)
+
+    def train(self, feat: torch.Tensor, target: torch.Tensor, steps: int, batch: int = 512, lr: float = 2e-3,
+              wd: float = 0.0, seed: int = 0, lr_final: float | None = None):
+        """AdamW on the MSE between the network's outputs and the normalised
+        targets; minibatches drawn from a seeded permutation.  Returns the
+        per-step losses (host floats)."""
+        n = feat.shape[0]
+        batch = min(batch, n)
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        act = torch.empty((batch, lsms.MLP_ACT), dtype=torch.float32, device="cuda")
+        out = torch.empty((batch, 1024), dtype=torch.float32, device="cuda")
+        dout = torch.empty((batch, 1024), dtype=torch.float32, device="cuda")
+        grad = torch.empty(lsms.MLP_PARAMS, dtype=torch.float32, device="cuda")
+        work = torch.empty((batch, 1280), dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        losses = []
+        perm = torch.randperm(n, generator=g)
+        pos = 0
+        for it in range(steps):
+            if pos + batch > n:
+                perm = torch.randperm(n, generator=g)
+                pos = 0
+            idx = perm[pos:pos + batch].to("cuda")
+            pos += batch
+            fb = feat.index_select(0, idx).contiguous()
+            tb = target.index_select(0, idx).contiguous()
+            lsms.mlp_forward(self.h, self.params, self.w_bf16, fb, act=act, out=out)
+            lsms.mlp_mse(self.h, out, tb, dout=dout, loss=loss)
+            lsms.mlp_backward(self.h, self.w_bf16, fb, act, dout, grad=grad, work=work)
+            self.step += 1
+            rate = lr if lr_final is None else lr * (lr_final / lr) ** (it / max(1, steps - 1))
+            lsms.mlp_adamw(self.h, self.params, self.w_bf16, self.m, self.v, grad, rate, self.step, wd=wd)
+            losses.append(loss.clone())
+        return [float(x.item()) for x in losses]
+
+    def seeds(self, feat: torch.Tensor) -> torch.Tensor:
+        """Approximations of [M^{-1}]_{00} ([n, 256] complex128) for tau00_gmres."""
+        out, _ = self.forward(feat)
+        return lsms.mlp_seed(self.h, out, self.scale, self.shift)
+
+
+def solve_direct(h: lsms.Handle, prob: lsms.Problem) -> torch.Tensor:
+    """tau00 of every instance by the FP64 path (persistent launch), as the
+    [n, 256] complex128 column-major buffer the library writes."""
+    opts = lsms.Opts(lsms.PREC_FP64, 0, 0, lsms.PERSISTENT)
+    work = torch.empty(lsms.workspace_size(h, prob, 0, opts), dtype=torch.uint8, device="cuda")
+    tau, info = lsms.tau00_solve(h, prob, work, opts)
+    del work
+    if int((info != 0).sum().item()):
+        raise RuntimeError("the direct solver reported errors on the training set")
+    return tau.transpose(1, 2).contiguous().reshape(-1, 256)
+
+
+def train_on(h: lsms.Handle, w, a_lat: float, init_params, steps: int, batch: int = 512, lr: float = 2e-3,
+             lr_final: float | None = 2e-4, max_liz: int = 1024):
+    """Generate the training set of workload `w` with the direct solver,
+    normalise it, and train a fresh network on it.  Returns (net, losses)."""
+    prob = lsms.problem_for_workload(h, w, max_liz)
+    tau = solve_direct(h, prob)
+    feat = lsms.mlp_features(h, prob, a_lat)
+    net = SeedNet(h, init_params)
+    net.set_normalisation(lsms.mlp_targets(h, prob, tau))
+    target = lsms.mlp_targets(h, prob, tau, net.scale, net.shift)
+    losses = net.train(feat, target, steps, batch=batch, lr=lr, lr_final=lr_final)
+    return net, losses

@@ -58,7 +58,14 @@ GRAPH = 2
 
 
 SYMBOLS = ("lsms_create", "lsms_destroy", "lsms_build_liz", "build_kkr", "tau00_batched",
-           "lsms_workspace_size", "tau00_solve", "lsms_autotune", "lsms_set_tuned_nb")
+           "lsms_workspace_size", "tau00_solve", "lsms_autotune", "lsms_set_tuned_nb",
+           "lsms_mlp_features", "lsms_mlp_cast", "lsms_mlp_forward", "lsms_mlp_backward", "lsms_mlp_mse",
+           "lsms_mlp_adamw", "lsms_mlp_seed", "lsms_mlp_targets", "lsms_mlp_norm_stats",
+           "lsms_gmres_workspace_size", "tau00_gmres")
+
+MLP_PARAMS = 399616
+MLP_ACT = 2560
+INFO_LU_FALLBACK = 512
 
 
 def lib():
@@ -82,6 +89,19 @@ def lib():
                                     ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_double)]
         L.lsms_set_tuned_nb.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
+        PP = ctypes.POINTER(_Problem)
+        L.lsms_mlp_features.argtypes = [_P, PP, ctypes.c_double, _P, _P]
+        L.lsms_mlp_cast.argtypes = [_P, _P, _P, _P]
+        L.lsms_mlp_forward.argtypes = [_P, _P, _P, _P, _I32, _P, _P, _P]
+        L.lsms_mlp_backward.argtypes = [_P, _P, _P, _P, _P, _I32, _P, _P, _P]
+        L.lsms_mlp_mse.argtypes = [_P, _P, _P, ctypes.c_int64, _P, _P, _P]
+        L.lsms_mlp_adamw.argtypes = [_P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, _I32, _P]
+        L.lsms_mlp_seed.argtypes = [_P, _P, _P, _P, _I32, _P, _P]
+        L.lsms_mlp_targets.argtypes = [_P, PP, _P, _P, _P, _P, _P]
+        L.lsms_mlp_norm_stats.argtypes = [_P, _P, _I32, _P, _P, _P]
+        L.lsms_gmres_workspace_size.argtypes = [_P, PP, _I32, ctypes.POINTER(ctypes.c_size_t)]
+        L.tau00_gmres.argtypes = [_P, PP, _P, _I32, _I32, ctypes.c_double, _P, _P, _P, _P, ctypes.c_size_t, _P]
         for s in SYMBOLS:
             getattr(L, s).restype = ctypes.c_int
         _lib = L
@@ -272,3 +292,111 @@ def autotune(h: Handle, prob: Problem, work: torch.Tensor, opts: Opts | None = N
 
 def set_tuned_nb(h: Handle, n: int, nb: int):
     _check(lib().lsms_set_tuned_nb(h.ptr, int(n), int(nb)), "lsms_set_tuned_nb")
+
+
+# ------------------------------------------------------------ learned form
+
+def mlp_features(h: Handle, prob: Problem, a_lat: float) -> torch.Tensor:
+    """lsms_mlp_features: [n_inst, 18] float32 features on the device."""
+    feat = torch.empty((max(prob.n_inst, 1), 18), dtype=torch.float32, device="cuda")
+    ps = prob.struct()
+    _check(lib().lsms_mlp_features(h.ptr, ctypes.byref(ps), float(a_lat), _ptr(feat), _stream()),
+           "lsms_mlp_features")
+    return feat[:prob.n_inst]
+
+
+def mlp_cast(h: Handle, params: torch.Tensor, w_bf16: torch.Tensor):
+    _check(lib().lsms_mlp_cast(h.ptr, _ptr(params), _ptr(w_bf16), _stream()), "lsms_mlp_cast")
+
+
+def mlp_forward(h: Handle, params: torch.Tensor, w_bf16: torch.Tensor, feat: torch.Tensor, act=None, out=None):
+    """lsms_mlp_forward: returns (out [n, 1024], act [n, MLP_ACT])."""
+    n = feat.shape[0]
+    if act is None:
+        act = torch.empty((max(n, 1), MLP_ACT), dtype=torch.float32, device="cuda")
+    if out is None:
+        out = torch.empty((max(n, 1), 1024), dtype=torch.float32, device="cuda")
+    _check(lib().lsms_mlp_forward(h.ptr, _ptr(params), _ptr(w_bf16), _ptr(feat), int(n), _ptr(out), _ptr(act),
+                                  _stream()), "lsms_mlp_forward")
+    return out[:n], act[:n]
+
+
+def mlp_backward(h: Handle, w_bf16: torch.Tensor, feat: torch.Tensor, act: torch.Tensor, dout: torch.Tensor,
+                 grad=None, work=None) -> torch.Tensor:
+    n = feat.shape[0]
+    if grad is None:
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+    if work is None:
+        work = torch.empty((n, 1280), dtype=torch.float32, device="cuda")
+    _check(lib().lsms_mlp_backward(h.ptr, _ptr(w_bf16), _ptr(feat), _ptr(act), _ptr(dout), int(n), _ptr(grad),
+                                   _ptr(work), _stream()), "lsms_mlp_backward")
+    return grad
+
+
+def mlp_mse(h: Handle, out: torch.Tensor, target: torch.Tensor, dout=None, loss=None):
+    """lsms_mlp_mse: returns (dout, loss (device scalar))."""
+    if dout is None:
+        dout = torch.empty_like(out)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib().lsms_mlp_mse(h.ptr, _ptr(out), _ptr(target), int(out.numel()), _ptr(dout), _ptr(loss), _stream()),
+           "lsms_mlp_mse")
+    return dout, loss
+
+
+def mlp_adamw(h: Handle, params, w_bf16, m, v, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, wd=0.0):
+    _check(lib().lsms_mlp_adamw(h.ptr, _ptr(params), _ptr(w_bf16), _ptr(m), _ptr(v), _ptr(grad), float(lr),
+                                float(beta1), float(beta2), float(eps), float(wd), int(step), _stream()),
+           "lsms_mlp_adamw")
+
+
+def mlp_targets(h: Handle, prob: Problem, tau: torch.Tensor, scale=None, shift=None, out=None) -> torch.Tensor:
+    """lsms_mlp_targets: [n_inst, 1024] float32 ([tau00 | [M^-1]_00], optionally normalised)."""
+    if out is None:
+        out = torch.empty((max(prob.n_inst, 1), 1024), dtype=torch.float32, device="cuda")
+    ps = prob.struct()
+    _check(lib().lsms_mlp_targets(h.ptr, ctypes.byref(ps), _ptr(tau), _ptr(scale), _ptr(shift), _ptr(out),
+                                  _stream()), "lsms_mlp_targets")
+    return out[:prob.n_inst]
+
+
+def mlp_norm_stats(h: Handle, target: torch.Tensor):
+    scale = torch.empty(1024, dtype=torch.float32, device="cuda")
+    shift = torch.empty(1024, dtype=torch.float32, device="cuda")
+    _check(lib().lsms_mlp_norm_stats(h.ptr, _ptr(target), int(target.shape[0]), _ptr(scale), _ptr(shift),
+                                     _stream()), "lsms_mlp_norm_stats")
+    return scale, shift
+
+
+def mlp_seed(h: Handle, out: torch.Tensor, scale: torch.Tensor, shift: torch.Tensor) -> torch.Tensor:
+    """lsms_mlp_seed: [n, 256] complex128 seeds (column-major 16 x 16 each)."""
+    n = out.shape[0]
+    seed = torch.empty((max(n, 1), 256), dtype=torch.complex128, device="cuda")
+    _check(lib().lsms_mlp_seed(h.ptr, _ptr(out), _ptr(scale), _ptr(shift), int(n), _ptr(seed), _stream()),
+           "lsms_mlp_seed")
+    return seed[:n]
+
+
+def gmres_workspace_size(h: Handle, prob: Problem, restart: int) -> int:
+    b = ctypes.c_size_t()
+    ps = prob.struct()
+    _check(lib().lsms_gmres_workspace_size(h.ptr, ctypes.byref(ps), int(restart), ctypes.byref(b)),
+           "lsms_gmres_workspace_size")
+    return int(b.value)
+
+
+def tau00_gmres(h: Handle, prob: Problem, work: torch.Tensor, seed=None, restart: int = 8, max_cycles: int = 8,
+                tol: float = 1e-12, tau=None, info=None, steps=None):
+    """tau00_gmres: returns (tau00 [n, 16, 16], info, steps)."""
+    n = max(prob.n_inst, 1)
+    if tau is None:
+        tau = torch.empty(n * 256, dtype=torch.complex128, device="cuda")
+    if info is None:
+        info = torch.empty(n, dtype=torch.int32, device="cuda")
+    if steps is None:
+        steps = torch.empty(n, dtype=torch.int32, device="cuda")
+    ps = prob.struct()
+    _check(lib().tau00_gmres(h.ptr, ctypes.byref(ps), _ptr(seed), int(restart), int(max_cycles), float(tol),
+                             _ptr(tau), _ptr(info), _ptr(steps), _ptr(work), work.numel() * work.element_size(),
+                             _stream()), "tau00_gmres")
+    return _tau_view(tau, 16)[:prob.n_inst], info[:prob.n_inst], steps[:prob.n_inst]

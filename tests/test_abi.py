@@ -45,6 +45,19 @@ def test_header_constants_match_binding():
     assert int(defs["LSMS_INFO_FP64_FALLBACK"]) == lsms.INFO_FP64_FALLBACK
     assert int(defs["LSMS_PERSISTENT"]) == lsms.PERSISTENT
     assert int(defs["LSMS_GRAPH"]) == lsms.GRAPH
+    assert int(defs["LSMS_INFO_LU_FALLBACK"]) == lsms.INFO_LU_FALLBACK
+    assert int(defs["LSMS_MLP_PARAMS"]) == lsms.MLP_PARAMS
+    assert int(defs["LSMS_MLP_ACT"]) == lsms.MLP_ACT
+
+
+def test_network_size_matches_reference():
+    from oracle import mlp
+
+    from paper_2308_16317_amd import lsms
+
+    assert mlp.param_count() == lsms.MLP_PARAMS
+    # activations kept per sample: Z and H of three hidden layers, then the output
+    assert lsms.MLP_ACT == 6 * 256 + 1024
 
 
 def test_null_handle_rejected_without_gpu():
