@@ -1357,7 +1357,7 @@ hipError_t lsms_launch_lu_fp64(const lsms_prob_dev& p, int32_t i0, int32_t n, do
   if (n <= 0) return hipSuccess;
   const int64_t nmax = (int64_t)p.kk * p.max_liz;
   if (nmax <= kThreads * 5)
-    return launch<5, 4>(p, i0, n, M, m_off, slot, xgb, xstride, tau00, info, keep_info, nb, s);
+    return launch<5, 8>(p, i0, n, M, m_off, slot, xgb, xstride, tau00, info, keep_info, nb, s);
   return launch<8, 4>(p, i0, n, M, m_off, slot, xgb, xstride, tau00, info, keep_info, nb, s);
 }
 
@@ -1378,7 +1378,7 @@ hipError_t lsms_persistent_grid(const lsms_prob_dev& p, int device, int* grid) {
   int per_cu = 0;
   const int64_t nmax = (int64_t)p.kk * p.max_liz;
   if (nmax <= kThreads * 5)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_persistent_kernel<5, 4>, kThreads, smem);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_persistent_kernel<5, 8>, kThreads, smem);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_persistent_kernel<8, 4>, kThreads, smem);
   if (e != hipSuccess) return e;
@@ -1392,7 +1392,7 @@ hipError_t lsms_launch_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& 
   if (p.n_inst <= 0) return hipSuccess;
   const int64_t nmax = (int64_t)p.kk * p.max_liz;
   if (nmax <= kThreads * 5)
-    return launch_persistent<5, 4>(p, g, order, p.n_inst, counter, work, slot, xoff, grid, tau00, info, nb, s);
+    return launch_persistent<5, 8>(p, g, order, p.n_inst, counter, work, slot, xoff, grid, tau00, info, nb, s);
   return launch_persistent<8, 4>(p, g, order, p.n_inst, counter, work, slot, xoff, grid, tau00, info, nb, s);
 }
 
@@ -1403,7 +1403,7 @@ hipError_t lsms_prepare_kernels() {
   {
     const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
     hipError_t eg;
-    if ((eg = hipFuncSetAttribute((const void*)tau00_gmres_persistent_kernel<5, 4>, at, gsm)) != hipSuccess) return eg;
+    if ((eg = hipFuncSetAttribute((const void*)tau00_gmres_persistent_kernel<5, 8>, at, gsm)) != hipSuccess) return eg;
     if ((eg = hipFuncSetAttribute((const void*)tau00_gmres_persistent_kernel<8, 4>, at, gsm)) != hipSuccess) return eg;
   }
   const int a = (int)sizeof(LuSmemD);
@@ -1411,13 +1411,13 @@ hipError_t lsms_prepare_kernels() {
   const int m = (int)mixed_smem_bytes();
   const hipFuncAttribute attr = hipFuncAttributeMaxDynamicSharedMemorySize;
   hipError_t e;
-  if ((e = hipFuncSetAttribute((const void*)tau00_mixed_kernel<5, 4>, attr, m)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)tau00_mixed_kernel<5, 8>, attr, m)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)tau00_mixed_kernel<8, 4>, attr, m)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)tau00_mixed_persistent_kernel<5, 4>, attr, m)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)tau00_mixed_persistent_kernel<5, 8>, attr, m)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)tau00_mixed_persistent_kernel<8, 4>, attr, m)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)lu_schur_fp64_kernel<5, 4>, attr, a)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)lu_schur_fp64_kernel<5, 8>, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)lu_schur_fp64_kernel<8, 4>, attr, a)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)tau00_persistent_kernel<5, 4>, attr, b)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)tau00_persistent_kernel<5, 8>, attr, b)) != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)tau00_persistent_kernel<8, 4>, attr, b);
 }
 
@@ -1431,7 +1431,7 @@ hipError_t lsms_launch_mixed(const lsms_prob_dev& p, int32_t i0, int32_t n, doub
   if (n <= 0) return hipSuccess;
   const int64_t nmax = (int64_t)p.kk * p.max_liz;
   if (nmax <= kThreads * 5)
-    return launch_mixed<5, 4>(p, i0, n, M, slot, extra, xslot, tau00, info, nb, tol, max_refine, s);
+    return launch_mixed<5, 8>(p, i0, n, M, slot, extra, xslot, tau00, info, nb, tol, max_refine, s);
   return launch_mixed<8, 4>(p, i0, n, M, slot, extra, xslot, tau00, info, nb, tol, max_refine, s);
 }
 
@@ -1442,7 +1442,7 @@ hipError_t lsms_mixed_persistent_grid(const lsms_prob_dev& p, int device, int* g
   int per_cu = 0;
   const int64_t nmax = (int64_t)p.kk * p.max_liz;
   if (nmax <= kThreads * 5)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_mixed_persistent_kernel<5, 4>, kThreads,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_mixed_persistent_kernel<5, 8>, kThreads,
                                                      mixed_smem_bytes());
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_mixed_persistent_kernel<8, 4>, kThreads,
@@ -1459,7 +1459,7 @@ hipError_t lsms_launch_mixed_persistent(const lsms_prob_dev& p, const lsms_gaunt
   if (p.n_inst <= 0) return hipSuccess;
   const int64_t nmax = (int64_t)p.kk * p.max_liz;
   if (nmax <= kThreads * 5)
-    return launch_mixed_persistent<5, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, tau00, info, nb, tol,
+    return launch_mixed_persistent<5, 8>(p, g, order, counter, work, slot_bytes, m_bytes, grid, tau00, info, nb, tol,
                                          max_refine, s);
   return launch_mixed_persistent<8, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, tau00, info, nb, tol,
                                        max_refine, s);
@@ -1476,7 +1476,7 @@ hipError_t lsms_gmres_grid(const lsms_prob_dev& p, int device, int* grid) {
   int per_cu = 0;
   const int64_t nmax = (int64_t)p.kk * p.max_liz;
   if (nmax <= kThreads * 5)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_gmres_persistent_kernel<5, 4>, kThreads,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_gmres_persistent_kernel<5, 8>, kThreads,
                                                      gmres_smem_bytes());
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_gmres_persistent_kernel<8, 4>, kThreads,
@@ -1493,7 +1493,7 @@ hipError_t lsms_launch_gmres(const lsms_prob_dev& p, const lsms_gaunt_dev& g, co
   if (p.n_inst <= 0) return hipSuccess;
   const int64_t nmax = (int64_t)p.kk * p.max_liz;
   if (nmax <= kThreads * 5)
-    return launch_gmres<5, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, seed, tau00, info, steps, nb,
+    return launch_gmres<5, 8>(p, g, order, counter, work, slot_bytes, m_bytes, grid, seed, tau00, info, steps, nb,
                               tol, max_cycles, m, s);
   return launch_gmres<8, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, seed, tau00, info, steps, nb, tol,
                             max_cycles, m, s);
