@@ -25,6 +25,8 @@ constexpr int kBMaxLm = 5;
 struct BuildSmem {
   double Y[kBuildChunk][kBMaxKK2];
   zd h[kBuildChunk][kBMaxL2 + 1];
+  double nlm[kBMaxL2 + 1][kBMaxL2 + 1];  // sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!)
+  double rcp[kBMaxL2 + 2];               // 1/k
   zd t[kBMaxSpecies][kBMaxLm];
   double coef[kBMaxNnz];
   int32_t rp[kBMaxKK * kBMaxKK + 1];
@@ -34,41 +36,41 @@ struct BuildSmem {
   int bad, bad_species;
 };
 
-// Real spherical harmonics Y_L''(r), l'' <= l2, of a nonzero vector r, by one
-// thread: cos(m phi) + i sin(m phi) as (x + i y)^m / rho^m, P_l^m by upward
-// recurrence in l from P_m^m = (2m-1)!! sin^m(theta).
-__device__ inline void ylm_all(int l2, double x, double y, double z, double* __restrict__ Y) {
+// Y_L''(r) for the l'' = m .. l2 of one order m >= 0 (both signs of m), of a
+// nonzero vector r: cos(m phi) + i sin(m phi) as ((x + i y)/rho)^m,
+// P_m^m = (2m-1)!! sin^m(theta) and upward recurrence in l; normalisation
+// constants and reciprocals from LDS (no divisions in the recurrence).
+__device__ inline void ylm_order(int l2, int m, double x, double y, double z, const BuildSmem& sb,
+                                 double* __restrict__ Y) {
   const double rho2 = x * x + y * y;
   const double r = sqrt(rho2 + z * z);
   const double rho = sqrt(rho2);
-  const double ct = z / r, st = rho / r;
-  const double cp = rho > 0.0 ? x / rho : 1.0, sp = rho > 0.0 ? y / rho : 0.0;
+  const double ir = 1.0 / r;
+  const double ct = z * ir, st = rho * ir;
+  const double irho = rho > 0.0 ? 1.0 / rho : 0.0;
+  const double cp = rho > 0.0 ? x * irho : 1.0, sp = rho > 0.0 ? y * irho : 0.0;
   double cm = 1.0, sm = 0.0, pmm = 1.0;
-  for (int m = 0; m <= l2; ++m) {
-    if (m > 0) {
-      const double c2 = cm * cp - sm * sp;
-      sm = sm * cp + cm * sp;
-      cm = c2;
-      pmm *= (2.0 * m - 1.0) * st;
-    }
-    double p_lm2 = 0.0, p_lm1 = 0.0;
-    for (int l = m; l <= l2; ++l) {
-      double pl;
-      if (l == m) pl = pmm;
-      else if (l == m + 1) pl = ct * (2.0 * m + 1.0) * p_lm1;
-      else pl = ((2.0 * l - 1.0) * ct * p_lm1 - (l + m - 1.0) * p_lm2) / (double)(l - m);
-      p_lm2 = p_lm1;
-      p_lm1 = pl;
-      double ratio = 1.0;  // (l-m)!/(l+m)!
-      for (int k = l - m + 1; k <= l + m; ++k) ratio /= (double)k;
-      const double nlm = sqrt((2.0 * l + 1.0) * ratio * 0.07957747154594767);  // 1/(4 pi)
-      if (m == 0) {
-        Y[l * l + l] = nlm * pl;
-      } else {
-        const double sc = 1.4142135623730951 * nlm * pl;
-        Y[l * l + l + m] = sc * cm;
-        Y[l * l + l - m] = sc * sm;
-      }
+  for (int k = 1; k <= m; ++k) {
+    const double c2 = cm * cp - sm * sp;
+    sm = sm * cp + cm * sp;
+    cm = c2;
+    pmm *= (2.0 * k - 1.0) * st;
+  }
+  double p_lm2 = 0.0, p_lm1 = 0.0;
+  for (int l = m; l <= l2; ++l) {
+    double pl;
+    if (l == m) pl = pmm;
+    else if (l == m + 1) pl = ct * (2.0 * m + 1.0) * p_lm1;
+    else pl = ((2.0 * l - 1.0) * ct * p_lm1 - (l + m - 1.0) * p_lm2) * sb.rcp[l - m];
+    p_lm2 = p_lm1;
+    p_lm1 = pl;
+    const double nlm = sb.nlm[l][m];
+    if (m == 0) {
+      Y[l * l + l] = nlm * pl;
+    } else {
+      const double sc = 1.4142135623730951 * nlm * pl;
+      Y[l * l + l + m] = sc * cm;
+      Y[l * l + l - m] = sc * sm;
     }
   }
 }
@@ -110,6 +112,13 @@ __device__ void build_setup(const lsms_prob_dev& p, const lsms_gaunt_dev& g, int
     sb.lof[q] = (int8_t)l_of(lpp);
     sb.coef[q] = g.coef[q];
   }
+  if (tid <= kBMaxL2 + 1) sb.rcp[tid] = tid > 0 ? 1.0 / (double)tid : 0.0;
+  if (tid < (kBMaxL2 + 1) * (kBMaxL2 + 1)) {
+    const int l = tid / (kBMaxL2 + 1), m = tid % (kBMaxL2 + 1);
+    double ratio = 1.0;  // (l-m)!/(l+m)!
+    for (int k = l - m + 1; k <= l + m; ++k) ratio /= (double)k;
+    sb.nlm[l][m] = m <= l ? sqrt((2.0 * l + 1.0) * ratio * 0.07957747154594767) : 0.0;  // 1/(4 pi)
+  }
   if (tid == 0) {
     sb.bad = 0;
     sb.bad_species = 0;
@@ -117,10 +126,12 @@ __device__ void build_setup(const lsms_prob_dev& p, const lsms_gaunt_dev& g, int
   __syncthreads();
 }
 
-// Block column j of M: phase A, one thread per LIZ row block of a chunk,
-// prepares Y_L''(R_ij) and h_l''(kappa R_ij); phase B sweeps the chunk's
-// kk x kk blocks with entry (L, L') of row block i at index L + kk (i + nb L'),
-// so consecutive threads write consecutive rows of one column.
+// Block column j of M, in chunks of kBuildChunk LIZ row blocks.  Phase A:
+// for each row block i of the chunk, 2 lmax + 2 threads: one per order
+// m = 0 .. 2 lmax of Y_L''(R_ij) and one for the Hankel functions
+// h_l''(kappa R_ij).  Phase B: each thread owns (row block,
+// L) pairs and sweeps the kk columns L', entry (L, L') of row block i at
+// index L + kk (i + nb L'), so consecutive threads write consecutive rows.
 template <int kNT>
 __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int inst, int j, zd* __restrict__ M, BuildSmem& sb) {
   const int tid = threadIdx.x;
@@ -135,48 +146,54 @@ __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int in
   const zd pref = zmake(4.0 * M_PI * kap.y, -4.0 * M_PI * kap.x);  // -4 pi i kappa
   for (int ib = 0; ib < nliz; ib += kBuildChunk) {
     const int nb = min(kBuildChunk, nliz - ib);
-    if (tid < nb) {
-      const int iw = ib + tid;
-      const int sp = spec[iw];
-      if (sp < 0 || sp >= p.n_species) sb.bad_species = 1;
-      sb.spec[tid] = (sp >= 0 && sp < p.n_species) ? sp : 0;
+    const int slots = l2 + 2;  // orders m = 0 .. l2, then the Hankel functions
+    for (int t = tid; t < slots * nb; t += kNT) {
+      const int il = t / slots, m = t - il * slots;
+      const int iw = ib + il;
+      if (m == 0) {
+        const int sp = spec[iw];
+        if (sp < 0 || sp >= p.n_species) sb.bad_species = 1;
+        sb.spec[il] = (sp >= 0 && sp < p.n_species) ? sp : 0;
+      }
       if (iw != j) {
         const double Rx = rel[3 * iw] - rjx, Ry = rel[3 * iw + 1] - rjy, Rz = rel[3 * iw + 2] - rjz;
-        const double R = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
-        if (R < 1e-8) {
-          sb.bad = 1;
+        const double R2 = Rx * Rx + Ry * Ry + Rz * Rz;
+        if (R2 < 1e-16) {
+          if (m == 0) sb.bad = 1;
+        } else if (m == l2 + 1) {
+          const double R = sqrt(R2);
+          hankel_all(l2, zmake(kap.x * R, kap.y * R), sb.h[il]);
         } else {
-          ylm_all(l2, Rx, Ry, Rz, sb.Y[tid]);
-          hankel_all(l2, zmake(kap.x * R, kap.y * R), sb.h[tid]);
+          ylm_order(l2, m, Rx, Ry, Rz, sb, sb.Y[il]);
         }
       }
     }
     __syncthreads();
     const int per_col = nb * kk;
-    for (int q = tid; q < per_col * kk; q += kNT) {
-      const int Lp = q / per_col;
-      const int rem = q - Lp * per_col;
-      const int il = rem / kk;
-      const int L = rem - il * kk;
+    for (int t = tid; t < per_col; t += kNT) {
+      const int il = t / kk;
+      const int L = t - il * kk;
       const int iw = ib + il;
-      zd val;
+      zd* out = M + (int64_t)(kk * j) * N + (int64_t)kk * iw + L;
       if (iw == j) {
-        val = zmake(L == Lp ? 1.0 : 0.0, 0.0);
+        for (int Lp = 0; Lp < kk; ++Lp) out[(int64_t)Lp * N] = zmake(L == Lp ? 1.0 : 0.0, 0.0);
       } else {
-        double sr = 0.0, si = 0.0;
-        const int pidx = L + kk * Lp;
-        const int e0 = sb.rp[pidx], e1 = sb.rp[pidx + 1];
-        for (int k = e0; k < e1; ++k) {
-          const double cy = sb.coef[k] * sb.Y[il][sb.lpp[k]];
-          const zd h = sb.h[il][sb.lof[k]];
-          sr += cy * h.x;
-          si += cy * h.y;
+        const zd tl = sb.t[sb.spec[il]][l_of(L)];
+        const zd tp = zmul(tl, pref);
+        for (int Lp = 0; Lp < kk; ++Lp) {
+          double sr = 0.0, si = 0.0;
+          const int pidx = L + kk * Lp;
+          const int e0 = sb.rp[pidx], e1 = sb.rp[pidx + 1];
+          for (int k = e0; k < e1; ++k) {
+            const double cy = sb.coef[k] * sb.Y[il][sb.lpp[k]];
+            const zd h = sb.h[il][sb.lof[k]];
+            sr += cy * h.x;
+            si += cy * h.y;
+          }
+          const zd tg = zmul(tp, zmake(sr, si));
+          out[(int64_t)Lp * N] = zmake(-tg.x, -tg.y);
         }
-        const zd G = zmul(pref, zmake(sr, si));
-        const zd tg = zmul(sb.t[sb.spec[il]][l_of(L)], G);
-        val = zmake(-tg.x, -tg.y);
       }
-      M[(int64_t)(kk * j + Lp) * N + (int64_t)kk * iw + L] = val;
     }
     __syncthreads();
   }

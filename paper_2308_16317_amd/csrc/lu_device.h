@@ -412,8 +412,10 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& A, int 
   }
   {
     const int kend = 16 * rt + 16;
-    C bn[2][4];
+    C bn[2][4], xn[4];
     trsm_load_chunk(A, c, kNB, 0, lk, bcol, cok, bn);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xn[j] = xg[row * kNB + 4 * lk + j];
     for (int kc = 0; kc < kend; kc += 16) {
       C b[2][4], x[4];
 #pragma unroll
@@ -421,8 +423,12 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& A, int 
 #pragma unroll
         for (int j = 0; j < 4; ++j) b[t][j] = bn[t][j];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) x[j] = xg[row * kNB + kc + 4 * lk + j];
-      if (kc + 16 < kend) trsm_load_chunk(A, c, kNB, kc + 16, lk, bcol, cok, bn);
+      for (int j = 0; j < 4; ++j) x[j] = xn[j];
+      if (kc + 16 < kend) {
+        trsm_load_chunk(A, c, kNB, kc + 16, lk, bcol, cok, bn);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xn[j] = xg[row * kNB + kc + 16 + 4 * lk + j];
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -461,15 +467,28 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& A, int 
   {
     const bool rok = row < wb;
     const C* lrow = A.base + A.phys(c + kNB + (rok ? row : 0)) * A.N + A.phys(c) + 4 * lk;
+    C ln[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      C v;
+      v.x = 0;
+      v.y = 0;
+      if (rok) v = lrow[j];
+      ln[j] = v;
+    }
     for (int kc = 0; kc < kNB; kc += 16) {
       C l[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        C v;
-        v.x = 0;
-        v.y = 0;
-        if (rok) v = lrow[kc + j];
-        l[j] = v;
+      for (int j = 0; j < 4; ++j) l[j] = ln[j];
+      if (kc + 16 < kNB) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          C v;
+          v.x = 0;
+          v.y = 0;
+          if (rok) v = lrow[kc + 16 + j];
+          ln[j] = v;
+        }
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -503,11 +522,21 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& A, int 
   {
     const int kend = min(wb, 16 * rt + 16);
     const C* xb = xg + kNB * kNB;
+    C xn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xn[j] = xb[row * kNB + 4 * lk + j];
     for (int kc = 0; kc < kend; kc += 16) {
+      C xc[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xc[j] = xn[j];
+      if (kc + 16 < kend) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xn[j] = xb[row * kNB + kc + 16 + 4 * lk + j];
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = kc + 4 * lk + j;
-        const C x = xb[row * kNB + k];
+        const C x = xc[j];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           const C b = U2[kNB + k][16 * (ct0 + t) + li];
