@@ -133,7 +133,8 @@ __device__ void build_setup(const lsms_prob_dev& p, const lsms_gaunt_dev& g, int
 // L) pairs and sweeps the kk columns L', entry (L, L') of row block i at
 // index L + kk (i + nb L'), so consecutive threads write consecutive rows.
 template <int kNT>
-__device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int inst, int j, zd* __restrict__ M, BuildSmem& sb) {
+__device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int inst, int j, zd* __restrict__ M,
+                                                  BuildSmem& sb, zf* __restrict__ M32 = nullptr) {
   const int tid = threadIdx.x;
   const int64_t a = p.liz_off[inst];
   const int nliz = (int)(p.liz_off[inst + 1] - a);
@@ -174,9 +175,14 @@ __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int in
       const int il = t / kk;
       const int L = t - il * kk;
       const int iw = ib + il;
-      zd* out = M + (int64_t)(kk * j) * N + (int64_t)kk * iw + L;
+      const int64_t o0 = (int64_t)(kk * j) * N + (int64_t)kk * iw + L;
+      zd* out = M + o0;
+      zf* out32 = M32 ? M32 + o0 : nullptr;
       if (iw == j) {
-        for (int Lp = 0; Lp < kk; ++Lp) out[(int64_t)Lp * N] = zmake(L == Lp ? 1.0 : 0.0, 0.0);
+        for (int Lp = 0; Lp < kk; ++Lp) {
+          out[(int64_t)Lp * N] = zmake(L == Lp ? 1.0 : 0.0, 0.0);
+          if (out32) out32[(int64_t)Lp * N] = zmake(L == Lp ? 1.f : 0.f, 0.f);
+        }
       } else {
         const zd tl = sb.t[sb.spec[il]][l_of(L)];
         const zd tp = zmul(tl, pref);
@@ -192,6 +198,7 @@ __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int in
           }
           const zd tg = zmul(tp, zmake(sr, si));
           out[(int64_t)Lp * N] = zmake(-tg.x, -tg.y);
+          if (out32) out32[(int64_t)Lp * N] = zmake((float)-tg.x, (float)-tg.y);
         }
       }
     }
@@ -200,11 +207,12 @@ __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int in
 }
 
 // Out-of-line form for kernels that also eliminate (separate register
-// allocation for the build and the factorisation).
+// allocation for the build and the factorisation); M32, if given, receives an
+// FP32 copy of the column at the same positions.
 template <int kNT>
 __device__ __noinline__ void build_column(const lsms_prob_dev& p, int inst, int j, zd* __restrict__ M,
-                                          BuildSmem& sb) {
-  build_column_body<kNT>(p, inst, j, M, sb);
+                                          BuildSmem& sb, zf* __restrict__ M32 = nullptr) {
+  build_column_body<kNT>(p, inst, j, M, sb, M32);
 }
 
 }  // namespace lsms

@@ -924,12 +924,16 @@ __device__ void panel_factor(const Mat<typename Prec<R>::C>& A, int c, int w, in
 // written back when store_u, and the panel pivots stored at ipiv_out[column]
 // (if non-null).  A panel wider than 64 needs xg, room for two 64 x 64
 // blocks (the inverses of its diagonal blocks); without xg panels are at most
-// 64 wide.  Ends after a barrier.
+// 64 wide.  With xcache, the inverse of every (at most 64-column) diagonal
+// block of L, in panel order, is kept at xcache + 64*64*q for block q
+// (panels that have trailing columns only).  Ends after a barrier.
 template <typename R, int kR, int kWL>
 __device__ void eliminate(const Mat<typename Prec<R>::C>& A, int c_begin, int ncols, int plim, int nb,
-                          bool store_u, int32_t* ipiv_out, typename Prec<R>::C* xg, LuSmem<R>& sh) {
+                          bool store_u, int32_t* ipiv_out, typename Prec<R>::C* xg, LuSmem<R>& sh,
+                          typename Prec<R>::C* xcache = nullptr) {
   const int N = (int)A.N;
-  if (!xg) nb = min(nb, kNB);
+  if (!xg && !xcache) nb = min(nb, kNB);
+  int blk = 0;
   for (int c = c_begin; c < ncols; c += nb) {
     const int w = min(nb, ncols - c);
     panel_factor<R, kR, kWL>(A, c, w, plim, store_u, sh);
@@ -939,19 +943,23 @@ __device__ void eliminate(const Mat<typename Prec<R>::C>& A, int c_begin, int nc
     if (c + w < N) {
       if (w <= kNB) {
         invert_unit_lower<R>(A, c, w, sh);
+        if (xcache) save_x<R>(sh, xcache + (int64_t)blk * kNB * kNB);
+        blk += 1;
         for (int s0 = c + w; s0 < N; s0 += kSW) {
           const int sw = min(kSW, N - s0);
           trsm_strip<R>(A, c, w, s0, sw, store_u, sh);
           update_strip<R>(A, c, w, s0, sw, sh.U);
         }
       } else {
+        typename Prec<R>::C* xp = xcache ? xcache + (int64_t)blk * kNB * kNB : xg;
+        blk += 2;
         invert_unit_lower<R>(A, c, kNB, sh);
-        save_x<R>(sh, xg);
+        save_x<R>(sh, xp);
         invert_unit_lower<R>(A, c + kNB, w - kNB, sh);
-        save_x<R>(sh, xg + kNB * kNB);
+        save_x<R>(sh, xp + kNB * kNB);
         for (int s0 = c + w; s0 < N; s0 += kSW) {
           const int sw = min(kSW, N - s0);
-          trsm2_strip<R>(A, c, w, s0, sw, store_u, xg, sh);
+          trsm2_strip<R>(A, c, w, s0, sw, store_u, xp, sh);
           update_strip<R>(A, c, w, s0, sw, ustrip2(sh));
         }
       }

@@ -242,8 +242,24 @@ struct MixedBufs {
   zd* Y;          // N x kp FP64 solution, internal rows
   int32_t* ipiv;  // N pivot rows
   zd* xg;         // two 64 x 64 blocks (FP64, or FP32 in the first half) for wide panels
+  zf* lcache;     // inverses of the 64-column diagonal blocks of L (factorisation order)
+  zf* ucache;     // inverses of the 64-row diagonal blocks of U (filled by the first solve)
   int kp;         // 16 or 32: kk rounded up to a multiple of 16
 };
+
+// Number of cached diagonal blocks of L in the panels of [0, c) (panels of
+// nb columns over [0, Nd); a panel wider than 64 has two).
+__device__ inline int lower_blocks_before(int c, int Nd, int nb) {
+  int n = 0;
+  for (int q = 0; q < c && q < Nd; q += nb) n += (min(nb, Nd - q) + kNB - 1) / kNB;
+  return n;
+}
+
+// sh.X := the 64 x 64 block at src.
+__device__ inline void load_x(const zf* __restrict__ src, LuSmem<float>& sh) {
+  for (int q = threadIdx.x; q < kNB * kNB; q += kLuThreads) sh.X[q / kNB][q % kNB] = src[q];
+  __syncthreads();
+}
 
 struct MixedSmem {
   LuSmem<float> f;
@@ -383,7 +399,7 @@ __device__ void rhs_update(const Mat<zf>& A, const MixedBufs& b, int r0, int s, 
 // panel wider than 64 is then taken in 64-column blocks, its own L being in
 // the panel's final row order), then backward with the upper factor in
 // 64-row blocks.
-__device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, MixedSmem& ms) {
+__device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, bool have_uinv, MixedSmem& ms) {
   typedef Prec<float>::V4 V4;
   LuSmem<float>& sh = ms.f;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -409,9 +425,10 @@ __device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, MixedSme
       }
     }
     __syncthreads();
-    for (int c2 = c; c2 < c + w; c2 += kNB) {
+    int blk = pi + 1 < npan ? lower_blocks_before(c, Nd, nb) : lower_blocks_before(Nd, Nd, nb);
+    for (int c2 = c; c2 < c + w; c2 += kNB, ++blk) {
       const int w2 = min(kNB, c + w - c2);
-      invert_unit_lower<float>(A, c2, w2, sh);
+      load_x(b.lcache + (int64_t)blk * kNB * kNB, sh);
       tri_apply(b, c2, w2, sh);
       if (c2 + w2 < N) rhs_update(A, b, c2, w2, c2 + w2, sh);
     }
@@ -445,7 +462,13 @@ __device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, MixedSme
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       ms.part[split][16 * rt + Prec<float>::drow(r, lq)][16 * ct + li] = zmake(ar[r], ai[r]);
-    invert_upper<float>(A, c, w, sh);  // starts and ends with a barrier
+    if (have_uinv) {
+      __syncthreads();
+      load_x(b.ucache + (int64_t)pi * kNB * kNB, sh);
+    } else {
+      invert_upper<float>(A, c, w, sh);  // starts and ends with a barrier
+      save_x<float>(sh, b.ucache + (int64_t)pi * kNB * kNB);
+    }
     for (int q = tid; q < kNB * 32; q += kLuThreads) {
       const int i = q / 32, j = q % 32;
       zf v = zmake(0.f, 0.f);
@@ -568,7 +591,8 @@ __device__ void residual(const Mat<zd>& A, const MixedBufs& b) {
 // unmodified unless the FP64 fallback runs).  Ends after a barrier.
 template <int kR, int kWL>
 __device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd* A64, const MixedBufs& b, double* tau00,
-                               int32_t* info, int nb, double tol, int max_refine, unsigned char* smem) {
+                               int32_t* info, int nb, double tol, int max_refine, bool have_a32,
+                               unsigned char* smem) {
   MixedSmem& ms = *reinterpret_cast<MixedSmem*>(smem);
   LuSmem<float>& sh = ms.f;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -585,14 +609,19 @@ __device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd
   F.N = N;
   F.Nd = Nd;
   F.kk = kk;
-  for (int64_t q = tid; q < (int64_t)N * N; q += kLuThreads) {
-    const zd x = A64[q];
-    b.A32[q] = zmake((float)x.x, (float)x.y);
+  if (!have_a32) {
+    for (int64_t q = tid; q < (int64_t)N * N; q += kLuThreads) {
+      const zd x = A64[q];
+      b.A32[q] = zmake((float)x.x, (float)x.y);
+    }
   }
   if (tid == 0) sh.info = 0;
   __syncthreads();
-  eliminate<float, kR, kWL>(F, 0, Nd, Nd, nb, true, b.ipiv, reinterpret_cast<zf*>(b.xg), sh);
+  eliminate<float, kR, kWL>(F, 0, Nd, Nd, nb, true, b.ipiv, reinterpret_cast<zf*>(b.xg), sh, b.lcache);
   eliminate<float, kR, kWL>(F, Nd, N, N, nb, true, b.ipiv, reinterpret_cast<zf*>(b.xg), sh);
+  // the central block's unit lower inverse (it has no trailing columns)
+  invert_unit_lower<float>(F, Nd, N - Nd, sh);
+  save_x<float>(sh, b.lcache + (int64_t)lower_blocks_before(Nd, Nd, nb) * kNB * kNB);
   bool ok = __builtin_amdgcn_readfirstlane(sh.info) == 0;
   if (ok) {
     for (int q = tid; q < N * b.kp; q += kLuThreads) {
@@ -600,7 +629,7 @@ __device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd
       b.z[q] = zmake((j < kk && v == Nd + j) ? 1.f : 0.f, 0.f);
     }
     __syncthreads();
-    solve_f32(F, b, nb, ms);
+    solve_f32(F, b, nb, false, ms);
     for (int q = tid; q < N * b.kp; q += kLuThreads) {
       const zf x = b.z[q];
       b.Y[q] = zmake((double)x.x, (double)x.y);
@@ -610,7 +639,7 @@ __device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd
     double dprev = 0.0;
     for (int it = 0; it < max_refine && !conv; ++it) {
       residual(A, b);
-      solve_f32(F, b, nb, ms);
+      solve_f32(F, b, nb, true, ms);
       double dn = 0.0, yn = 0.0;
       for (int q = tid; q < N * b.kp; q += kLuThreads) {
         const int v = q / b.kp, j = q % b.kp;
@@ -686,12 +715,18 @@ size_t mixed_smem_bytes() {
 // [FP32 matrix | z | Y | pivots | X blocks], each 256-byte aligned, for
 // matrices up to nmax.
 constexpr int64_t kXgBytes = 2 * kNB * kNB * 16;
+// inverse-block caches: L blocks follow the panels (at most one per 16
+// columns for panel widths >= 16), U blocks the 64-row blocks
+__host__ __device__ inline int64_t mixed_lcache_bytes(int64_t nmax) { return (nmax / 16 + 2) * kNB * kNB * 8; }
+__host__ __device__ inline int64_t mixed_ucache_bytes(int64_t nmax) {
+  return ((nmax + kNB - 1) / kNB + 1) * kNB * kNB * 8;
+}
 __host__ __device__ inline int64_t mixed_extra_bytes(int64_t nmax, int kp) {
   const int64_t a = ((nmax * nmax * 8) + 255) & ~(int64_t)255;
   const int64_t z = ((nmax * kp * 8) + 255) & ~(int64_t)255;
   const int64_t y = ((nmax * kp * 16) + 255) & ~(int64_t)255;
   const int64_t pv = ((nmax * 4) + 255) & ~(int64_t)255;
-  return a + z + y + pv + kXgBytes;
+  return a + z + y + pv + kXgBytes + mixed_lcache_bytes(nmax) + mixed_ucache_bytes(nmax);
 }
 
 __device__ inline MixedBufs mixed_bufs(unsigned char* base, int64_t nmax, int kp) {
@@ -704,6 +739,8 @@ __device__ inline MixedBufs mixed_bufs(unsigned char* base, int64_t nmax, int kp
   b.Y = reinterpret_cast<zd*>(base + a + z);
   b.ipiv = reinterpret_cast<int32_t*>(base + a + z + y);
   b.xg = reinterpret_cast<zd*>(base + a + z + y + (((nmax * 4) + 255) & ~(int64_t)255));
+  b.lcache = reinterpret_cast<zf*>(reinterpret_cast<unsigned char*>(b.xg) + kXgBytes);
+  b.ucache = reinterpret_cast<zf*>(reinterpret_cast<unsigned char*>(b.lcache) + mixed_lcache_bytes(nmax));
   b.kp = kp;
   return b;
 }
@@ -727,7 +764,7 @@ __global__ __launch_bounds__(kThreads) void tau00_mixed_kernel(lsms_prob_dev p, 
   const int kp = p.kk > 16 ? 32 : 16;
   const MixedBufs b = mixed_bufs(extra + (int64_t)blockIdx.x * xslot, (int64_t)p.kk * p.max_liz, kp);
   mixed_instance<kR, kWL>(p, inst, reinterpret_cast<zd*>(Mb) + (int64_t)blockIdx.x * slot, b, tau00, info, nb,
-                          tol, max_refine, smem_raw);
+                          tol, max_refine, false, smem_raw);
 }
 
 // Persistent form, as tau00_persistent_kernel with the precision form per
@@ -752,12 +789,12 @@ __global__ __launch_bounds__(kThreads) void tau00_mixed_persistent_kernel(
     if (status == 0) {
       const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
       build_setup<kThreads>(p, g, inst, sb);
-      for (int j = 0; j < nliz; ++j) build_column<kThreads>(p, inst, j, M, sb);
+      for (int j = 0; j < nliz; ++j) build_column<kThreads>(p, inst, j, M, sb, b.A32);
       status = __builtin_amdgcn_readfirstlane(sb.bad_species ? -3 : (sb.bad ? -2 : 0));
       __syncthreads();
     }
     if (status == 0) {
-      mixed_instance<kR, kWL>(p, inst, M, b, tau00, info, nb, tol, max_refine, smem_raw);
+      mixed_instance<kR, kWL>(p, inst, M, b, tau00, info, nb, tol, max_refine, true, smem_raw);
     } else {
       fill_nan(p, inst, tau00);
       if (threadIdx.x == 0) info[inst] = status;

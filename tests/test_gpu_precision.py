@@ -175,3 +175,39 @@ def test_ir_rejected_where_unsupported(P, h):
                 P.Opts(P.PREC_FP32_IR, 0, 0, 0, 0, 1, 0.0), P.Opts(7, 0, 0, 0, 0, 0, 0.0)):
         b = ctypes.c_size_t()
         assert L.lsms_workspace_size(h.ptr, ctypes.byref(ps), ctypes.byref(bad), 1, ctypes.byref(b)) == -3
+
+
+def test_ir_lmax4_full_size(P, h):
+    # the config-2 systems at lmax = 4 (N = 3375), both contour ends and
+    # mid-contour, FP64 path and precision form against the oracle
+    torch = _torch()
+    w = inputs.subset(inputs.config3(), [0, 15, 31])
+    ref, rinfo = oracle.tau00_workload(w)
+    assert np.all(rinfo == 0)
+    prob = P.problem_for_workload(h, w)
+    for prec, bar in ((P.PREC_FP64, TOL_FP64), (P.PREC_FP32_IR, TOL_IR)):
+        opts = P.Opts(prec, 0, 0, P.PERSISTENT, 0, 0, 0.0)
+        work = torch.empty(P.workspace_size(h, prob, 0, opts), dtype=torch.uint8, device="cuda")
+        print(f"lmax=4 N=3375 precision={prec}", flush=True)
+        tau, info = P.tau00_solve(h, prob, work, opts)
+        torch.cuda.synchronize()
+        info = info.cpu().numpy()
+        err = rel_f(tau.cpu().numpy(), ref)
+        print("lmax=4 N=3375", prec, "info", info, "rel_F", err)
+        assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK))
+        assert err.max() <= bar
+        del work
+
+
+def test_ir_error_per_energy(P, h):
+    # one site of the benchmark alloy at all 32 contour energies: the
+    # precision form's error per energy point
+    w = inputs.subset(inputs.config2(), np.arange(32) + 32 * 77)
+    ref, _ = oracle.tau00_workload(w)
+    tau, info = _solve(P, h, w, flags=P.PERSISTENT)
+    err = rel_f(tau, ref)
+    E = w.energies[w.e_idx]
+    for e, x, i in zip(E, err, info):
+        print(f"E = {e.real:+.4f}{e.imag:+.4f}i  rel_F = {x:.2e}  info = {i}")
+    assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK))
+    assert err.max() <= TOL_IR
