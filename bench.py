@@ -28,7 +28,7 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per instance moved by the fused kernel (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, each scaled by the counts of a plain copy of known size), valid
 # only for the kernel sources whose hash is given; null otherwise.
-TRAFFIC_PER_INSTANCE = {("fp64", "4fb2f07e9ebdcc6f"): 2.99e9}
+TRAFFIC_PER_INSTANCE = {("fp64", "032be228809eab48"): 2.09e9}
 KERNEL_SOURCES = ("kkr_device.h", "lu_device.h", "lu_fp64.hip", "lsms_common.h")
 
 
@@ -66,6 +66,80 @@ def cpu_baseline(w, n_threads: int):
                       f"{dt:.1f} s wall"}
 
 
+def rel_f_rows(a, b):
+    import torch
+
+    return (torch.linalg.vector_norm(a - b, dim=1) / torch.linalg.vector_norm(b, dim=1)).max().item()
+
+
+def time_forms(args, P, h, w, liz, energy, e_idx, delta, max_liz, tau64, fp64_rate):
+    """The precision and learned forms on the same instances (one warm-up and
+    one timed pass each, persistent launch), with their speedup over the FP64
+    path and the largest per-instance deviation of their tau00 from it."""
+    import torch
+
+    import inputs
+    from paper_2308_16317_amd import learned
+
+    prob = P.Problem(w.lmax, liz["liz_off"], liz["pos"], liz["species"], energy, e_idx, delta, max_liz=max_liz)
+    res = {"fp64": {"solves_per_s": fp64_rate, "reference": "the FP64 path of this run"}}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    try:
+        opts = P.Opts(P.PREC_FP32_IR, args.nb, 0, P.PERSISTENT, 0, 0, args.tol)
+        work = torch.empty(P.workspace_size(h, prob, 0, opts), dtype=torch.uint8, device="cuda")
+        t32 = torch.empty_like(tau64)
+        i32 = torch.empty(w.n_inst, dtype=torch.int32, device="cuda")
+        _, dt = timed(lambda: P.tau00_solve(h, prob, work, opts, tau=t32, info=i32))
+        del work
+        fb = int((i32 == P.INFO_FP64_FALLBACK).sum().item())
+        res["fp32ir"] = {"solves_per_s": w.n_inst / dt, "speedup_vs_fp64": w.n_inst / dt / fp64_rate,
+                         "max_rel_F_vs_fp64": rel_f_rows(t32, tau64), "fp64_fallbacks": fb,
+                         "errors": int((i32 != 0).sum().item()) - fb,
+                         "peak_tflops": FP32_PEAK_TFLOPS}
+        log(f"[bench] fp32ir: {res['fp32ir']}")
+    except Exception as e:  # reported, not fatal: the FP64 line stands on its own
+        res["fp32ir"] = {"error": repr(e)}
+    if args.forms == "all":
+        try:
+            t0 = time.perf_counter()
+            net, losses = learned.train_on(h, inputs.config2(seed=1), inputs.A_LAT, inputs.mlp_init(seed=0),
+                                           steps=3000)
+            torch.cuda.synchronize()
+            t_train = time.perf_counter() - t0
+            restart = 8
+            work = torch.empty(P.gmres_workspace_size(h, prob, restart), dtype=torch.uint8, device="cuda")
+            tl = torch.empty(w.n_inst * 256, dtype=torch.complex128, device="cuda")
+            il = torch.empty(w.n_inst, dtype=torch.int32, device="cuda")
+            sl = torch.empty(w.n_inst, dtype=torch.int32, device="cuda")
+
+            def run():
+                feat = P.mlp_features(h, prob, inputs.A_LAT)
+                seed = net.seeds(feat)
+                return P.tau00_gmres(h, prob, work, seed=seed, restart=restart, max_cycles=20, tol=1e-12, tau=tl,
+                                     info=il, steps=sl)
+
+            _, dt = timed(run)
+            fb = int((il == P.INFO_LU_FALLBACK).sum().item())
+            res["learned"] = {"solves_per_s": w.n_inst / dt, "speedup_vs_fp64": w.n_inst / dt / fp64_rate,
+                              "max_rel_F_vs_fp64": rel_f_rows(tl.view(-1, 256), tau64), "lu_fallbacks": fb,
+                              "errors": int((il != 0).sum().item()) - fb,
+                              "mean_gmres_block_steps": float(sl.double().mean().item()),
+                              "train_loss_first_last": [losses[0], float(np.mean(losses[-50:]))],
+                              "train_seconds": t_train, "restart": restart}
+            log(f"[bench] learned: {res['learned']}")
+        except Exception as e:
+            res["learned"] = {"error": repr(e)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +155,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=1024, help="instances per build/LU launch (chunked)")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--n-inst", type=int, default=0, help="limit the batch (0 = all 8192)")
+    ap.add_argument("--forms", choices=["none", "fp32ir", "all"], default="all",
+                    help="also time the other forms on the same instances (persistent launch) and report them "
+                         "with their speedup over the FP64 path and their deviation from it")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     args = ap.parse_args()
@@ -219,6 +296,8 @@ def main():
                      "kernel": kernel, "ms_per_launch": float(np.mean(lu_ms)),
                      "instances_per_launch": chunk},
     }
+    if args.forms != "none" and args.precision == "fp64" and args.mode != "chunked":
+        out["forms"] = time_forms(args, P, h, w, liz, energy, e_idx, delta, max_liz, tau, n_inst * args.steps / dt)
     if not args.no_cpu:
         nthr = args.cpu_threads or min(16, os.cpu_count() or 1)
         log(f"[bench] cpu baseline: oracle on {nthr} threads")
