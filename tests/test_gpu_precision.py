@@ -211,3 +211,43 @@ def test_ir_error_per_energy(P, h):
         print(f"E = {e.real:+.4f}{e.imag:+.4f}i  rel_F = {x:.2e}  info = {i}")
     assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK))
     assert err.max() <= TOL_IR
+
+
+def test_ir_graph_replay_and_autotune(P, h):
+    # the batching form with the precision form: persistent launch captured
+    # once into a hipGraph and replayed, with eager work and an input change
+    # between replays, every replay checked; then the autotuner on it
+    torch = _torch()
+    w = inputs.subset(inputs.config4(n_inst=1024), [3, 4, 5, 6, 900, 901])
+    ref, _ = oracle.tau00_workload(w)
+    w2 = inputs.subset(inputs.config4(n_inst=1024), [3, 4, 5, 6, 900, 901])
+    w2.e_idx = (w2.e_idx + 7) % 32
+    ref2, _ = oracle.tau00_workload(w2)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        prob = P.problem_for_workload(h, w)
+        opts = P.Opts(P.PREC_FP32_IR, 0, 0, P.PERSISTENT | P.GRAPH, 0, 0, 0.0)
+        work = torch.empty(P.workspace_size(h, prob, 0, opts), dtype=torch.uint8, device="cuda")
+        tau = torch.empty(prob.n_inst * 256, dtype=torch.complex128, device="cuda")
+        info = torch.empty(prob.n_inst, dtype=torch.int32, device="cuda")
+        for rep in range(4):
+            if rep == 2:
+                prob.e_idx.copy_(torch.as_tensor(w2.e_idx, device="cuda"))
+            tau.fill_(0)
+            t, i = P.tau00_solve(h, prob, work, opts, tau=tau, info=info)
+            s.synchronize()
+            junk = torch.randn(1000, device="cuda").sum()
+            s.synchronize()
+            iv = i.cpu().numpy()
+            assert np.all((iv == 0) | (iv == P.INFO_FP64_FALLBACK))
+            err = rel_f(t.cpu().numpy(), ref if rep < 2 else ref2)
+            assert err.max() <= TOL_IR, (rep, err.max())
+        del junk
+        prob.e_idx.copy_(torch.as_tensor(w.e_idx, device="cuda"))
+        o2 = P.Opts(P.PREC_FP32_IR, 0, 0, P.PERSISTENT, 0, 0, 0.0)
+        best, ms = P.autotune(h, prob, work, o2)
+        print("precision-form autotune", best, ms)
+        assert best in (32, 64, 96, 128) and all(v > 0 for v in ms.values())
+        t, i = P.tau00_solve(h, prob, work, o2)
+        s.synchronize()
+        assert rel_f(t.cpu().numpy(), ref).max() <= TOL_IR
