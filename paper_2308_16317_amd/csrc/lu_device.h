@@ -76,13 +76,35 @@ struct LuSmem {
   int gj_piv;
 };
 
+// Pointers into the matrix reach the kernels as generic pointers; the hot
+// loops cast them to the global address space so that they compile to
+// global (not flat) memory instructions, whose completion is tracked apart
+// from LDS accesses (a flat load also counts as an LDS access, so every LDS
+// wait would also wait for the loads issued ahead).
+// The qualifiers exist only in the device pass; the host pass sees plain
+// pointers.
+#ifdef __HIP_DEVICE_COMPILE__
+#define LSMS_GLOBAL __attribute__((address_space(1)))
+#define LSMS_LDS __attribute__((address_space(3)))
+#else
+#define LSMS_GLOBAL
+#define LSMS_LDS
+#endif
+
+template <typename T>
+__device__ __forceinline__ LSMS_GLOBAL T* glb(T* p) {
+  return (LSMS_GLOBAL T*)p;
+}
+
 template <typename C>
 struct Mat {
-  C* base;
+  LSMS_GLOBAL C* base;  // global memory (see glb above)
   int64_t N;
   int Nd, kk;
   __device__ __forceinline__ int64_t phys(int v) const { return v < Nd ? (int64_t)v + kk : (int64_t)(v - Nd); }
-  __device__ __forceinline__ C* ptr(int r, int c) const { return base + phys(r) * N + phys(c); }
+  __device__ __forceinline__ LSMS_GLOBAL C* ptr(int r, int c) const {
+    return base + phys(r) * N + phys(c);
+  }
 };
 
 // The 128 x kSW view of sh.X and sh.U (contiguous), holding the U12 strip
@@ -104,8 +126,9 @@ __device__ __forceinline__ bool better(R ob, int oi, R b, int i) {
 // Kept out of line (with the triangle inverses and apply_swaps) so that the
 // register allocator treats the panel phase and the trailing update apart.
 template <typename R, int kR, int kWL>
-__device__ __noinline__ void leaf_factor(const Mat<typename Prec<R>::C>& A, int c, int w, int lc, int plim,
+__device__ __noinline__ void leaf_factor(const Mat<typename Prec<R>::C>& Ain, int c, int w, int lc, int plim,
                                          LuSmem<R>& sh) {
+  const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
   typedef typename Prec<R>::C C;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = (int)A.N;
@@ -115,7 +138,7 @@ __device__ __noinline__ void leaf_factor(const Mat<typename Prec<R>::C>& A, int 
   for (int q = 0; q < kR; ++q) {
     const int v = lc + tid + kLuThreads * q;
     if (v < N) {
-      const C* row = A.ptr(v, lc);
+      const auto row = A.ptr(v, lc);
 #pragma unroll
       for (int k = 0; k < kWL; ++k) a[q][k] = (k < wl) ? row[k] : zmake(R(0), R(0));
     } else {
@@ -251,7 +274,7 @@ __device__ __noinline__ void leaf_factor(const Mat<typename Prec<R>::C>& A, int 
   for (int q = 0; q < kR; ++q) {
     const int v = lc + tid + kLuThreads * q;
     if (v < N) {
-      C* row = A.ptr(v, lc);
+      const auto row = A.ptr(v, lc);
 #pragma unroll
       for (int k = 0; k < kWL; ++k)
         if (k < wl) row[k] = a[q][k];
@@ -284,7 +307,8 @@ __device__ __noinline__ void leaf_factor(const Mat<typename Prec<R>::C>& A, int 
 // staged first in sh.U; zero outside [0, s)^2.  Eight lanes per column: lane
 // p of a column accumulates the terms k = p (mod 8) of each row's dot product.
 template <typename R>
-__device__ __noinline__ void invert_unit_lower(const Mat<typename Prec<R>::C>& A, int r0, int s, LuSmem<R>& sh) {
+__device__ __noinline__ void invert_unit_lower(const Mat<typename Prec<R>::C>& Ain, int r0, int s, LuSmem<R>& sh) {
+  const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
   typedef typename Prec<R>::C C;
   const int tid = threadIdx.x;
   for (int q = tid; q < kNB * kNB; q += kLuThreads) {
@@ -332,7 +356,8 @@ __device__ __noinline__ void invert_unit_lower(const Mat<typename Prec<R>::C>& A
 // solves U x = e_j from the bottom: x_j = 1/U_jj, x_i = -(sum_{k=i+1..j}
 // U_ik x_k) / U_ii for i < j; eight lanes per column as in invert_unit_lower.
 template <typename R>
-__device__ __noinline__ void invert_upper(const Mat<typename Prec<R>::C>& A, int r0, int s, LuSmem<R>& sh) {
+__device__ __noinline__ void invert_upper(const Mat<typename Prec<R>::C>& Ain, int r0, int s, LuSmem<R>& sh) {
+  const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
   typedef typename Prec<R>::C C;
   const int tid = threadIdx.x;
   for (int q = tid; q < kNB * kNB; q += kLuThreads) {
@@ -385,8 +410,9 @@ __device__ __noinline__ void invert_upper(const Mat<typename Prec<R>::C>& A, int
 // The result goes to the 128-row view of sh.X and sh.U (rows >= w zero) and,
 // if `store`, to A.  Sixteen output tiles per 64-row half, two per wave.
 template <typename R>
-__device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& A, int c, int w, int s0, int sw,
+__device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, int c, int w, int s0, int sw,
                                          bool store, const typename Prec<R>::C* __restrict__ xg, LuSmem<R>& sh) {
+  const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
   C(*U2)[kSW] = ustrip2(sh);
@@ -457,38 +483,23 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& A, int 
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * rt + Prec<R>::drow(r, lk);
-      C v;
-      v.x = 0;
-      v.y = 0;
-      if (i < wb && cok[t]) v = A.base[A.phys(c + kNB + i) * A.N + bcol[t]];
+      // rows >= wb clamped (their T rows meet zero columns of X_b and zero rows of it)
+      const C v = A.base[A.phys(c + kNB + min(i, wb - 1)) * A.N + bcol[t]];
       ar[t][r] = v.x;
       ai[t][r] = v.y;
     }
   {
-    const bool rok = row < wb;
-    const C* lrow = A.base + A.phys(c + kNB + (rok ? row : 0)) * A.N + A.phys(c) + 4 * lk;
+    const auto lrow = A.base + A.phys(c + kNB + min(row, wb - 1)) * A.N + A.phys(c) + 4 * lk;
     C ln[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      C v;
-      v.x = 0;
-      v.y = 0;
-      if (rok) v = lrow[j];
-      ln[j] = v;
-    }
+    for (int j = 0; j < 4; ++j) ln[j] = lrow[j];
     for (int kc = 0; kc < kNB; kc += 16) {
       C l[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) l[j] = ln[j];
       if (kc + 16 < kNB) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          C v;
-          v.x = 0;
-          v.y = 0;
-          if (rok) v = lrow[kc + 16 + j];
-          ln[j] = v;
-        }
+        for (int j = 0; j < 4; ++j) ln[j] = lrow[kc + 16 + j];
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -569,24 +580,17 @@ __device__ __forceinline__ void save_x(const LuSmem<R>& sh, typename Prec<R>::C*
 }
 
 // Loads the B operands of one 16-deep chunk of trsm_strip: lane (li, lk)
-// takes rows k = kc + 4 lk + j (j < 4) of its two columns, zero outside
-// k < s and the strip.
+// takes rows k = kc + 4 lk + j (j < 4) of its two columns, the row clamped to
+// s - 1 and the column to the strip (in-range, straight-line loads).
 template <typename C>
 __device__ __forceinline__ void trsm_load_chunk(const Mat<C>& A, int r0, int s, int kc, int lk,
                                                 const int64_t (&bcol)[2], const bool (&cok)[2], C (&dst)[2][4]) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int k = kc + 4 * lk + j;
-    const bool kok = k < s;
-    const C* rowp = A.base + A.phys(r0 + (kok ? k : 0)) * A.N;
+    // rows k >= s clamped to s - 1: X is zero in those columns
+    const auto rowp = glb(A.base + A.phys(r0 + min(kc + 4 * lk + j, s - 1)) * A.N);
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      C b;
-      b.x = 0;
-      b.y = 0;
-      if (kok && cok[t]) b = rowp[bcol[t]];
-      dst[t][j] = b;
-    }
+    for (int t = 0; t < 2; ++t) dst[t][j] = rowp[bcol[t]];  // columns >= sw are never stored
   }
 }
 
@@ -597,8 +601,9 @@ __device__ __forceinline__ void trsm_load_chunk(const Mat<C>& A, int r0, int s, 
 // while the current one is multiplied; X is lower triangular, so row tile rt
 // stops at k = 16 rt + 16.
 template <typename R>
-__device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
+__device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& Ain, int r0, int s, int s0, int sw,
                                         bool store, LuSmem<R>& sh) {
+  const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -676,7 +681,6 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
   const int li = lane & 15, lq = lane >> 4;
   const int N = (int)A.N;
   const int rstart = r0 + s;
-  const int64_t pr0 = A.phys(r0) + 4 * lq;
   int64_t ccol[NCS];
   bool cok[NCS];
 #pragma unroll
@@ -687,35 +691,29 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
   int rb = rstart + 16 * wave;
   if (rb >= N) return;
   C cn[NCS][4], an[4];
+  // Loads are unconditional, from clamped in-range addresses, so that they
+  // stay in straight-line code with exact wait counts: entries of rows >= N
+  // or columns >= sw are never stored, and an L entry of a column >= s
+  // (clamped to s - 1, a finite matrix entry) meets a zero row of Ub.
   // accumulator block of row block q: rows q + drow(r, lq)
   auto load_c = [&](int q) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int v = q + Prec<R>::drow(r, lq);
-      const C* crow = A.base + A.phys(v < N ? v : rstart) * A.N;
+      const auto crow = glb(A.base + A.phys(v < N ? v : rstart) * A.N);
 #pragma unroll
-      for (int cs = 0; cs < NCS; ++cs) {
-        C cv;
-        cv.x = 0;
-        cv.y = 0;
-        if (v < N && cok[cs]) cv = crow[ccol[cs]];
-        cn[cs][r] = cv;
-      }
+      for (int cs = 0; cs < NCS; ++cs) cn[cs][r] = crow[ccol[cs]];
     }
   };
   // chunk kc of the L operand of row block q: row q + li, k = kc + 4 lq + j
+  const int64_t pc0 = A.phys(r0);
   auto load_a = [&](int q, int kc) {
     const int va = q + li;
-    const C* arow = A.base + A.phys(va < N ? va : rstart) * A.N + pr0 + kc;
+    const auto arow = glb(A.base + A.phys(va < N ? va : rstart) * A.N + pc0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      C av;
-      av.x = 0;
-      av.y = 0;
-      if (va < N && kc + 4 * lq + j < s) av = arow[j];
-      an[j] = av;
-    }
+    for (int j = 0; j < 4; ++j) an[j] = arow[min(kc + 4 * lq + j, s - 1)];
   };
+  const LSMS_LDS C(*U)[kSW] = (const LSMS_LDS C(*)[kSW])Ub;
   load_c(rb);
   load_a(rb, 0);
   for (; rb < N; rb += 16 * kLuWaves) {
@@ -744,7 +742,7 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
         const R nx = -a[j].x, ny = -a[j].y;
 #pragma unroll
         for (int cs = 0; cs < NCS; ++cs) {
-          const C b = Ub[k][16 * cs + li];
+          const C b = U[k][16 * cs + li];
           accr[cs] = Prec<R>::mfma(nx, b.x, accr[cs]);
           accr[cs] = Prec<R>::mfma(a[j].y, b.y, accr[cs]);
           acci[cs] = Prec<R>::mfma(nx, b.y, acci[cs]);
@@ -756,7 +754,7 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
     for (int r = 0; r < 4; ++r) {
       const int v = rb + Prec<R>::drow(r, lq);
       if (v >= N) continue;
-      C* crow = A.base + A.phys(v) * A.N;
+      const auto crow = glb(A.base + A.phys(v) * A.N);
 #pragma unroll
       for (int cs = 0; cs < NCS; ++cs)
         if (cok[cs]) crow[ccol[cs]] = zmake(accr[cs][r], acci[cs][r]);
@@ -779,7 +777,7 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
   const int li = lane & 15, lq = lane >> 4;
   const int N = (int)A.N;
   const int rstart = r0 + s;
-  const int64_t pr0 = A.phys(r0) + 4 * lq;
+  const int64_t pc0 = A.phys(r0);
   constexpr int kStep = 16 * kLuWaves;
   int64_t ccol[NCS];
   bool cok[NCS];
@@ -795,24 +793,19 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int v = rb + b * kStep + Prec<R>::drow(r, lq);
-        const C* crow = A.base + A.phys(v < N ? v : rstart) * A.N;
+        const auto crow = glb(A.base + A.phys(v < N ? v : rstart) * A.N);
 #pragma unroll
         for (int cs = 0; cs < NCS; ++cs) {
-          C cv;
-          cv.x = 0;
-          cv.y = 0;
-          if (v < N && cok[cs]) cv = crow[ccol[cs]];
+          const C cv = crow[ccol[cs]];  // clamped in range; unused entries are not stored
           accr[b][cs][r] = cv.x;
           acci[b][cs][r] = cv.y;
         }
       }
-    const C* arow[RB];
-    bool rok[RB];
+    LSMS_GLOBAL const C* arow[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
       const int va = rb + b * kStep + li;
-      rok[b] = va < N;
-      arow[b] = A.base + A.phys(rok[b] ? va : rstart) * A.N + pr0;
+      arow[b] = glb(A.base + A.phys(va < N ? va : rstart) * A.N + pc0);
     }
     for (int kc = 0; kc < s; kc += 16) {
       // k = kc + lq + 4 j here, so that MFMA steps past the end of a short
@@ -822,20 +815,14 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
 #pragma unroll
       for (int b = 0; b < RB; ++b)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          C av;
-          av.x = 0;
-          av.y = 0;
-          if (rok[b] && kc + lq + 4 * j < s) av = arow[b][kc + 4 * j - 3 * lq];
-          a[b][j] = av;
-        }
+        for (int j = 0; j < 4; ++j) a[b][j] = arow[b][min(kc + lq + 4 * j, s - 1)];  // Ub rows >= s are zero
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (j >= nj) break;
         const int k = (kc + lq + 4 * j) & (kPanelMax - 1);
 #pragma unroll
         for (int cs = 0; cs < NCS; ++cs) {
-          const C u = Ub[k][16 * cs + li];
+          const C u = ((const LSMS_LDS C(*)[kSW])Ub)[k][16 * cs + li];
 #pragma unroll
           for (int b = 0; b < RB; ++b) {
             const R nx = -a[b][j].x, ny = -a[b][j].y;
@@ -853,7 +840,7 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
       for (int r = 0; r < 4; ++r) {
         const int v = rb + b * kStep + Prec<R>::drow(r, lq);
         if (v >= N) continue;
-        C* crow = A.base + A.phys(v) * A.N;
+        const auto crow = glb(A.base + A.phys(v) * A.N);
 #pragma unroll
         for (int cs = 0; cs < NCS; ++cs)
           if (cok[cs]) crow[ccol[cs]] = zmake(accr[b][cs][r], acci[b][cs][r]);
@@ -864,8 +851,9 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
 // A(v, s0 + j) -= sum_{k < s} A(v, r0 + k) Ub[k][j] for v in [r0 + s, N),
 // j < sw <= 64, s <= 128 (Ub in LDS, rows k >= s zero).
 template <typename R>
-__device__ __noinline__ void update_strip(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
+__device__ __noinline__ void update_strip(const Mat<typename Prec<R>::C>& Ain, int r0, int s, int s0, int sw,
                                           const typename Prec<R>::C (*Ub)[kSW]) {
+  const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
   if (sw > 48) update_rows<R, 4>(A, r0, s, s0, sw, Ub);
   else if (sw > 32) update_rows<R, 3>(A, r0, s, s0, sw, Ub);
   else if (sw > 16) update_rows_multi<R, 2, 2>(A, r0, s, s0, sw, Ub);
@@ -876,14 +864,15 @@ __device__ __noinline__ void update_strip(const Mat<typename Prec<R>::C>& A, int
 // Each thread owns whole columns, so the interchanges are applied in order
 // per thread.
 template <typename R>
-__device__ __noinline__ void apply_swaps(const Mat<typename Prec<R>::C>& A, int c, int w, int c0, int c1,
+__device__ __noinline__ void apply_swaps(const Mat<typename Prec<R>::C>& Ain, int c, int w, int c0, int c1,
                                          const LuSmem<R>& sh) {
+  const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
   typedef typename Prec<R>::C C;
   for (int jj = 0; jj < w; ++jj) {
     const int p = sh.ipiv[jj], r = c + jj;
     if (p == r) continue;
-    C* rr = A.base + A.phys(r) * A.N;
-    C* rp = A.base + A.phys(p) * A.N;
+    const auto rr = A.base + A.phys(r) * A.N;
+    const auto rp = A.base + A.phys(p) * A.N;
     for (int u = c0 + threadIdx.x; u < c1; u += kLuThreads) {
       const int64_t pu = A.phys(u);
       const C x = rr[pu], y = rp[pu];

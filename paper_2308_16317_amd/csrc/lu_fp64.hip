@@ -54,7 +54,7 @@ __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, 
   const int N = kk * nliz, Nd = N - kk;
   zd* tout = reinterpret_cast<zd*>(tau00) + (int64_t)inst * kk * kk;
   Mat<zd> A;
-  A.base = base;
+  A.base = glb(base);
   A.N = N;
   A.Nd = Nd;
   A.kk = kk;
@@ -237,14 +237,14 @@ __global__ __launch_bounds__(kThreads) void tau00_persistent_kernel(lsms_prob_de
 constexpr int kInfoIrFallback = 256;
 
 struct MixedBufs {
-  zf* A32;        // N x N FP32 factors, same physical layout as M
-  zf* z;          // N x kp FP32 right-hand sides / corrections, internal rows
-  zd* Y;          // N x kp FP64 solution, internal rows
-  int32_t* ipiv;  // N pivot rows
-  zd* xg;         // two 64 x 64 blocks (FP64, or FP32 in the first half) for wide panels
-  zf* lcache;     // inverses of the 64-column diagonal blocks of L (factorisation order)
-  zf* ucache;     // inverses of the 64-row diagonal blocks of U (filled by the first solve)
-  int kp;         // 16 or 32: kk rounded up to a multiple of 16
+  LSMS_GLOBAL zf* A32;        // N x N FP32 factors, same physical layout as M
+  LSMS_GLOBAL zf* z;          // N x kp FP32 right-hand sides / corrections, internal rows
+  LSMS_GLOBAL zd* Y;          // N x kp FP64 solution, internal rows
+  LSMS_GLOBAL int32_t* ipiv;  // N pivot rows
+  LSMS_GLOBAL zd* xg;         // two 64 x 64 blocks (FP64, or FP32 in the first half) for wide panels
+  LSMS_GLOBAL zf* lcache;     // inverses of the 64-column diagonal blocks of L (factorisation order)
+  LSMS_GLOBAL zf* ucache;     // inverses of the 64-row diagonal blocks of U (filled by the first solve)
+  int kp;                // 16 or 32: kk rounded up to a multiple of 16
 };
 
 // Number of cached diagonal blocks of L in the panels of [0, c) (panels of
@@ -332,7 +332,7 @@ __device__ void rhs_update_rows(const Mat<zf>& A, const MixedBufs& b, int r0, in
     };
     auto load_a = [&](int q, int kc) {
       const int va = q + li;
-      const zf* arow = A.base + A.phys(va < N ? va : v0) * A.N + pr0 + kc;
+      const auto arow = A.base + A.phys(va < N ? va : v0) * A.N + pr0 + kc;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         zf av = zmake(0.f, 0.f);
@@ -448,7 +448,7 @@ __device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, bool hav
     V4 ar = V4{0.f, 0.f, 0.f, 0.f}, ai = V4{0.f, 0.f, 0.f, 0.f};
     const int row = c + 16 * rt + li;
     const bool rok = 16 * rt + li < w;
-    const zf* urow = A.base + A.phys(rok ? row : c) * A.N;
+    const auto urow = A.base + A.phys(rok ? row : c) * A.N;
     for (int kb = ka; kb < kz; kb += 4) {
       const int k = kb + lq;
       const bool kok = k < kz;
@@ -526,7 +526,7 @@ __device__ void residual_rows(const Mat<zd>& A, const MixedBufs& b) {
     }
     const int va = rb + li;
     const bool rok = va < N;
-    const zd* arow = A.base + A.phys(rok ? va : 0) * A.N;
+    const auto arow = A.base + A.phys(rok ? va : 0) * A.N;
     // A(va, k) for k < Nd is at arow[kk + k], for k >= Nd at arow[k - Nd]
     zd an[4], yn[NCT][4];
     auto load = [&](int kc) {
@@ -600,12 +600,12 @@ __device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd
   const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
   const int N = kk * nliz, Nd = N - kk;
   Mat<zd> A;
-  A.base = A64;
+  A.base = glb(A64);
   A.N = N;
   A.Nd = Nd;
   A.kk = kk;
   Mat<zf> F;
-  F.base = b.A32;
+  F.base = glb(b.A32);
   F.N = N;
   F.Nd = Nd;
   F.kk = kk;
@@ -734,13 +734,14 @@ __device__ inline MixedBufs mixed_bufs(unsigned char* base, int64_t nmax, int kp
   const int64_t a = ((nmax * nmax * 8) + 255) & ~(int64_t)255;
   const int64_t z = ((nmax * kp * 8) + 255) & ~(int64_t)255;
   const int64_t y = ((nmax * kp * 16) + 255) & ~(int64_t)255;
-  b.A32 = reinterpret_cast<zf*>(base);
-  b.z = reinterpret_cast<zf*>(base + a);
-  b.Y = reinterpret_cast<zd*>(base + a + z);
-  b.ipiv = reinterpret_cast<int32_t*>(base + a + z + y);
-  b.xg = reinterpret_cast<zd*>(base + a + z + y + (((nmax * 4) + 255) & ~(int64_t)255));
-  b.lcache = reinterpret_cast<zf*>(reinterpret_cast<unsigned char*>(b.xg) + kXgBytes);
-  b.ucache = reinterpret_cast<zf*>(reinterpret_cast<unsigned char*>(b.lcache) + mixed_lcache_bytes(nmax));
+  const int64_t pv = ((nmax * 4) + 255) & ~(int64_t)255;
+  b.A32 = glb(reinterpret_cast<zf*>(base));
+  b.z = glb(reinterpret_cast<zf*>(base + a));
+  b.Y = glb(reinterpret_cast<zd*>(base + a + z));
+  b.ipiv = glb(reinterpret_cast<int32_t*>(base + a + z + y));
+  b.xg = glb(reinterpret_cast<zd*>(base + a + z + y + pv));
+  b.lcache = glb(reinterpret_cast<zf*>(base + a + z + y + pv + kXgBytes));
+  b.ucache = glb(reinterpret_cast<zf*>(base + a + z + y + pv + kXgBytes + mixed_lcache_bytes(nmax)));
   b.kp = kp;
   return b;
 }
@@ -823,13 +824,13 @@ constexpr int kInfoLuFallback = 512;
 constexpr int kGmMaxM = 8;  // block Arnoldi steps per restart, at most
 
 struct GmresBufs {
-  zd* Y;  // N x 16 solution (row-major, internal rows)
-  zd* R;  // N x 16 residual
-  zd* V;  // (m + 1) blocks of N x 16
-  zd* H;  // ((m + 1) 16) x (m 16) block Hessenberg, column-major
-  zd* G;  // ((m + 1) 16) x 16 least-squares right-hand side, column-major
-  zd* Q;  // Householder vectors of the QR of H, 32 per column (16 m columns)
-  double* beta;  // their scale factors
+  LSMS_GLOBAL zd* Y;  // N x 16 solution (row-major, internal rows)
+  LSMS_GLOBAL zd* R;  // N x 16 residual
+  LSMS_GLOBAL zd* V;  // (m + 1) blocks of N x 16
+  LSMS_GLOBAL zd* H;  // ((m + 1) 16) x (m 16) block Hessenberg, column-major
+  LSMS_GLOBAL zd* G;  // ((m + 1) 16) x 16 least-squares right-hand side, column-major
+  LSMS_GLOBAL zd* Q;  // Householder vectors of the QR of H, 32 per column (16 m columns)
+  LSMS_GLOBAL double* beta;  // their scale factors
   int m;
 };
 
@@ -858,7 +859,7 @@ __device__ void gm_amul(const Mat<zd>& A, const zd* __restrict__ X, zd* __restri
     V4 ar = V4{0.0, 0.0, 0.0, 0.0}, ai = V4{0.0, 0.0, 0.0, 0.0};
     const int va = rb + li;
     const bool rok = va < N;
-    const zd* arow = A.base + A.phys(rok ? va : 0) * A.N;
+    const auto arow = A.base + A.phys(rok ? va : 0) * A.N;
     zd an[4], xn[4];
     auto load = [&](int kc) {
 #pragma unroll
@@ -1214,15 +1215,15 @@ __device__ inline GmresBufs gmres_bufs(unsigned char* base, int64_t nmax, int m)
   const int64_t h = (((int64_t)16 * (m + 1) * 16 * m * 16) + 255) & ~(int64_t)255;
   GmresBufs b;
   unsigned char* q = base + kXgBytes;
-  b.Y = reinterpret_cast<zd*>(q);
-  b.R = reinterpret_cast<zd*>(q + blk);
-  b.V = reinterpret_cast<zd*>(q + 2 * blk);
-  b.H = reinterpret_cast<zd*>(q + (3 + m) * blk);
+  b.Y = glb(reinterpret_cast<zd*>(q));
+  b.R = glb(reinterpret_cast<zd*>(q + blk));
+  b.V = glb(reinterpret_cast<zd*>(q + 2 * blk));
+  b.H = glb(reinterpret_cast<zd*>(q + (3 + m) * blk));
   const int64_t g = (((int64_t)16 * (m + 1) * 16 * 16) + 255) & ~(int64_t)255;
   const int64_t qv = (((int64_t)16 * m * 32 * 16) + 255) & ~(int64_t)255;
-  b.G = reinterpret_cast<zd*>(q + (3 + m) * blk + h);
-  b.Q = reinterpret_cast<zd*>(q + (3 + m) * blk + h + g);
-  b.beta = reinterpret_cast<double*>(q + (3 + m) * blk + h + g + qv);
+  b.G = glb(reinterpret_cast<zd*>(q + (3 + m) * blk + h));
+  b.Q = glb(reinterpret_cast<zd*>(q + (3 + m) * blk + h + g));
+  b.beta = glb(reinterpret_cast<double*>(q + (3 + m) * blk + h + g + qv));
   b.m = m;
   return b;
 }
@@ -1266,7 +1267,7 @@ __global__ __launch_bounds__(kThreads) void tau00_gmres_persistent_kernel(
     if (status == 0) {
       const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
       Mat<zd> A;
-      A.base = M;
+      A.base = glb(M);
       A.N = (int64_t)p.kk * nliz;
       A.Nd = (int)A.N - p.kk;
       A.kk = p.kk;
