@@ -61,12 +61,11 @@ struct LuSmem {
   C X[kNB][kNB];    // inverse of a triangular block
   C U[kNB][kSW];    // U12 strip; block staging; Gauss-Jordan workspace at the end
                     // (X and U together: the 128-row U12 strip of a wide panel)
-  C rowP[kMaxWL];   // pivot row of a leaf step
-  C rowJ[kMaxWL];
+  C cand[2][kLuWaves][kMaxWL];  // each wave's pivot candidate row (two buffers)
+  R candv[2][kLuWaves];         // its magnitude |Re| + |Im|
+  int candi[2][kLuWaves];       // its row
   zd tz[kMaxKK];
   zd pinv;
-  R redv[kLuWaves];
-  int redi[kLuWaves];
   int ipiv[kPanelMax];
   int lrow[2 * kMaxWL];  // rows touched by a leaf's interchanges
   int lsrc[2 * kMaxWL];  // lrow[q] receives the old content of lrow[lsrc[q]]
@@ -120,6 +119,59 @@ __device__ __forceinline__ bool better(R ob, int oi, R b, int i) {
   return ob > b || (ob == b && oi < i);
 }
 
+// Lane exchanges inside rows of 16 lanes by DPP (a VALU operand modifier, no
+// LDS round trip).  Each control pairs every lane with one other lane:
+// quad_perm [1,0,3,2] with lane ^ 1, quad_perm [2,3,0,1] with lane ^ 2,
+// row_half_mirror with 7 - i inside each group of 8, row_mirror with 15 - i
+// inside each row of 16.  Applied in this order to a reduction, each pairs a
+// lane with one from the half not yet combined with it.
+enum : int { kDppX1 = 0xB1, kDppX2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140 };
+
+template <int kCtrl>
+__device__ __forceinline__ int dpp_int(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, kCtrl, 0xF, 0xF, false);
+}
+template <int kCtrl>
+__device__ __forceinline__ double dpp_val(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)dpp_int<kCtrl>((int)(unsigned)u);
+  const unsigned hi = (unsigned)dpp_int<kCtrl>((int)(unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int kCtrl>
+__device__ __forceinline__ float dpp_val(float x) {
+  return __int_as_float(dpp_int<kCtrl>(__float_as_int(x)));
+}
+
+template <int kCtrl, typename R>
+__device__ __forceinline__ void argmax_dpp(R& best, int& bi) {
+  const R ob = dpp_val<kCtrl>(best);
+  const int oi = dpp_int<kCtrl>(bi);
+  if (better(ob, oi, best, bi)) {
+    best = ob;
+    bi = oi;
+  }
+}
+
+// (best, bi) of every lane becomes the wave's maximum of best, ties to the
+// smallest bi; all lanes must be active.
+template <typename R>
+__device__ __forceinline__ void wave_argmax(R& best, int& bi) {
+  argmax_dpp<kDppX1>(best, bi);
+  argmax_dpp<kDppX2>(best, bi);
+  argmax_dpp<kDppHalfMirror>(best, bi);
+  argmax_dpp<kDppMirror>(best, bi);
+#pragma unroll
+  for (int off = 16; off <= 32; off <<= 1) {
+    const R ob = __shfl_xor(best, off);
+    const int oi = __shfl_xor(bi, off);
+    if (better(ob, oi, best, bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+}
+
 // Factorises the leaf columns [lc, lc + kWL) of the panel [c, c + w), rows
 // [lc, N), with the leaf in registers (thread t owns rows lc + t + 512 q).
 // Interchanges are applied at once to the other panel columns in memory.
@@ -146,98 +198,81 @@ __device__ __noinline__ void leaf_factor(const Mat<typename Prec<R>::C>& Ain, in
       for (int k = 0; k < kWL; ++k) a[q][k] = zmake(R(0), R(0));
     }
   }
-  for (int jj = 0; jj < wl; ++jj) {
+  // Rows are not moved in registers: pos[q] is the current position of the
+  // row held in a[q].  An interchange of positions j and bi only relabels the
+  // two rows; each row is stored at its final position at the end.  The loop
+  // is unrolled over the leaf's columns so that every register index is a
+  // compile-time constant (a run-time column index turns each access into a
+  // chain of selects).
+  int pos[kR];
+#pragma unroll
+  for (int q = 0; q < kR; ++q) pos[q] = lc + tid + kLuThreads * q;
+#pragma unroll
+  for (int jj = 0; jj < kWL; ++jj) {
+    if (jj >= wl) break;
     const int j = lc + jj;
     R best = R(-1);
     int bi = j;
 #pragma unroll
     for (int q = 0; q < kR; ++q) {
-      const int v = lc + tid + kLuThreads * q;
-      if (v >= j && v < plim) {
-        R x = R(0);
-#pragma unroll
-        for (int k = 0; k < kWL; ++k)
-          if (k == jj) x = zcabs1(a[q][k]);
-        if (x > best || (x == best && v < bi)) {
+      if (pos[q] >= j && pos[q] < plim) {
+        const R x = zcabs1(a[q][jj]);
+        if (x > best || (x == best && pos[q] < bi)) {
           best = x;
-          bi = v;
+          bi = pos[q];
         }
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const R ob = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (better(ob, oi, best, bi)) {
-        best = ob;
-        bi = oi;
+    // each wave publishes its candidate and the candidate's row (the lane
+    // holding it writes the row); one barrier, then every thread picks the
+    // winner.  Two buffers: a wave writes buffer jj & 1 only after the barrier
+    // of step jj - 1, which every thread passes after its reads of step jj - 2.
+    wave_argmax(best, bi);
+    const int buf = jj & 1;
+    if (lane == 0) {
+      sh.candv[buf][wave] = best;
+      sh.candi[buf][wave] = bi;
+    }
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+      if (pos[q] == bi) {
+#pragma unroll
+        for (int k = 0; k < kWL; ++k) sh.cand[buf][wave][k] = a[q][k];
       }
     }
-    if (lane == 0) {
-      sh.redv[wave] = best;
-      sh.redi[wave] = bi;
-    }
     __syncthreads();
-    best = sh.redv[0];
-    bi = sh.redi[0];
+    best = sh.candv[buf][0];
+    bi = sh.candi[buf][0];
+    int wv = 0;
 #pragma unroll
     for (int q = 1; q < kLuWaves; ++q)
-      if (better(sh.redv[q], sh.redi[q], best, bi)) {
-        best = sh.redv[q];
-        bi = sh.redi[q];
+      if (better(sh.candv[buf][q], sh.candi[buf][q], best, bi)) {
+        best = sh.candv[buf][q];
+        bi = sh.candi[buf][q];
+        wv = q;
       }
     const bool zero = !(best > R(0));
     if (zero) bi = j;
-    // owners of rows j and bi publish them
-    const int oj = j - lc, ob = bi - lc;
-#pragma unroll
-    for (int q = 0; q < kR; ++q) {
-      if (oj == tid + kLuThreads * q) {
-#pragma unroll
-        for (int k = 0; k < kWL; ++k) sh.rowJ[k] = a[q][k];
-      }
-      if (ob == tid + kLuThreads * q) {
-#pragma unroll
-        for (int k = 0; k < kWL; ++k) sh.rowP[k] = a[q][k];
-      }
-    }
     if (tid == 0) {
       sh.ipiv[j - c] = bi;
       if (zero && best == R(0) && sh.info == 0) sh.info = j + 1;
     }
-    __syncthreads();
-    if (bi != j) {
 #pragma unroll
-      for (int q = 0; q < kR; ++q) {
-        if (oj == tid + kLuThreads * q) {
-#pragma unroll
-          for (int k = 0; k < kWL; ++k) a[q][k] = sh.rowP[k];
-        }
-        if (ob == tid + kLuThreads * q) {
-#pragma unroll
-          for (int k = 0; k < kWL; ++k) a[q][k] = sh.rowJ[k];
-        }
-      }
-    }
+    for (int q = 0; q < kR; ++q) pos[q] = pos[q] == bi ? j : (pos[q] == j ? bi : pos[q]);
     if (!zero) {
-      C piv = zmake(R(0), R(0));
+      const C inv = zinv(sh.cand[buf][wv][jj]);
+      C pr[kWL];
 #pragma unroll
-      for (int k = 0; k < kWL; ++k)
-        if (k == jj) piv = sh.rowP[k];
-      const C inv = zinv(piv);
+      for (int k = jj + 1; k < kWL; ++k) pr[k] = sh.cand[buf][wv][k];
 #pragma unroll
       for (int q = 0; q < kR; ++q) {
-        const int v = lc + tid + kLuThreads * q;
-        if (v > j && v < N) {
-          C l = zmake(R(0), R(0));
+        // rows that do not take part get a zero multiplier: a - 0 p == a
+        const bool act = pos[q] > j && pos[q] < N;
+        const C l0 = zmul(a[q][jj], inv);
+        const C l = act ? l0 : zmake(R(0), R(0));
+        if (act) a[q][jj] = l0;
 #pragma unroll
-          for (int k = 0; k < kWL; ++k)
-            if (k == jj) l = zmul(a[q][k], inv);
-#pragma unroll
-          for (int k = 0; k < kWL; ++k) {
-            if (k == jj) a[q][k] = l;
-            else if (k > jj) a[q][k] = zfms(a[q][k], l, sh.rowP[k]);
-          }
-        }
+        for (int k = jj + 1; k < kWL; ++k) a[q][k] = zfms(a[q][k], l, pr[k]);
       }
     }
   }
@@ -272,9 +307,8 @@ __device__ __noinline__ void leaf_factor(const Mat<typename Prec<R>::C>& Ain, in
   }
 #pragma unroll
   for (int q = 0; q < kR; ++q) {
-    const int v = lc + tid + kLuThreads * q;
-    if (v < N) {
-      const auto row = A.ptr(v, lc);
+    if (pos[q] < N) {
+      const auto row = A.ptr(pos[q], lc);
 #pragma unroll
       for (int k = 0; k < kWL; ++k)
         if (k < wl) row[k] = a[q][k];

@@ -194,6 +194,58 @@ def test_tau00_config2_full_size_sample(P, h):
     assert sym.max() <= TOL_TAU
 
 
+def _pivot_sensitive_matrix(rng, N, kk, eps=1e-8):
+    """M whose elimination (Sec. 3.2: partial pivoting, the central block
+    last) has a known and unambiguous pivot sequence.  In elimination order
+    (non-central rows and columns first, the central block last) the matrix
+    read as A = M^T is P L U: P a random permutation inside each of the two
+    row groups, L unit lower triangular with |L_ij| ~ eps, U upper triangular
+    and well conditioned.  Partial pivoting recovers P; any other pivot gives
+    multipliers of order 1/eps and errors far above the FP64 bar."""
+    Nd = N - kk
+    cn = lambda *s: (rng.standard_normal(s) + 1j * rng.standard_normal(s)) / np.sqrt(2)
+    L = np.eye(N, dtype=np.complex128) + np.tril(eps * cn(N, N), -1)
+    U = np.triu(0.3 / np.sqrt(N) * cn(N, N), 1)
+    U += np.diag((1.0 + 0.5 * rng.random(N)) * np.exp(2j * np.pi * rng.random(N)))
+    perm = np.concatenate([rng.permutation(Nd), Nd + rng.permutation(kk)])
+    A = (L @ U)[np.argsort(perm)]  # row perm[i] of A is row i of L U
+    ph = np.where(np.arange(N) < Nd, np.arange(N) + kk, np.arange(N) - Nd)  # elimination -> storage index
+    M = np.empty((N, N), np.complex128)
+    M[np.ix_(ph, ph)] = A.T
+    return M
+
+
+@pytest.mark.parametrize("which", ["config1", "config2"])
+def test_pivot_choice_caller_matrix(P, h, which):
+    # the largest candidate sits at random rows, so every lane, wave and
+    # reduction stage of the pivot search is the winner somewhere
+    torch = _torch()
+    w = inputs.config1() if which == "config1" else inputs.config2()
+    w = inputs.subset(w, [0, 37])
+    prob = P.problem_for_workload(h, w)
+    kk = prob.kk
+    liz_off = prob.liz_off.cpu().numpy()
+    N = kk * np.diff(liz_off)
+    rng = np.random.default_rng(2024)
+    mats = [_pivot_sensitive_matrix(rng, int(n), kk) for n in N]
+    m_off = np.concatenate([[0], np.cumsum(N * N)[:-1]]).astype(np.int64)
+    M = torch.as_tensor(np.concatenate([m.ravel(order="F") for m in mats])).to("cuda")
+    tau, info = P.tau00_batched(h, prob, M, torch.as_tensor(m_off, device="cuda"))
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    liz_off_o, pos, spec = oracle.liz_batch(w)
+    l_of = np.floor(np.sqrt(np.arange(kk))).astype(int)
+    ref = []
+    for i, m in enumerate(mats):
+        E = w.energies[w.e_idx[i]]
+        t = oracle.tmat(w.lmax, E, w.delta[spec[liz_off_o[i]], w.e_idx[i]])[l_of]
+        X = np.linalg.solve(m, np.eye(m.shape[0], kk))  # first block column of M^-1
+        ref.append(X[:kk] * t[None, :])
+    err = rel_f(tau.cpu().numpy(), np.stack(ref))
+    print(which, "pivot-sensitive rel_F", err)
+    assert err.max() <= TOL_TAU
+
+
 # --------------------------------------------------------- edge cases
 def test_one_atom_and_zero_t(P, h):
     torch = _torch()
