@@ -698,14 +698,19 @@ __device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& Ain, int
 }
 
 // A(v, s0 + j) -= sum_{k < s} A(v, r0 + k) U[k][j] for v in [r0 + s, N),
-// j < sw <= 16 NCS.  Each wave owns blocks of 16 rows x 16 NCS columns (NCS
-// MFMA tiles) whose accumulators start from the loaded block of A.  The
-// reduction runs in chunks of 16: in a chunk starting at kc, lane (li, lq)
-// supplies k = kc + 4 lq + j at MFMA step j, so that it reads four
-// consecutive entries of its row.  Loads run one chunk ahead: the next chunk
-// of the row block, or, during its last chunk, the next row block's
-// accumulator block and first chunk.  The LDS operand rows U[k] are zero for
-// k >= s.
+// j < sw <= 16 NCS, s > 16.  Each wave owns blocks of 16 rows x 16 NCS
+// columns (NCS MFMA tiles).  The reduction runs in chunks of 16: in a chunk
+// starting at kc, lane (li, lq) supplies k = kc + 4 lq + j at MFMA step j, so
+// that it reads four consecutive entries of its row.  Loads run one chunk
+// ahead: the next chunk of the row block or, during its last chunk, the
+// block's own entries of A (added to the product at the end) and the next
+// row block's first chunk.  A finished block stays in registers and is
+// stored after the first MFMA step of the next block: loads and stores share
+// one completion counter, so a store issued just before a wait for loads
+// would be waited for too; issued there it completes behind three steps of
+// MFMA work.  The first and last chunks are peeled so that the block of A
+// and the pending results occupy registers only there.  The LDS operand rows
+// U[k] are zero for k >= s.
 template <typename R, int NCS>
 __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
                                             const typename Prec<R>::C (*Ub)[kSW]) {
@@ -724,19 +729,30 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
   }
   int rb = rstart + 16 * wave;
   if (rb >= N) return;
-  C cn[NCS][4], an[4];
   // Loads are unconditional, from clamped in-range addresses, so that they
   // stay in straight-line code with exact wait counts: entries of rows >= N
   // or columns >= sw are never stored, and an L entry of a column >= s
   // (clamped to s - 1, a finite matrix entry) meets a zero row of Ub.
-  // accumulator block of row block q: rows q + drow(r, lq)
+  C cv[NCS][4], an[4], pv[NCS][4];
+  // block q of A: rows q + drow(r, lq)
   auto load_c = [&](int q) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int v = q + Prec<R>::drow(r, lq);
       const auto crow = glb(A.base + A.phys(v < N ? v : rstart) * A.N);
 #pragma unroll
-      for (int cs = 0; cs < NCS; ++cs) cn[cs][r] = crow[ccol[cs]];
+      for (int cs = 0; cs < NCS; ++cs) cv[cs][r] = crow[ccol[cs]];
+    }
+  };
+  auto store_pv = [&](int q) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = q + Prec<R>::drow(r, lq);
+      if (v >= N) continue;
+      const auto crow = glb(A.base + A.phys(v) * A.N);
+#pragma unroll
+      for (int cs = 0; cs < NCS; ++cs)
+        if (cok[cs]) crow[ccol[cs]] = pv[cs][r];
     }
   };
   // chunk kc of the L operand of row block q: row q + li, k = kc + 4 lq + j
@@ -748,52 +764,65 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
     for (int j = 0; j < 4; ++j) an[j] = arow[min(kc + 4 * lq + j, s - 1)];
   };
   const LSMS_LDS C(*U)[kSW] = (const LSMS_LDS C(*)[kSW])Ub;
-  load_c(rb);
+  V4 accr[NCS], acci[NCS];
+  auto step = [&](int kc, int j, const C& aj) {
+    const int k = (kc + 4 * lq + j) & (kPanelMax - 1);
+    const R nx = -aj.x, ny = -aj.y;
+#pragma unroll
+    for (int cs = 0; cs < NCS; ++cs) {
+      const C b = U[k][16 * cs + li];
+      accr[cs] = Prec<R>::mfma(nx, b.x, accr[cs]);
+      accr[cs] = Prec<R>::mfma(aj.y, b.y, accr[cs]);
+      acci[cs] = Prec<R>::mfma(nx, b.y, acci[cs]);
+      acci[cs] = Prec<R>::mfma(ny, b.x, acci[cs]);
+    }
+  };
+  const int klast = 16 * ((s - 1) >> 4);  // first k of the last chunk (> 0)
+  int pb = -1;
   load_a(rb, 0);
   for (; rb < N; rb += 16 * kLuWaves) {
     const int rn = rb + 16 * kLuWaves;
-    V4 accr[NCS], acci[NCS];
 #pragma unroll
-    for (int cs = 0; cs < NCS; ++cs)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        accr[cs][r] = cn[cs][r].x;
-        acci[cs][r] = cn[cs][r].y;
-      }
-    for (int kc = 0; kc < s; kc += 16) {
+    for (int cs = 0; cs < NCS; ++cs) {
+      accr[cs] = V4{R(0), R(0), R(0), R(0)};
+      acci[cs] = V4{R(0), R(0), R(0), R(0)};
+    }
+    {
       C a[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) a[j] = an[j];
-      if (kc + 16 < s) {
-        load_a(rb, kc + 16);
-      } else if (rn < N) {
-        load_c(rn);
-        load_a(rn, 0);
-      }
+      step(0, 0, a[0]);
+      __builtin_amdgcn_sched_barrier(0);
+      if (pb >= 0) store_pv(pb);
+      load_a(rb, 16);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = (kc + 4 * lq + j) & (kPanelMax - 1);
-        const R nx = -a[j].x, ny = -a[j].y;
+      for (int j = 1; j < 4; ++j) step(0, j, a[j]);
+    }
+    for (int kc = 16; kc < klast; kc += 16) {
+      C a[4];
 #pragma unroll
-        for (int cs = 0; cs < NCS; ++cs) {
-          const C b = U[k][16 * cs + li];
-          accr[cs] = Prec<R>::mfma(nx, b.x, accr[cs]);
-          accr[cs] = Prec<R>::mfma(a[j].y, b.y, accr[cs]);
-          acci[cs] = Prec<R>::mfma(nx, b.y, acci[cs]);
-          acci[cs] = Prec<R>::mfma(ny, b.x, acci[cs]);
-        }
-      }
+      for (int j = 0; j < 4; ++j) a[j] = an[j];
+      load_a(rb, kc + 16);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) step(kc, j, a[j]);
+    }
+    {
+      C a[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[j] = an[j];
+      load_c(rb);
+      if (rn < N) load_a(rn, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) step(klast, j, a[j]);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int v = rb + Prec<R>::drow(r, lq);
-      if (v >= N) continue;
-      const auto crow = glb(A.base + A.phys(v) * A.N);
+    for (int cs = 0; cs < NCS; ++cs)
 #pragma unroll
-      for (int cs = 0; cs < NCS; ++cs)
-        if (cok[cs]) crow[ccol[cs]] = zmake(accr[cs][r], acci[cs][r]);
-    }
+      for (int r = 0; r < 4; ++r) pv[cs][r] = zmake(cv[cs][r].x + accr[cs][r], cv[cs][r].y + acci[cs][r]);
+    pb = rb;
   }
+  store_pv(pb);
 }
 
 // As update_rows for narrow strips (the sibling updates of the recursive
@@ -888,10 +917,19 @@ template <typename R>
 __device__ __noinline__ void update_strip(const Mat<typename Prec<R>::C>& Ain, int r0, int s, int s0, int sw,
                                           const typename Prec<R>::C (*Ub)[kSW]) {
   const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
-  if (sw > 48) update_rows<R, 4>(A, r0, s, s0, sw, Ub);
-  else if (sw > 32) update_rows<R, 3>(A, r0, s, s0, sw, Ub);
-  else if (sw > 16) update_rows_multi<R, 2, 2>(A, r0, s, s0, sw, Ub);
-  else update_rows_multi<R, 1, 4>(A, r0, s, s0, sw, Ub);
+  typedef const typename Prec<R>::C(*Rows)[kSW];
+  if (sw > 32 && s <= 16) {  // one reduction chunk: two strips of at most 32 columns
+    update_rows_multi<R, 2, 2>(A, r0, s, s0, 32, Ub);
+    update_rows_multi<R, 2, 2>(A, r0, s, s0 + 32, sw - 32, reinterpret_cast<Rows>(&Ub[0][32]));
+  } else if (sw > 48) {
+    update_rows<R, 4>(A, r0, s, s0, sw, Ub);
+  } else if (sw > 32) {
+    update_rows<R, 3>(A, r0, s, s0, sw, Ub);
+  } else if (sw > 16) {
+    update_rows_multi<R, 2, 2>(A, r0, s, s0, sw, Ub);
+  } else {
+    update_rows_multi<R, 1, 4>(A, r0, s, s0, sw, Ub);
+  }
 }
 
 // Row interchanges of the panel [c, c + w) applied to the columns [c0, c1).
