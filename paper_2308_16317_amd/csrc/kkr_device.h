@@ -14,7 +14,7 @@
 
 namespace lsms {
 
-constexpr int kBuildChunk = 64;  // LIZ row blocks prepared per phase
+constexpr int kBuildChunk = 64;  // LIZ row blocks prepared per phase (one per lane)
 constexpr int kBMaxL2 = 8;       // 2 * lmax for lmax <= 4
 constexpr int kBMaxKK2 = (kBMaxL2 + 1) * (kBMaxL2 + 1);
 constexpr int kBMaxKK = 25;
@@ -127,9 +127,10 @@ __device__ void build_setup(const lsms_prob_dev& p, const lsms_gaunt_dev& g, int
 }
 
 // Block column j of M, in chunks of kBuildChunk LIZ row blocks.  Phase A:
-// for each row block i of the chunk, 2 lmax + 2 threads: one per order
+// for each row block i of the chunk, 2 lmax + 2 tasks: one per order
 // m = 0 .. 2 lmax of Y_L''(R_ij) and one for the Hankel functions
-// h_l''(kappa R_ij).  Phase B: each thread owns (row block,
+// h_l''(kappa R_ij); task (m, i) is thread 64 m + i, so that a wave runs one
+// kind of task.  Phase B: each thread owns (row block,
 // L) pairs and sweeps the kk columns L', entry (L, L') of row block i at
 // index L + kk (i + nb L'), so consecutive threads write consecutive rows.
 template <int kNT>
@@ -148,9 +149,10 @@ __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int in
   for (int ib = 0; ib < nliz; ib += kBuildChunk) {
     const int nb = min(kBuildChunk, nliz - ib);
     const int slots = l2 + 2;  // orders m = 0 .. l2, then the Hankel functions
-    for (int t = tid; t < slots * nb; t += kNT) {
-      const int il = t / slots, m = t - il * slots;
+    for (int t = tid; t < slots * kBuildChunk; t += kNT) {
+      const int m = t >> 6, il = t & 63;  // one kind of task per wave
       const int iw = ib + il;
+      if (il >= nb) continue;
       if (m == 0) {
         const int sp = spec[iw];
         if (sp < 0 || sp >= p.n_species) sb.bad_species = 1;
