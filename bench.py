@@ -28,7 +28,7 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per instance moved by the fused kernel (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, each scaled by the counts of a plain copy of known size), valid
 # only for the kernel sources whose hash is given; null otherwise.
-TRAFFIC_PER_INSTANCE = {("fp64", "032be228809eab48"): 2.09e9}
+TRAFFIC_PER_INSTANCE = {("fp64", "1d22f3e07b7ea380"): 2.044e9}
 KERNEL_SOURCES = ("kkr_device.h", "lu_device.h", "lu_fp64.hip", "lsms_common.h")
 
 
@@ -163,7 +163,20 @@ def main():
                          "with their speedup over the FP64 path and their deviation from it")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run three plain device copies of MIB MiB (the reference kernel whose "
+                         "FETCH_SIZE / WRITE_SIZE counters scale the HBM-traffic measurement) and exit")
     args = ap.parse_args()
+    if args.copy_calib:
+        import torch
+
+        a = torch.ones((args.copy_calib << 20) // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_calib} MiB three times")
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
