@@ -452,7 +452,9 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
   C(*U2)[kSW] = ustrip2(sh);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int rt = wave & 3, ct0 = 2 * (wave >> 2);
+  // waves w and w + 4 share a SIMD: they take row tiles r and 3 - r, so
+  // every SIMD carries the same share of the triangular work
+  const int rt = wave < 4 ? wave : 7 - wave, ct0 = 2 * (wave >> 2);
   const int row = 16 * rt + li;
   const int wb = w - kNB;  // rows of the second block
   int64_t bcol[2];
@@ -642,8 +644,8 @@ __device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& Ain, int
   typedef typename Prec<R>::V4 V4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int rt = wave & 3;            // row tile
-  const int ct0 = 2 * (wave >> 2);    // first of two column tiles
+  const int rt = wave < 4 ? wave : 7 - wave;  // row tile (r and 3 - r per SIMD, as in trsm2_strip)
+  const int ct0 = 2 * (wave >> 2);            // first of two column tiles
   V4 ar[2], ai[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
