@@ -699,11 +699,17 @@ __device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& Ain, int
   __syncthreads();
 }
 
+// Reduction depth of one chunk of the trailing update: 16 in FP64; 32 in
+// FP32, whose MFMA takes half the cycles, so that a chunk of MFMA work still
+// covers the latency of the next chunk's loads.
+template <typename R>
+constexpr int kUpdChunk = sizeof(R) == 4 ? 32 : 16;
+
 // A(v, s0 + j) -= sum_{k < s} A(v, r0 + k) U[k][j] for v in [r0 + s, N),
-// j < sw <= 16 NCS, s > 16.  Each wave owns blocks of 16 rows x 16 NCS
-// columns (NCS MFMA tiles).  The reduction runs in chunks of 16: in a chunk
-// starting at kc, lane (li, lq) supplies k = kc + 4 lq + j at MFMA step j, so
-// that it reads four consecutive entries of its row.  Loads run one chunk
+// j < sw <= 16 NCS, s > kUpdChunk.  Each wave owns blocks of 16 rows x 16 NCS
+// columns (NCS MFMA tiles).  The reduction runs in chunks of KC = kUpdChunk:
+// in a chunk starting at kc, lane (li, lq) supplies k = kc + (KC/4) lq + j at
+// MFMA step j, so that it reads KC/4 consecutive entries of its row.  Loads run one chunk
 // ahead: the next chunk of the row block or, during its last chunk, the
 // block's own entries of A (added to the product at the end) and the next
 // row block's first chunk.  A finished block stays in registers and is
@@ -718,6 +724,7 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
                                             const typename Prec<R>::C (*Ub)[kSW]) {
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
+  constexpr int KJ = kUpdChunk<R> / 4;  // MFMA steps per chunk
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int N = (int)A.N;
@@ -735,7 +742,7 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
   // stay in straight-line code with exact wait counts: entries of rows >= N
   // or columns >= sw are never stored, and an L entry of a column >= s
   // (clamped to s - 1, a finite matrix entry) meets a zero row of Ub.
-  C cv[NCS][4], an[4], pv[NCS][4];
+  C cv[NCS][4], an[KJ], pv[NCS][4];
   // block q of A: rows q + drow(r, lq)
   auto load_c = [&](int q) {
 #pragma unroll
@@ -757,18 +764,18 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
         if (cok[cs]) crow[ccol[cs]] = pv[cs][r];
     }
   };
-  // chunk kc of the L operand of row block q: row q + li, k = kc + 4 lq + j
+  // chunk kc of the L operand of row block q: row q + li, k = kc + KJ lq + j
   const int64_t pc0 = A.phys(r0);
   auto load_a = [&](int q, int kc) {
     const int va = q + li;
     const auto arow = glb(A.base + A.phys(va < N ? va : rstart) * A.N + pc0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) an[j] = arow[min(kc + 4 * lq + j, s - 1)];
+    for (int j = 0; j < KJ; ++j) an[j] = arow[min(kc + KJ * lq + j, s - 1)];
   };
   const LSMS_LDS C(*U)[kSW] = (const LSMS_LDS C(*)[kSW])Ub;
   V4 accr[NCS], acci[NCS];
   auto step = [&](int kc, int j, const C& aj) {
-    const int k = (kc + 4 * lq + j) & (kPanelMax - 1);
+    const int k = (kc + KJ * lq + j) & (kPanelMax - 1);
     const R nx = -aj.x, ny = -aj.y;
 #pragma unroll
     for (int cs = 0; cs < NCS; ++cs) {
@@ -779,7 +786,7 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
       acci[cs] = Prec<R>::mfma(ny, b.x, acci[cs]);
     }
   };
-  const int klast = 16 * ((s - 1) >> 4);  // first k of the last chunk (> 0)
+  const int klast = kUpdChunk<R> * ((s - 1) / kUpdChunk<R>);  // first k of the last chunk (> 0)
   int pb = -1;
   load_a(rb, 0);
   for (; rb < N; rb += 16 * kLuWaves) {
@@ -790,33 +797,33 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
       acci[cs] = V4{R(0), R(0), R(0), R(0)};
     }
     {
-      C a[4];
+      C a[KJ];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) a[j] = an[j];
+      for (int j = 0; j < KJ; ++j) a[j] = an[j];
       step(0, 0, a[0]);
       __builtin_amdgcn_sched_barrier(0);
       if (pb >= 0) store_pv(pb);
-      load_a(rb, 16);
+      load_a(rb, kUpdChunk<R>);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int j = 1; j < 4; ++j) step(0, j, a[j]);
+      for (int j = 1; j < KJ; ++j) step(0, j, a[j]);
     }
-    for (int kc = 16; kc < klast; kc += 16) {
-      C a[4];
+    for (int kc = kUpdChunk<R>; kc < klast; kc += kUpdChunk<R>) {
+      C a[KJ];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) a[j] = an[j];
-      load_a(rb, kc + 16);
+      for (int j = 0; j < KJ; ++j) a[j] = an[j];
+      load_a(rb, kc + kUpdChunk<R>);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) step(kc, j, a[j]);
+      for (int j = 0; j < KJ; ++j) step(kc, j, a[j]);
     }
     {
-      C a[4];
+      C a[KJ];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) a[j] = an[j];
+      for (int j = 0; j < KJ; ++j) a[j] = an[j];
       load_c(rb);
       if (rn < N) load_a(rn, 0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) step(klast, j, a[j]);
+      for (int j = 0; j < KJ; ++j) step(klast, j, a[j]);
     }
 #pragma unroll
     for (int cs = 0; cs < NCS; ++cs)
@@ -920,7 +927,7 @@ __device__ __noinline__ void update_strip(const Mat<typename Prec<R>::C>& Ain, i
                                           const typename Prec<R>::C (*Ub)[kSW]) {
   const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
   typedef const typename Prec<R>::C(*Rows)[kSW];
-  if (sw > 32 && s <= 16) {  // one reduction chunk: two strips of at most 32 columns
+  if (sw > 32 && s <= kUpdChunk<R>) {  // one reduction chunk: two strips of at most 32 columns
     update_rows_multi<R, 2, 2>(A, r0, s, s0, 32, Ub);
     update_rows_multi<R, 2, 2>(A, r0, s, s0 + 32, sw - 32, reinterpret_cast<Rows>(&Ub[0][32]));
   } else if (sw > 48) {
