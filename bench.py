@@ -6,7 +6,10 @@ with tau00, for the 8192 instances of the fcc NiAu 50/50 workload with a
 135-atom LIZ (N = 2160, lmax = 3, 256 sites x 32 contour energies).  Inputs
 are synthetic and resident on the GPU before the timed region.
 
-Prints one JSON line (see the contract in the design doc).
+Prints one JSON line: metric, value (solves/s), timing, the roofline of the
+dominant kernel (HIP-event timing, measured HBM traffic when the kernel
+sources match the profiled ones), the other forms timed on the same
+instances, and the CPU oracle baseline.
 """
 
 from __future__ import annotations
@@ -178,7 +181,7 @@ def main():
         log(f"[bench] copied {args.copy_calib} MiB three times")
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.precision == "fp32ir" and args.mode == "chunked":
