@@ -834,23 +834,26 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
   store_pv(pb);
 }
 
-// As update_rows for narrow strips (the sibling updates of the recursive
-// panel, reductions of at most 32 there): each wave takes RB row blocks at a
-// time (row blocks rb + 16 kLuWaves i, i < RB) and issues all their loads
-// together, so that a narrow update is not bound by one memory latency per
-// 16 rows; lane (li, lq) supplies k = kc + lq + 4 j at step j, so that a
-// reduction of s needs only ceil(s / 4) MFMA steps.
-template <typename R, int NCS, int RB>
+// As update_rows for short reductions, s <= 4 KA <= 32 (the sibling updates
+// of the recursive panel), sw <= 16 NCS: each wave takes RB row blocks at a time
+// (row blocks rb + 16 kLuWaves i, i < RB), with all their operands for the
+// whole reduction loaded together, one group ahead; lane (li, lq) supplies
+// k = lq + 4 j at step j, so that a reduction of s takes ceil(s / 4) MFMA
+// steps.  A finished group's results are stored after the next group's loads
+// have been issued, so that they complete behind a group of MFMA work.
+template <typename R, int NCS, int RB, int KA>
 __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0,
                                                   int sw, const typename Prec<R>::C (*Ub)[kSW]) {
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
+  static_assert(KA == 4 || KA == 8, "L entries per lane and row block: s <= 4 KA");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int N = (int)A.N;
   const int rstart = r0 + s;
   const int64_t pc0 = A.phys(r0);
   constexpr int kStep = 16 * kLuWaves;
+  const int nj = (s + 3) >> 2;  // MFMA steps
   int64_t ccol[NCS];
   bool cok[NCS];
 #pragma unroll
@@ -858,66 +861,90 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
     cok[cs] = 16 * cs + li < sw;
     ccol[cs] = A.phys(s0 + min(16 * cs + li, sw - 1));
   }
-  for (int rb = rstart + 16 * wave; rb < N; rb += RB * kStep) {
-    V4 accr[RB][NCS], acci[RB][NCS];
-#pragma unroll
-    for (int b = 0; b < RB; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int v = rb + b * kStep + Prec<R>::drow(r, lq);
-        const auto crow = glb(A.base + A.phys(v < N ? v : rstart) * A.N);
-#pragma unroll
-        for (int cs = 0; cs < NCS; ++cs) {
-          const C cv = crow[ccol[cs]];  // clamped in range; unused entries are not stored
-          accr[b][cs][r] = cv.x;
-          acci[b][cs][r] = cv.y;
-        }
-      }
-    LSMS_GLOBAL const C* arow[RB];
+  int rb = rstart + 16 * wave;
+  if (rb >= N) return;
+  // operands of the group starting at row block q: clamped in-range loads
+  // (rows >= N and columns >= sw are never stored; L entries of columns
+  // >= s, clamped to s - 1, meet zero rows of Ub)
+  C cn[RB][NCS][4], an[RB][KA];
+  auto load_group = [&](int q) {
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
-      const int va = rb + b * kStep + li;
-      arow[b] = glb(A.base + A.phys(va < N ? va : rstart) * A.N + pc0);
-    }
-    for (int kc = 0; kc < s; kc += 16) {
-      // k = kc + lq + 4 j here, so that MFMA steps past the end of a short
-      // reduction are skipped
-      const int nj = min(4, (s - kc + 3) >> 2);
-      C a[RB][4];
 #pragma unroll
-      for (int b = 0; b < RB; ++b)
+      for (int r = 0; r < 4; ++r) {
+        const int v = q + b * kStep + Prec<R>::drow(r, lq);
+        const auto crow = glb(A.base + A.phys(v < N ? v : rstart) * A.N);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) a[b][j] = arow[b][min(kc + lq + 4 * j, s - 1)];  // Ub rows >= s are zero
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (j >= nj) break;
-        const int k = (kc + lq + 4 * j) & (kPanelMax - 1);
-#pragma unroll
-        for (int cs = 0; cs < NCS; ++cs) {
-          const C u = ((const LSMS_LDS C(*)[kSW])Ub)[k][16 * cs + li];
-#pragma unroll
-          for (int b = 0; b < RB; ++b) {
-            const R nx = -a[b][j].x, ny = -a[b][j].y;
-            accr[b][cs] = Prec<R>::mfma(nx, u.x, accr[b][cs]);
-            accr[b][cs] = Prec<R>::mfma(a[b][j].y, u.y, accr[b][cs]);
-            acci[b][cs] = Prec<R>::mfma(nx, u.y, acci[b][cs]);
-            acci[b][cs] = Prec<R>::mfma(ny, u.x, acci[b][cs]);
-          }
-        }
+        for (int cs = 0; cs < NCS; ++cs) cn[b][cs][r] = crow[ccol[cs]];
       }
+      const int va = q + b * kStep + li;
+      const auto arow = glb(A.base + A.phys(va < N ? va : rstart) * A.N + pc0);
+#pragma unroll
+      for (int j = 0; j < KA; ++j)
+        if (j < nj) an[b][j] = arow[min(lq + 4 * j, s - 1)];
     }
+  };
+  C pv[RB][NCS][4];
+  int pb = -1;
+  auto store_group = [&](int q) {
 #pragma unroll
     for (int b = 0; b < RB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int v = rb + b * kStep + Prec<R>::drow(r, lq);
+        const int v = q + b * kStep + Prec<R>::drow(r, lq);
         if (v >= N) continue;
         const auto crow = glb(A.base + A.phys(v) * A.N);
 #pragma unroll
         for (int cs = 0; cs < NCS; ++cs)
-          if (cok[cs]) crow[ccol[cs]] = zmake(accr[b][cs][r], acci[b][cs][r]);
+          if (cok[cs]) crow[ccol[cs]] = pv[b][cs][r];
       }
+  };
+  load_group(rb);
+  for (; rb < N; rb += RB * kStep) {
+    V4 accr[RB][NCS], acci[RB][NCS];
+    C a[RB][KA];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+#pragma unroll
+      for (int cs = 0; cs < NCS; ++cs)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          accr[b][cs][r] = cn[b][cs][r].x;
+          acci[b][cs][r] = cn[b][cs][r].y;
+        }
+#pragma unroll
+      for (int j = 0; j < KA; ++j) a[b][j] = an[b][j];
+    }
+    const int rn = rb + RB * kStep;
+    if (rn < N) load_group(rn);
+    if (pb >= 0) store_group(pb);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < KA; ++j) {
+      if (j >= nj) break;
+      const int k = lq + 4 * j;
+#pragma unroll
+      for (int cs = 0; cs < NCS; ++cs) {
+        const C u = ((const LSMS_LDS C(*)[kSW])Ub)[k][16 * cs + li];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          const R nx = -a[b][j].x, ny = -a[b][j].y;
+          accr[b][cs] = Prec<R>::mfma(nx, u.x, accr[b][cs]);
+          accr[b][cs] = Prec<R>::mfma(a[b][j].y, u.y, accr[b][cs]);
+          acci[b][cs] = Prec<R>::mfma(nx, u.y, acci[b][cs]);
+          acci[b][cs] = Prec<R>::mfma(ny, u.x, acci[b][cs]);
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int cs = 0; cs < NCS; ++cs)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pv[b][cs][r] = zmake(accr[b][cs][r], acci[b][cs][r]);
+    pb = rb;
   }
+  store_group(pb);
 }
 
 // A(v, s0 + j) -= sum_{k < s} A(v, r0 + k) Ub[k][j] for v in [r0 + s, N),
@@ -927,17 +954,32 @@ __device__ __noinline__ void update_strip(const Mat<typename Prec<R>::C>& Ain, i
                                           const typename Prec<R>::C (*Ub)[kSW]) {
   const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
   typedef const typename Prec<R>::C(*Rows)[kSW];
-  if (sw > 32 && s <= kUpdChunk<R>) {  // one reduction chunk: two strips of at most 32 columns
-    update_rows_multi<R, 2, 2>(A, r0, s, s0, 32, Ub);
-    update_rows_multi<R, 2, 2>(A, r0, s, s0 + 32, sw - 32, reinterpret_cast<Rows>(&Ub[0][32]));
+  if (s <= 16) {  // short reductions: operands of whole row blocks at once
+    if (sw > 32) {  // two strips of at most 32 columns
+      update_rows_multi<R, 2, 1, 4>(A, r0, s, s0, 32, Ub);
+      update_rows_multi<R, 2, 1, 4>(A, r0, s, s0 + 32, sw - 32, reinterpret_cast<Rows>(&Ub[0][32]));
+    } else if (sw > 16) {
+      update_rows_multi<R, 2, 1, 4>(A, r0, s, s0, sw, Ub);
+    } else {
+      update_rows_multi<R, 1, 2, 4>(A, r0, s, s0, sw, Ub);
+    }
+  } else if (s <= 32) {
+    if (sw > 32) {
+      update_rows_multi<R, 2, 1, 8>(A, r0, s, s0, 32, Ub);
+      update_rows_multi<R, 2, 1, 8>(A, r0, s, s0 + 32, sw - 32, reinterpret_cast<Rows>(&Ub[0][32]));
+    } else if (sw > 16) {
+      update_rows_multi<R, 2, 1, 8>(A, r0, s, s0, sw, Ub);
+    } else {
+      update_rows_multi<R, 1, 1, 8>(A, r0, s, s0, sw, Ub);
+    }
   } else if (sw > 48) {
     update_rows<R, 4>(A, r0, s, s0, sw, Ub);
   } else if (sw > 32) {
     update_rows<R, 3>(A, r0, s, s0, sw, Ub);
   } else if (sw > 16) {
-    update_rows_multi<R, 2, 2>(A, r0, s, s0, sw, Ub);
+    update_rows<R, 2>(A, r0, s, s0, sw, Ub);
   } else {
-    update_rows_multi<R, 1, 4>(A, r0, s, s0, sw, Ub);
+    update_rows<R, 1>(A, r0, s, s0, sw, Ub);
   }
 }
 
