@@ -153,6 +153,18 @@ __device__ __forceinline__ void argmax_dpp(R& best, int& bi) {
   }
 }
 
+// Sum over each aligned group of 8 lanes, by DPP (xor 1, xor 2, then the
+// mirror inside the group of 8), the same value in all 8 lanes (the two
+// operands of every addition are the same pair in both lanes).  The 8 lanes
+// of a group must be active together.
+template <typename R>
+__device__ __forceinline__ R sum8(R x) {
+  x += dpp_val<kDppX1>(x);
+  x += dpp_val<kDppX2>(x);
+  x += dpp_val<kDppHalfMirror>(x);
+  return x;
+}
+
 // (best, bi) of every lane becomes the wave's maximum of best, ties to the
 // smallest bi; all lanes must be active.
 template <typename R>
@@ -369,12 +381,8 @@ __device__ __noinline__ void invert_unit_lower(const Mat<typename Prec<R>::C>& A
           si += l.x * xr[m].y + l.y * xr[m].x;
         }
       }
-      sr += __shfl_xor(sr, 1);
-      si += __shfl_xor(si, 1);
-      sr += __shfl_xor(sr, 2);
-      si += __shfl_xor(si, 2);
-      sr += __shfl_xor(sr, 4);
-      si += __shfl_xor(si, 4);
+      sr = sum8(sr);
+      si = sum8(si);
 #pragma unroll
       for (int m = 0; m < kNB / 8; ++m)
         if (p + 8 * m == i) xr[m] = zmake(-sr, -si);
@@ -419,12 +427,8 @@ __device__ __noinline__ void invert_upper(const Mat<typename Prec<R>::C>& Ain, i
           si += u.x * xr[m].y + u.y * xr[m].x;
         }
       }
-      sr += __shfl_xor(sr, 1);
-      si += __shfl_xor(si, 1);
-      sr += __shfl_xor(sr, 2);
-      si += __shfl_xor(si, 2);
-      sr += __shfl_xor(sr, 4);
-      si += __shfl_xor(si, 4);
+      sr = sum8(sr);
+      si = sum8(si);
       const C xi = zmul(zmake(-sr, -si), zinv(sh.U[i][i]));
 #pragma unroll
       for (int m = 0; m < kNB / 8; ++m)
