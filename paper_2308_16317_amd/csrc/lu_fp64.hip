@@ -306,7 +306,11 @@ __device__ void tri_apply(const MixedBufs& b, int r0, int s, LuSmem<float>& sh) 
 // z[v] -= sum_{k < s} A(v, r0 + k) sh.U[k] for v in [v0, N): 16-row blocks
 // per wave, accumulators starting from the loaded block of z; the reduction
 // in chunks of 16 (lane (li, lq) supplies k = kc + 4 lq + j at MFMA step j),
-// loads one chunk (or, in the last chunk, the next row block) ahead.
+// loads one chunk (or, in the last chunk, the next row block) ahead.  Loads
+// are unconditional from clamped in-range addresses (rows >= N are never
+// stored; L entries of columns >= s meet the zero rows s.. of sh.U), and a
+// finished block is stored after the next block's first loads are issued
+// (loads and stores share one completion counter).
 template <int NCT>
 __device__ void rhs_update_rows(const Mat<zf>& A, const MixedBufs& b, int r0, int s, int v0,
                                 const LuSmem<float>& sh) {
@@ -314,30 +318,32 @@ __device__ void rhs_update_rows(const Mat<zf>& A, const MixedBufs& b, int r0, in
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int N = (int)A.N;
-  const int64_t pr0 = A.phys(r0) + 4 * lq;
+  const int64_t pr0 = A.phys(r0);
   int rb = v0 + 16 * wave;
   if (rb < N) {
-    zf cn[NCT][4], an[4];
+    zf cn[NCT][4], an[4], pv[NCT][4];
+    int pb = -1;
     auto load_c = [&](int q) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int v = q + Prec<float>::drow(r, lq);
+        const int v = min(q + Prec<float>::drow(r, lq), N - 1);
 #pragma unroll
-        for (int t = 0; t < NCT; ++t) {
-          zf cv = zmake(0.f, 0.f);
-          if (v < N) cv = b.z[(int64_t)v * b.kp + 16 * t + li];
-          cn[t][r] = cv;
-        }
+        for (int t = 0; t < NCT; ++t) cn[t][r] = b.z[(int64_t)v * b.kp + 16 * t + li];
       }
     };
     auto load_a = [&](int q, int kc) {
       const int va = q + li;
-      const auto arow = A.base + A.phys(va < N ? va : v0) * A.N + pr0 + kc;
+      const auto arow = A.base + A.phys(va < N ? va : v0) * A.N + pr0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        zf av = zmake(0.f, 0.f);
-        if (va < N && kc + 4 * lq + j < s) av = arow[j];
-        an[j] = av;
+      for (int j = 0; j < 4; ++j) an[j] = arow[min(kc + 4 * lq + j, s - 1)];
+    };
+    auto store_pv = [&](int q) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int v = q + Prec<float>::drow(r, lq);
+        if (v >= N) continue;
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) b.z[(int64_t)v * b.kp + 16 * t + li] = pv[t][r];
       }
     };
     load_c(rb);
@@ -362,6 +368,10 @@ __device__ void rhs_update_rows(const Mat<zf>& A, const MixedBufs& b, int r0, in
           load_c(rn);
           load_a(rn, 0);
         }
+        if (kc == 0 && pb >= 0) {
+          store_pv(pb);
+          pb = -1;
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int k = (kc + 4 * lq + j) & (kNB - 1);
@@ -377,13 +387,12 @@ __device__ void rhs_update_rows(const Mat<zf>& A, const MixedBufs& b, int r0, in
         }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int v = rb + Prec<float>::drow(r, lq);
-        if (v >= N) continue;
+      for (int t = 0; t < NCT; ++t)
 #pragma unroll
-        for (int t = 0; t < NCT; ++t) b.z[(int64_t)v * b.kp + 16 * t + li] = zmake(ar[t][r], ai[t][r]);
-      }
+        for (int r = 0; r < 4; ++r) pv[t][r] = zmake(ar[t][r], ai[t][r]);
+      pb = rb;
     }
+    if (pb >= 0) store_pv(pb);
   }
   __syncthreads();
 }
@@ -443,21 +452,42 @@ __device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, bool hav
     const int tile = wave % ntile, split = wave / ntile;
     const int rt = tile & 3, ct = tile >> 2;
     const int k0 = c + w, klen = N - k0;
-    const int kchunk = ((klen + nsplit - 1) / nsplit + 3) & ~3;
+    const int kchunk = ((klen + nsplit - 1) / nsplit + 15) & ~15;
     const int ka = k0 + split * kchunk, kz = min(N, ka + kchunk);
     V4 ar = V4{0.f, 0.f, 0.f, 0.f}, ai = V4{0.f, 0.f, 0.f, 0.f};
     const int row = c + 16 * rt + li;
     const bool rok = 16 * rt + li < w;
     const auto urow = A.base + A.phys(rok ? row : c) * A.N;
-    for (int kb = ka; kb < kz; kb += 4) {
-      const int k = kb + lq;
-      const bool kok = k < kz;
-      const zf a = (rok && kok) ? urow[A.phys(k)] : zmake(0.f, 0.f);
-      const zf y = kok ? b.z[(int64_t)k * b.kp + 16 * ct + li] : zmake(0.f, 0.f);
-      ar = Prec<float>::mfma(a.x, y.x, ar);
-      ar = Prec<float>::mfma(-a.y, y.y, ar);
-      ai = Prec<float>::mfma(a.x, y.y, ai);
-      ai = Prec<float>::mfma(a.y, y.x, ai);
+    // chunks of 16 (lane (li, lq) takes k = kb + 4 lq + j at step j), loaded
+    // one chunk ahead from clamped addresses; entries past the range are
+    // zeroed before they enter the product
+    zf an[4], yn[4];
+    auto ld = [&](int kb) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = min(kb + 4 * lq + j, N - 1);
+        an[j] = urow[A.phys(k)];
+        yn[j] = b.z[(int64_t)k * b.kp + 16 * ct + li];
+      }
+    };
+    if (ka < kz) ld(ka);
+    for (int kb = ka; kb < kz; kb += 16) {
+      zf a[4], y[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        a[j] = an[j];
+        y[j] = yn[j];
+      }
+      if (kb + 16 < kz) ld(kb + 16);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool ok = rok && kb + 4 * lq + j < kz;
+        const float axr = ok ? a[j].x : 0.f, axi = ok ? a[j].y : 0.f;
+        ar = Prec<float>::mfma(axr, y[j].x, ar);
+        ar = Prec<float>::mfma(-axi, y[j].y, ar);
+        ai = Prec<float>::mfma(axr, y[j].y, ai);
+        ai = Prec<float>::mfma(axi, y[j].x, ai);
+      }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -527,22 +557,16 @@ __device__ void residual_rows(const Mat<zd>& A, const MixedBufs& b) {
     const int va = rb + li;
     const bool rok = va < N;
     const auto arow = A.base + A.phys(rok ? va : 0) * A.N;
-    // A(va, k) for k < Nd is at arow[kk + k], for k >= Nd at arow[k - Nd]
+    // A(va, k) for k < Nd is at arow[kk + k], for k >= Nd at arow[k - Nd];
+    // clamped in-range loads, entries of k >= N zeroed before the product
     zd an[4], yn[NCT][4];
     auto load = [&](int kc) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int k = kc + 4 * lq + j;
-        const bool kok = k < N;
-        zd av = zmake(0.0, 0.0);
-        if (rok && kok) av = arow[A.phys(k)];
-        an[j] = av;
+        const int k = min(kc + 4 * lq + j, N - 1);
+        an[j] = arow[A.phys(k)];
 #pragma unroll
-        for (int t = 0; t < NCT; ++t) {
-          zd y = zmake(0.0, 0.0);
-          if (kok) y = b.Y[(int64_t)k * b.kp + 16 * t + li];
-          yn[t][j] = y;
-        }
+        for (int t = 0; t < NCT; ++t) yn[t][j] = b.Y[(int64_t)k * b.kp + 16 * t + li];
       }
     };
     load(0);
@@ -550,7 +574,8 @@ __device__ void residual_rows(const Mat<zd>& A, const MixedBufs& b) {
       zd a[4], y[NCT][4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        a[j] = an[j];
+        const bool ok = kc + 4 * lq + j < N;
+        a[j] = ok ? an[j] : zmake(0.0, 0.0);
 #pragma unroll
         for (int t = 0; t < NCT; ++t) y[t][j] = yn[t][j];
       }
