@@ -279,15 +279,21 @@ __device__ void tri_apply(const MixedBufs& b, int r0, int s, LuSmem<float>& sh) 
   V4 ar = V4{0.f, 0.f, 0.f, 0.f}, ai = V4{0.f, 0.f, 0.f, 0.f};
   const bool act = ct < nct;
   if (act) {
-    for (int kb = 0; kb < s; kb += 4) {
-      const int k = kb + lq;
+    // the lane's z entries for the whole block, loaded together (rows
+    // clamped to the block; X is zero in the columns k >= s)
+    zf y[kNB / 4];
+#pragma unroll
+    for (int m = 0; m < kNB / 4; ++m) y[m] = b.z[(int64_t)(r0 + min(4 * m + lq, s - 1)) * b.kp + 16 * ct + li];
+#pragma unroll
+    for (int m = 0; m < kNB / 4; ++m) {
+      if (4 * m >= s) break;
+      const int k = 4 * m + lq;
       const zf x = sh.X[16 * rt + li][k];
-      const zf y = (k < s) ? b.z[(int64_t)(r0 + k) * b.kp + 16 * ct + li] : zmake(0.f, 0.f);
       const float xr = (k < s) ? x.x : 0.f, xi = (k < s) ? x.y : 0.f;
-      ar = Prec<float>::mfma(xr, y.x, ar);
-      ar = Prec<float>::mfma(-xi, y.y, ar);
-      ai = Prec<float>::mfma(xr, y.y, ai);
-      ai = Prec<float>::mfma(xi, y.x, ai);
+      ar = Prec<float>::mfma(xr, y[m].x, ar);
+      ar = Prec<float>::mfma(-xi, y[m].y, ar);
+      ai = Prec<float>::mfma(xr, y[m].y, ai);
+      ai = Prec<float>::mfma(xi, y[m].x, ai);
     }
   }
   __syncthreads();  // every wave has read z[r0 ..] and sh.X
