@@ -130,9 +130,10 @@ __device__ void build_setup(const lsms_prob_dev& p, const lsms_gaunt_dev& g, int
 // for each row block i of the chunk, 2 lmax + 2 tasks: one per order
 // m = 0 .. 2 lmax of Y_L''(R_ij) and one for the Hankel functions
 // h_l''(kappa R_ij); task (m, i) is thread 64 m + i, so that a wave runs one
-// kind of task.  Phase B: each thread owns (row block,
-// L) pairs and sweeps the kk columns L', entry (L, L') of row block i at
-// index L + kk (i + nb L'), so consecutive threads write consecutive rows.
+// kind of task.  Phase B: each thread owns one L and two row blocks (which
+// share the Gaunt lists) and sweeps the kk columns L', entry (L, L') of row
+// block i at index L + kk (i + nb L'), so consecutive threads write
+// consecutive rows.
 template <int kNT>
 __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int inst, int j, zd* __restrict__ M,
                                                   BuildSmem& sb, zf* __restrict__ M32 = nullptr) {
@@ -172,35 +173,51 @@ __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int in
       }
     }
     __syncthreads();
-    const int per_col = nb * kk;
-    for (int t = tid; t < per_col; t += kNT) {
-      const int il = t / kk;
-      const int L = t - il * kk;
-      const int iw = ib + il;
-      const int64_t o0 = (int64_t)(kk * j) * N + (int64_t)kk * iw + L;
-      zd* out = M + o0;
-      zf* out32 = M32 ? M32 + o0 : nullptr;
-      if (iw == j) {
-        for (int Lp = 0; Lp < kk; ++Lp) {
-          out[(int64_t)Lp * N] = zmake(L == Lp ? 1.0 : 0.0, 0.0);
-          if (out32) out32[(int64_t)Lp * N] = zmake(L == Lp ? 1.f : 0.f, 0.f);
+    // a thread takes one L and two row blocks 2 ip, 2 ip + 1 of the chunk,
+    // which share the Gaunt list of every (L, L')
+    const int npair = (nb + 1) >> 1;
+    for (int t = tid; t < npair * kk; t += kNT) {
+      const int ip = t / kk;
+      const int L = t - ip * kk;
+      const int i0 = 2 * ip, i1 = min(2 * ip + 1, nb - 1);
+      const bool two = 2 * ip + 1 < nb;
+      const int iw0 = ib + i0, iw1 = ib + i1;
+      const int64_t o0 = (int64_t)(kk * j) * N + (int64_t)kk * iw0 + L;
+      const int64_t o1 = (int64_t)(kk * j) * N + (int64_t)kk * iw1 + L;
+      const zd tp0 = zmul(sb.t[sb.spec[i0]][l_of(L)], pref);
+      const zd tp1 = zmul(sb.t[sb.spec[i1]][l_of(L)], pref);
+      for (int Lp = 0; Lp < kk; ++Lp) {
+        double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
+        const int pidx = L + kk * Lp;
+        const int e0 = sb.rp[pidx], e1 = sb.rp[pidx + 1];
+        for (int k = e0; k < e1; ++k) {
+          const double c = sb.coef[k];
+          const int lp = sb.lpp[k], lo = sb.lof[k];
+          const double cy0 = c * sb.Y[i0][lp], cy1 = c * sb.Y[i1][lp];
+          const zd h0 = sb.h[i0][lo], h1 = sb.h[i1][lo];
+          sr0 += cy0 * h0.x;
+          si0 += cy0 * h0.y;
+          sr1 += cy1 * h1.x;
+          si1 += cy1 * h1.y;
         }
-      } else {
-        const zd tl = sb.t[sb.spec[il]][l_of(L)];
-        const zd tp = zmul(tl, pref);
-        for (int Lp = 0; Lp < kk; ++Lp) {
-          double sr = 0.0, si = 0.0;
-          const int pidx = L + kk * Lp;
-          const int e0 = sb.rp[pidx], e1 = sb.rp[pidx + 1];
-          for (int k = e0; k < e1; ++k) {
-            const double cy = sb.coef[k] * sb.Y[il][sb.lpp[k]];
-            const zd h = sb.h[il][sb.lof[k]];
-            sr += cy * h.x;
-            si += cy * h.y;
-          }
-          const zd tg = zmul(tp, zmake(sr, si));
-          out[(int64_t)Lp * N] = zmake(-tg.x, -tg.y);
-          if (out32) out32[(int64_t)Lp * N] = zmake((float)-tg.x, (float)-tg.y);
+        zd v0, v1;
+        if (iw0 == j) {
+          v0 = zmake(L == Lp ? 1.0 : 0.0, 0.0);
+        } else {
+          const zd tg = zmul(tp0, zmake(sr0, si0));
+          v0 = zmake(-tg.x, -tg.y);
+        }
+        if (iw1 == j) {
+          v1 = zmake(L == Lp ? 1.0 : 0.0, 0.0);
+        } else {
+          const zd tg = zmul(tp1, zmake(sr1, si1));
+          v1 = zmake(-tg.x, -tg.y);
+        }
+        M[o0 + (int64_t)Lp * N] = v0;
+        if (M32) M32[o0 + (int64_t)Lp * N] = zmake((float)v0.x, (float)v0.y);
+        if (two) {
+          M[o1 + (int64_t)Lp * N] = v1;
+          if (M32) M32[o1 + (int64_t)Lp * N] = zmake((float)v1.x, (float)v1.y);
         }
       }
     }
