@@ -22,8 +22,14 @@ namespace lsms {
 constexpr int kLuThreads = 512;
 constexpr int kLuWaves = kLuThreads / 64;
 constexpr int kNB = 64;         // triangular blocks and LDS tiles
-constexpr int kSW = 64;         // trailing-update strip width (columns)
+constexpr int kSW = 64;         // trailing-update strip width in FP64 (columns)
 constexpr int kPanelMax = 128;  // maximum panel width (two triangular blocks)
+
+// Strip width of the trailing update: 64 columns in FP64; 96 in FP32, whose
+// 128-row U12 strip of 96 columns takes the LDS of FP64's 64, and whose
+// update, bound by HBM traffic, then re-reads L21 a third less often.
+template <typename R>
+constexpr int kSWp = sizeof(R) == 4 ? 96 : kSW;
 constexpr int kMaxKK = 25;
 constexpr int kMaxWL = 8;
 
@@ -58,8 +64,8 @@ struct Prec<float> {
 template <typename R>
 struct LuSmem {
   typedef typename Prec<R>::C C;
-  C X[kNB][kNB];    // inverse of a triangular block
-  C U[kNB][kSW];    // U12 strip; block staging; Gauss-Jordan workspace at the end
+  C X[kNB][kSWp<R>];  // inverse of a triangular block (columns < 64)
+  C U[kNB][kSWp<R>];  // U12 strip; block staging; Gauss-Jordan workspace at the end
                     // (X and U together: the 128-row U12 strip of a wide panel)
   C cand[2][kLuWaves][kMaxWL];  // each wave's pivot candidate row (two buffers)
   R candv[2][kLuWaves];         // its magnitude |Re| + |Im|
@@ -106,12 +112,12 @@ struct Mat {
   }
 };
 
-// The 128 x kSW view of sh.X and sh.U (contiguous), holding the U12 strip
+// The 128 x kSWp view of sh.X and sh.U (contiguous), holding the U12 strip
 // of a panel wider than kNB.
 template <typename R>
-__device__ __forceinline__ typename Prec<R>::C (*ustrip2(LuSmem<R>& sh))[kSW] {
-  static_assert(sizeof(sh.X) == kNB * kSW * sizeof(typename Prec<R>::C), "X rows must match U rows");
-  return reinterpret_cast<typename Prec<R>::C(*)[kSW]>(&sh.X[0][0]);
+__device__ __forceinline__ typename Prec<R>::C (*ustrip2(LuSmem<R>& sh))[kSWp<R>] {
+  static_assert(sizeof(sh.X) == kNB * kSWp<R> * sizeof(typename Prec<R>::C), "X rows must match U rows");
+  return reinterpret_cast<typename Prec<R>::C(*)[kSWp<R>]>(&sh.X[0][0]);
 }
 
 template <typename R>
@@ -446,46 +452,48 @@ __device__ __noinline__ void invert_upper(const Mat<typename Prec<R>::C>& Ain, i
 // X_a and X_b being the inverses of the two unit lower diagonal blocks
 // (64 x 64 each, row-major at xg and xg + 64*64, zero outside their blocks).
 // The result goes to the 128-row view of sh.X and sh.U (rows >= w zero) and,
-// if `store`, to A.  Sixteen output tiles per 64-row half, two per wave.
+// if `store`, to A.  4 x kSWp/16 output tiles per 64-row half, kSWp/32 per
+// wave.
 template <typename R>
 __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, int c, int w, int s0, int sw,
                                          bool store, const typename Prec<R>::C* __restrict__ xg, LuSmem<R>& sh) {
   const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
-  C(*U2)[kSW] = ustrip2(sh);
+  constexpr int NT = kSWp<R> / 32;  // column tiles per wave
+  C(*U2)[kSWp<R>] = ustrip2(sh);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   // waves w and w + 4 share a SIMD: they take row tiles r and 3 - r, so
   // every SIMD carries the same share of the triangular work
-  const int rt = wave < 4 ? wave : 7 - wave, ct0 = 2 * (wave >> 2);
+  const int rt = wave < 4 ? wave : 7 - wave, ct0 = NT * (wave >> 2);
   const int row = 16 * rt + li;
   const int wb = w - kNB;  // rows of the second block
-  int64_t bcol[2];
-  bool cok[2];
+  int64_t bcol[NT];
+  bool cok[NT];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NT; ++t) {
     const int col = 16 * (ct0 + t) + li;
     cok[t] = col < sw;
     bcol[t] = A.phys(s0 + min(col, sw - 1));
   }
-  V4 ar[2], ai[2];
+  V4 ar[NT], ai[NT];
   // U_a = X_a B, B[k][col] = A(c + k, s0 + col)
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NT; ++t) {
     ar[t] = V4{R(0), R(0), R(0), R(0)};
     ai[t] = V4{R(0), R(0), R(0), R(0)};
   }
   {
     const int kend = 16 * rt + 16;
-    C bn[2][4], xn[4];
+    C bn[NT][4], xn[4];
     trsm_load_chunk(A, c, kNB, 0, lk, bcol, cok, bn);
 #pragma unroll
     for (int j = 0; j < 4; ++j) xn[j] = xg[row * kNB + 4 * lk + j];
     for (int kc = 0; kc < kend; kc += 16) {
-      C b[2][4], x[4];
+      C b[NT][4], x[4];
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+      for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int j = 0; j < 4; ++j) b[t][j] = bn[t][j];
 #pragma unroll
@@ -498,7 +506,7 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NT; ++t) {
           ar[t] = Prec<R>::mfma(x[j].x, b[t][j].x, ar[t]);
           ar[t] = Prec<R>::mfma(-x[j].y, b[t][j].y, ar[t]);
           ai[t] = Prec<R>::mfma(x[j].x, b[t][j].y, ai[t]);
@@ -508,7 +516,7 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
   }
   __syncthreads();  // earlier readers of the strip are done
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * rt + Prec<R>::drow(r, lk), col = 16 * (ct0 + t) + li;
@@ -519,7 +527,7 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
   __syncthreads();
   // T = A(c + 64 + i, strip) - L(c + 64 + i, c .. c+63) U_a, rows i < wb
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * rt + Prec<R>::drow(r, lk);
@@ -546,7 +554,7 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
         const int k = kc + 4 * lk + j;
         const R nx = -l[j].x, ny = -l[j].y;
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NT; ++t) {
           const C u = U2[k][16 * (ct0 + t) + li];
           ar[t] = Prec<R>::mfma(nx, u.x, ar[t]);
           ar[t] = Prec<R>::mfma(l[j].y, u.y, ar[t]);
@@ -557,7 +565,7 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
     }
   }
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * rt + Prec<R>::drow(r, lk), col = 16 * (ct0 + t) + li;
@@ -566,7 +574,7 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
   __syncthreads();
   // U_b = X_b T
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NT; ++t) {
     ar[t] = V4{R(0), R(0), R(0), R(0)};
     ai[t] = V4{R(0), R(0), R(0), R(0)};
   }
@@ -589,7 +597,7 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
         const int k = kc + 4 * lk + j;
         const C x = xc[j];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NT; ++t) {
           const C b = U2[kNB + k][16 * (ct0 + t) + li];
           ar[t] = Prec<R>::mfma(x.x, b.x, ar[t]);
           ar[t] = Prec<R>::mfma(-x.y, b.y, ar[t]);
@@ -601,7 +609,7 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
   }
   __syncthreads();  // T fully read
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * rt + Prec<R>::drow(r, lk), col = 16 * (ct0 + t) + li;
@@ -622,21 +630,21 @@ __device__ __forceinline__ void save_x(const LuSmem<R>& sh, typename Prec<R>::C*
 // Loads the B operands of one 16-deep chunk of trsm_strip: lane (li, lk)
 // takes rows k = kc + 4 lk + j (j < 4) of its two columns, the row clamped to
 // s - 1 and the column to the strip (in-range, straight-line loads).
-template <typename C>
+template <typename C, int NT>
 __device__ __forceinline__ void trsm_load_chunk(const Mat<C>& A, int r0, int s, int kc, int lk,
-                                                const int64_t (&bcol)[2], const bool (&cok)[2], C (&dst)[2][4]) {
+                                                const int64_t (&bcol)[NT], const bool (&cok)[NT], C (&dst)[NT][4]) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     // rows k >= s clamped to s - 1: X is zero in those columns
     const auto rowp = glb(A.base + A.phys(r0 + min(kc + 4 * lk + j, s - 1)) * A.N);
 #pragma unroll
-    for (int t = 0; t < 2; ++t) dst[t][j] = rowp[bcol[t]];  // columns >= sw are never stored
+    for (int t = 0; t < NT; ++t) dst[t][j] = rowp[bcol[t]];  // columns >= sw are never stored
   }
 }
 
 // U = X * A(r0 .. r0+s-1, s0 .. s0+sw-1) into sh.U rows 0..63 (rows >= s are
-// zero), and, if `store`, also into those rows of A.  Sixteen 16x16 output
-// tiles, two per wave.  The reduction runs in chunks of 16 (lane (li, lk)
+// zero), and, if `store`, also into those rows of A.  4 x kSWp/16 output
+// tiles of 16x16, kSWp/32 per wave.  The reduction runs in chunks of 16 (lane (li, lk)
 // supplies k = kc + 4 lk + j at MFMA step j), the next chunk being loaded
 // while the current one is multiplied; X is lower triangular, so row tile rt
 // stops at k = 16 rt + 16.
@@ -646,32 +654,33 @@ __device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& Ain, int
   const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
+  constexpr int NT = kSWp<R> / 32;  // column tiles per wave
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int rt = wave < 4 ? wave : 7 - wave;  // row tile (r and 3 - r per SIMD, as in trsm2_strip)
-  const int ct0 = 2 * (wave >> 2);            // first of two column tiles
-  V4 ar[2], ai[2];
+  const int ct0 = NT * (wave >> 2);           // first of NT column tiles
+  V4 ar[NT], ai[NT];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NT; ++t) {
     ar[t] = V4{R(0), R(0), R(0), R(0)};
     ai[t] = V4{R(0), R(0), R(0), R(0)};
   }
-  int64_t bcol[2];
-  bool cok[2];
+  int64_t bcol[NT];
+  bool cok[NT];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NT; ++t) {
     const int col = 16 * (ct0 + t) + li;
     cok[t] = col < sw;
     bcol[t] = A.phys(s0 + min(col, sw - 1));
   }
   const int row = 16 * rt + li;
   const int kend = min(s, 16 * rt + 16);
-  C bn[2][4];
+  C bn[NT][4];
   if (kend > 0) trsm_load_chunk(A, r0, s, 0, lk, bcol, cok, bn);
   for (int kc = 0; kc < kend; kc += 16) {
-    C b[2][4];
+    C b[NT][4];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int j = 0; j < 4; ++j) b[t][j] = bn[t][j];
     if (kc + 16 < kend) trsm_load_chunk(A, r0, s, kc + 16, lk, bcol, cok, bn);
@@ -682,7 +691,7 @@ __device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& Ain, int
       const R xr = (k < s) ? x.x : R(0);
       const R xi = (k < s) ? x.y : R(0);
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int t = 0; t < NT; ++t) {
         ar[t] = Prec<R>::mfma(xr, b[t][j].x, ar[t]);
         ar[t] = Prec<R>::mfma(-xi, b[t][j].y, ar[t]);
         ai[t] = Prec<R>::mfma(xr, b[t][j].y, ai[t]);
@@ -692,7 +701,7 @@ __device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& Ain, int
   }
   __syncthreads();  // earlier readers of sh.U are done
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * rt + Prec<R>::drow(r, lk), col = 16 * (ct0 + t) + li;
@@ -725,7 +734,7 @@ constexpr int kUpdChunk = sizeof(R) == 4 ? 32 : 16;
 // U[k] are zero for k >= s.
 template <typename R, int NCS>
 __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
-                                            const typename Prec<R>::C (*Ub)[kSW]) {
+                                            const typename Prec<R>::C (*Ub)[kSWp<R>]) {
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
   constexpr int KJ = kUpdChunk<R> / 4;  // MFMA steps per chunk
@@ -776,7 +785,7 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
 #pragma unroll
     for (int j = 0; j < KJ; ++j) an[j] = arow[min(kc + KJ * lq + j, s - 1)];
   };
-  const LSMS_LDS C(*U)[kSW] = (const LSMS_LDS C(*)[kSW])Ub;
+  const LSMS_LDS C(*U)[kSWp<R>] = (const LSMS_LDS C(*)[kSWp<R>])Ub;
   V4 accr[NCS], acci[NCS];
   auto step = [&](int kc, int j, const C& aj) {
     const int k = (kc + KJ * lq + j) & (kPanelMax - 1);
@@ -847,7 +856,7 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
 // have been issued, so that they complete behind a group of MFMA work.
 template <typename R, int NCS, int RB, int KA>
 __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0,
-                                                  int sw, const typename Prec<R>::C (*Ub)[kSW]) {
+                                                  int sw, const typename Prec<R>::C (*Ub)[kSWp<R>]) {
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
   static_assert(KA == 4 || KA == 8, "L entries per lane and row block: s <= 4 KA");
@@ -929,7 +938,7 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
       const int k = lq + 4 * j;
 #pragma unroll
       for (int cs = 0; cs < NCS; ++cs) {
-        const C u = ((const LSMS_LDS C(*)[kSW])Ub)[k][16 * cs + li];
+        const C u = ((const LSMS_LDS C(*)[kSWp<R>])Ub)[k][16 * cs + li];
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
           const R nx = -a[b][j].x, ny = -a[b][j].y;
@@ -952,16 +961,16 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
 }
 
 // A(v, s0 + j) -= sum_{k < s} A(v, r0 + k) Ub[k][j] for v in [r0 + s, N),
-// j < sw <= 64, s <= 128 (Ub in LDS, rows k >= s zero).
+// j < sw <= kSWp, s <= 128 (Ub in LDS, rows k >= s zero).
 template <typename R>
 __device__ __noinline__ void update_strip(const Mat<typename Prec<R>::C>& Ain, int r0, int s, int s0, int sw,
-                                          const typename Prec<R>::C (*Ub)[kSW]) {
+                                          const typename Prec<R>::C (*Ub)[kSWp<R>]) {
   const Mat<typename Prec<R>::C> A = Ain;  // by value: fields stay in registers
-  typedef const typename Prec<R>::C(*Rows)[kSW];
+  typedef const typename Prec<R>::C(*Rows)[kSWp<R>];
   if (s <= 16) {  // short reductions: operands of whole row blocks at once
-    if (sw > 32) {  // two strips of at most 32 columns
-      update_rows_multi<R, 2, 1, 4>(A, r0, s, s0, 32, Ub);
-      update_rows_multi<R, 2, 1, 4>(A, r0, s, s0 + 32, sw - 32, reinterpret_cast<Rows>(&Ub[0][32]));
+    if (sw > 32) {  // strips of at most 32 columns
+      for (int o = 0; o < sw; o += 32)
+        update_rows_multi<R, 2, 1, 4>(A, r0, s, s0 + o, min(32, sw - o), reinterpret_cast<Rows>(&Ub[0][o]));
     } else if (sw > 16) {
       update_rows_multi<R, 2, 1, 4>(A, r0, s, s0, sw, Ub);
     } else {
@@ -969,13 +978,17 @@ __device__ __noinline__ void update_strip(const Mat<typename Prec<R>::C>& Ain, i
     }
   } else if (s <= 32) {
     if (sw > 32) {
-      update_rows_multi<R, 2, 1, 8>(A, r0, s, s0, 32, Ub);
-      update_rows_multi<R, 2, 1, 8>(A, r0, s, s0 + 32, sw - 32, reinterpret_cast<Rows>(&Ub[0][32]));
+      for (int o = 0; o < sw; o += 32)
+        update_rows_multi<R, 2, 1, 8>(A, r0, s, s0 + o, min(32, sw - o), reinterpret_cast<Rows>(&Ub[0][o]));
     } else if (sw > 16) {
       update_rows_multi<R, 2, 1, 8>(A, r0, s, s0, sw, Ub);
     } else {
       update_rows_multi<R, 1, 1, 8>(A, r0, s, s0, sw, Ub);
     }
+  } else if (kSWp<R> > 64 && sw > 80) {
+    update_rows<R, (kSWp<R> > 64 ? 6 : 4)>(A, r0, s, s0, sw, Ub);
+  } else if (kSWp<R> > 64 && sw > 64) {
+    update_rows<R, (kSWp<R> > 64 ? 5 : 4)>(A, r0, s, s0, sw, Ub);
   } else if (sw > 48) {
     update_rows<R, 4>(A, r0, s, s0, sw, Ub);
   } else if (sw > 32) {
@@ -1061,8 +1074,8 @@ __device__ void eliminate(const Mat<typename Prec<R>::C>& A, int c_begin, int nc
         invert_unit_lower<R>(A, c, w, sh);
         if (xcache) save_x<R>(sh, xcache + (int64_t)blk * kNB * kNB);
         blk += 1;
-        for (int s0 = c + w; s0 < N; s0 += kSW) {
-          const int sw = min(kSW, N - s0);
+        for (int s0 = c + w; s0 < N; s0 += kSWp<R>) {
+          const int sw = min(kSWp<R>, N - s0);
           trsm_strip<R>(A, c, w, s0, sw, store_u, sh);
           update_strip<R>(A, c, w, s0, sw, sh.U);
         }
@@ -1073,8 +1086,8 @@ __device__ void eliminate(const Mat<typename Prec<R>::C>& A, int c_begin, int nc
         save_x<R>(sh, xp);
         invert_unit_lower<R>(A, c + kNB, w - kNB, sh);
         save_x<R>(sh, xp + kNB * kNB);
-        for (int s0 = c + w; s0 < N; s0 += kSW) {
-          const int sw = min(kSW, N - s0);
+        for (int s0 = c + w; s0 < N; s0 += kSWp<R>) {
+          const int sw = min(kSWp<R>, N - s0);
           trsm2_strip<R>(A, c, w, s0, sw, store_u, xp, sh);
           update_strip<R>(A, c, w, s0, sw, ustrip2(sh));
         }

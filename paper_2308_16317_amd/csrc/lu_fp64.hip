@@ -514,7 +514,7 @@ __device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, bool hav
         if (nsplit > 1) acc = zmake(acc.x + ms.part[1][i][j].x, acc.y + ms.part[1][i][j].y);
         v = zmake(zc.x - acc.x, zc.y - acc.y);
       }
-      if (j < kSW) sh.U[i][j] = v;
+      if (j < kSWp<float>) sh.U[i][j] = v;
     }
     __syncthreads();
     // z(c .. c+w) = X_u * sh.U
