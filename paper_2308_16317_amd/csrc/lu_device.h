@@ -25,11 +25,11 @@ constexpr int kNB = 64;         // triangular blocks and LDS tiles
 constexpr int kSW = 64;         // trailing-update strip width in FP64 (columns)
 constexpr int kPanelMax = 128;  // maximum panel width (two triangular blocks)
 
-// Strip width of the trailing update: 64 columns in FP64; 96 in FP32, whose
-// 128-row U12 strip of 96 columns takes the LDS of FP64's 64, and whose
-// update, bound by HBM traffic, then re-reads L21 a third less often.
+// Strip width of the trailing update: 64 columns in FP64; 128 in FP32, whose
+// 128-row U12 strip of 128 columns takes the LDS of FP64's 64, and whose
+// update, bound by HBM traffic, then re-reads L21 half as often.
 template <typename R>
-constexpr int kSWp = sizeof(R) == 4 ? 96 : kSW;
+constexpr int kSWp = sizeof(R) == 4 ? 128 : kSW;
 constexpr int kMaxKK = 25;
 constexpr int kMaxWL = 8;
 
@@ -985,6 +985,10 @@ __device__ __noinline__ void update_strip(const Mat<typename Prec<R>::C>& Ain, i
     } else {
       update_rows_multi<R, 1, 1, 8>(A, r0, s, s0, sw, Ub);
     }
+  } else if (kSWp<R> > 96 && sw > 112) {
+    update_rows<R, (kSWp<R> > 96 ? 8 : 4)>(A, r0, s, s0, sw, Ub);
+  } else if (kSWp<R> > 96 && sw > 96) {
+    update_rows<R, (kSWp<R> > 96 ? 7 : 4)>(A, r0, s, s0, sw, Ub);
   } else if (kSWp<R> > 64 && sw > 80) {
     update_rows<R, (kSWp<R> > 64 ? 6 : 4)>(A, r0, s, s0, sw, Ub);
   } else if (kSWp<R> > 64 && sw > 64) {

@@ -263,10 +263,13 @@ __device__ inline void load_x(const zf* __restrict__ src, LuSmem<float>& sh) {
 
 struct MixedSmem {
   LuSmem<float> f;
-  zf part[2][kNB][32];  // split-K partial sums of the backward solve
+  zf part[2 * kNB * 16];  // split-K partial sums of the backward solve: [split][row][kp]
   double red[2][kLuWaves];
   int flag;
 };
+static_assert(sizeof(MixedSmem) <= 160 * 1024 && sizeof(LuSmem<double>) <= 160 * 1024 &&
+                  sizeof(BuildSmem) <= 160 * 1024,
+              "a workgroup's LDS on gfx950 is 160 KB");
 
 // z[v][j] (v in [r0, r0 + s), j < kp) = X * z[r0 .. r0 + s) with X = sh.X (s x s):
 // up to eight 16x16 tiles, one per wave; the result also goes to sh.U.
@@ -497,7 +500,7 @@ __device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, bool hav
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      ms.part[split][16 * rt + Prec<float>::drow(r, lq)][16 * ct + li] = zmake(ar[r], ai[r]);
+      ms.part[(split * kNB + 16 * rt + Prec<float>::drow(r, lq)) * b.kp + 16 * ct + li] = zmake(ar[r], ai[r]);
     if (have_uinv) {
       __syncthreads();
       load_x(b.ucache + (int64_t)pi * kNB * kNB, sh);
@@ -510,8 +513,11 @@ __device__ void solve_f32(const Mat<zf>& A, const MixedBufs& b, int nb, bool hav
       zf v = zmake(0.f, 0.f);
       if (i < w && j < b.kp) {
         const zf zc = b.z[(int64_t)(c + i) * b.kp + j];
-        zf acc = ms.part[0][i][j];
-        if (nsplit > 1) acc = zmake(acc.x + ms.part[1][i][j].x, acc.y + ms.part[1][i][j].y);
+        zf acc = ms.part[i * b.kp + j];
+        if (nsplit > 1) {
+          const zf p1 = ms.part[(kNB + i) * b.kp + j];
+          acc = zmake(acc.x + p1.x, acc.y + p1.y);
+        }
         v = zmake(zc.x - acc.x, zc.y - acc.y);
       }
       if (j < kSWp<float>) sh.U[i][j] = v;
