@@ -101,6 +101,22 @@ __device__ __forceinline__ LSMS_GLOBAL T* glb(T* p) {
   return (LSMS_GLOBAL T*)p;
 }
 
+// Non-temporal access to entries of the trailing block, which an update
+// reads and writes once, so that they do not displace the L21 panel that
+// every strip re-reads.
+template <typename C>
+__device__ __forceinline__ C ntload(const LSMS_GLOBAL C* p) {
+  C v;
+  v.x = __builtin_nontemporal_load(&p->x);
+  v.y = __builtin_nontemporal_load(&p->y);
+  return v;
+}
+template <typename C>
+__device__ __forceinline__ void ntstore(LSMS_GLOBAL C* p, C v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+
 template <typename C>
 struct Mat {
   LSMS_GLOBAL C* base;  // global memory (see glb above)
@@ -763,7 +779,7 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
       const int v = q + Prec<R>::drow(r, lq);
       const auto crow = glb(A.base + A.phys(v < N ? v : rstart) * A.N);
 #pragma unroll
-      for (int cs = 0; cs < NCS; ++cs) cv[cs][r] = crow[ccol[cs]];
+      for (int cs = 0; cs < NCS; ++cs) cv[cs][r] = ntload(&crow[ccol[cs]]);
     }
   };
   auto store_pv = [&](int q) {
@@ -774,7 +790,7 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
       const auto crow = glb(A.base + A.phys(v) * A.N);
 #pragma unroll
       for (int cs = 0; cs < NCS; ++cs)
-        if (cok[cs]) crow[ccol[cs]] = pv[cs][r];
+        if (cok[cs]) ntstore(&crow[ccol[cs]], pv[cs][r]);
     }
   };
   // chunk kc of the L operand of row block q: row q + li, k = kc + KJ lq + j
