@@ -31,7 +31,7 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per instance moved by the fused kernel (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, each scaled by the counts of a plain copy of known size), valid
 # only for the kernel sources whose hash is given; null otherwise.
-TRAFFIC_PER_INSTANCE = {("fp64", "abbf61f8a860fe94"): 2.037e9, ("fp32ir", "abbf61f8a860fe94"): 1.299e9}
+TRAFFIC_PER_INSTANCE = {("fp64", "fd4a032b33f6215a"): 2.030e9, ("fp32ir", "fd4a032b33f6215a"): 1.288e9}
 KERNEL_SOURCES = ("kkr_device.h", "lu_device.h", "lu_fp64.hip", "lsms_common.h")
 
 
