@@ -18,19 +18,19 @@
 // block last: physical row/column phys(v) = v + kk for v < Nd = N - kk, and
 // v - Nd for the central block.
 //
-// One workgroup (8 waves, two per SIMD) per instance.  Per panel of w <= 64
-// columns:
+// One workgroup (8 waves, two per SIMD) per instance.  Per panel of w <= 128
+// columns (two 64-column diagonal blocks when w > 64):
 //   1. recursive panel factorisation: leaves of kWL columns are factorised
 //      with the leaf held in registers (each thread owns rows lc + t + 512 q),
-//      pivot search by wave shuffles and an 8-entry LDS reduction, row
-//      exchange through LDS; after each leaf the completed block of the
+//      pivot search by DPP within each wave and an 8-entry LDS reduction
+//      across the waves; after each leaf the completed block of the
 //      recursion updates its sibling block (triangular solve and product on
 //      MFMA);
 //   2. the panel's row interchanges applied to the trailing columns;
-//   3. X = L11^{-1} (unit lower, w x w) into LDS;
-//   4. per strip of 64 trailing columns: U12 = X A12 (MFMA) into LDS, then
-//      A22 -= L21 U12 (complex GEMM on v_mfma_f64_16x16x4f64; a complex
-//      product is four real MFMAs on separate real/imaginary accumulators).
+//   3. the inverses of the unit lower diagonal blocks of L11 (LDS, global);
+//   4. per strip of trailing columns (64 in FP64, 128 in FP32): U12 = L11^-1
+//      A12 (MFMA) into LDS, then A22 -= L21 U12 (complex GEMM on MFMA; a
+//      complex product is four real MFMAs on real/imaginary accumulators).
 // Finally S_A is inverted by Gauss-Jordan with partial pivoting.
 #include "kkr_device.h"
 #include "lsms_common.h"
