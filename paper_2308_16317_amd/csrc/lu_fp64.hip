@@ -312,25 +312,27 @@ __device__ void tri_apply(const MixedBufs& b, int r0, int s, LuSmem<float>& sh) 
   __syncthreads();
 }
 
-// z[v] -= sum_{k < s} A(v, r0 + k) sh.U[k] for v in [v0, N): 16-row blocks
-// per wave, accumulators starting from the loaded block of z; the reduction
-// in chunks of 16 (lane (li, lq) supplies k = kc + 4 lq + j at MFMA step j),
-// loads one chunk (or, in the last chunk, the next row block) ahead.  Loads
-// are unconditional from clamped in-range addresses (rows >= N are never
-// stored; L entries of columns >= s meet the zero rows s.. of sh.U), and a
-// finished block is stored after the next block's first loads are issued
-// (loads and stores share one completion counter).
+// z[v] -= sum_{k < s} A(v, r0 + k) sh.U[k] for v in [v0, N), s <= 64: 16-row
+// blocks per wave, accumulators starting from the loaded block of z; lane
+// (li, lq) supplies k = 16 c + 4 lq + j at MFMA step j of chunk c.  All
+// operands of the next row block (its whole reduction and its z entries) are
+// loaded while the current block is multiplied, so that a wave keeps a whole
+// block of loads in flight.  Loads are unconditional from clamped in-range
+// addresses (rows >= N are never stored; L entries of columns >= s meet the
+// zero rows s.. of sh.U), and a finished block is stored after the next
+// block's loads are issued (loads and stores share one completion counter).
 template <int NCT>
 __device__ void rhs_update_rows(const Mat<zf>& A, const MixedBufs& b, int r0, int s, int v0,
                                 const LuSmem<float>& sh) {
   typedef Prec<float>::V4 V4;
+  constexpr int KC = kNB / 16;  // chunks of 16 in a reduction of at most kNB
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int N = (int)A.N;
   const int64_t pr0 = A.phys(r0);
   int rb = v0 + 16 * wave;
   if (rb < N) {
-    zf cn[NCT][4], an[4], pv[NCT][4];
+    zf cn[NCT][4], an[KC][4], pv[NCT][4];
     int pb = -1;
     auto load_c = [&](int q) {
 #pragma unroll
@@ -340,11 +342,13 @@ __device__ void rhs_update_rows(const Mat<zf>& A, const MixedBufs& b, int r0, in
         for (int t = 0; t < NCT; ++t) cn[t][r] = b.z[(int64_t)v * b.kp + 16 * t + li];
       }
     };
-    auto load_a = [&](int q, int kc) {
+    auto load_a = [&](int q) {
       const int va = q + li;
       const auto arow = A.base + A.phys(va < N ? va : v0) * A.N + pr0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) an[j] = arow[min(kc + 4 * lq + j, s - 1)];
+      for (int c = 0; c < KC; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) an[c][j] = arow[min(16 * c + 4 * lq + j, s - 1)];
     };
     auto store_pv = [&](int q) {
 #pragma unroll
@@ -356,7 +360,7 @@ __device__ void rhs_update_rows(const Mat<zf>& A, const MixedBufs& b, int r0, in
       }
     };
     load_c(rb);
-    load_a(rb, 0);
+    load_a(rb);
     for (; rb < N; rb += 16 * kLuWaves) {
       const int rn = rb + 16 * kLuWaves;
       V4 ar[NCT], ai[NCT];
@@ -367,29 +371,28 @@ __device__ void rhs_update_rows(const Mat<zf>& A, const MixedBufs& b, int r0, in
           ar[t][r] = cn[t][r].x;
           ai[t][r] = cn[t][r].y;
         }
-      for (int kc = 0; kc < s; kc += 16) {
-        zf a[4];
+      zf a[KC][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) a[j] = an[j];
-        if (kc + 16 < s) {
-          load_a(rb, kc + 16);
-        } else if (rn < N) {
-          load_c(rn);
-          load_a(rn, 0);
-        }
-        if (kc == 0 && pb >= 0) {
-          store_pv(pb);
-          pb = -1;
-        }
+      for (int c = 0; c < KC; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[c][j] = an[c][j];
+      if (rn < N) {
+        load_c(rn);
+        load_a(rn);
+      }
+      if (pb >= 0) store_pv(pb);
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        if (16 * c >= s) break;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int k = (kc + 4 * lq + j) & (kNB - 1);
-          const float nx = -a[j].x, ny = -a[j].y;
+          const int k = 16 * c + 4 * lq + j;
+          const float nx = -a[c][j].x, ny = -a[c][j].y;
 #pragma unroll
           for (int t = 0; t < NCT; ++t) {
             const zf u = sh.U[k][16 * t + li];
             ar[t] = Prec<float>::mfma(nx, u.x, ar[t]);
-            ar[t] = Prec<float>::mfma(a[j].y, u.y, ar[t]);
+            ar[t] = Prec<float>::mfma(a[c][j].y, u.y, ar[t]);
             ai[t] = Prec<float>::mfma(nx, u.y, ai[t]);
             ai[t] = Prec<float>::mfma(ny, u.x, ai[t]);
           }
@@ -627,9 +630,14 @@ __device__ void residual(const Mat<zd>& A, const MixedBufs& b) {
 // Precision-form tau00 of one instance.  A64 is the FP64 matrix (left
 // unmodified unless the FP64 fallback runs).  Ends after a barrier.
 template <int kR, int kWL>
-__device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd* A64, const MixedBufs& b, double* tau00,
-                               int32_t* info, int nb, double tol, int max_refine, bool have_a32,
-                               unsigned char* smem) {
+__device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd* A64, const MixedBufs& bin,
+                                            double* tau00, int32_t* info, int nb, double tol, int max_refine,
+                                            bool have_a32, unsigned char* smem) {
+  // By value: the pointers and kp stay in registers.  Read through the
+  // reference, every use would reload them with a generic load (a store
+  // through z might alias the struct), and each such load waits for every
+  // outstanding memory access.
+  const MixedBufs b = bin;
   MixedSmem& ms = *reinterpret_cast<MixedSmem*>(smem);
   LuSmem<float>& sh = ms.f;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
