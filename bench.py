@@ -314,7 +314,8 @@ def main():
     ach = float(np.sum(lu_flops) / (np.sum(lu_ms) * 1e-3) / 1e12)
     peak = FP32_PEAK_TFLOPS if args.precision == "fp32ir" else FP64_PEAK_TFLOPS
     per_inst = TRAFFIC_PER_INSTANCE.get((args.precision, kernel_source_hash()))
-    traffic = None if (per_inst is None or args.mode == "chunked") else per_inst * chunk
+    # measured on the N = 2160 benchmark instances only
+    traffic = None if (per_inst is None or args.mode == "chunked" or args.workload != "benchmark") else per_inst * chunk
     form = ("complex FP32 LU + FP64 iterative refinement to 1e-12 (FP64 fallback per instance)"
             if args.precision == "fp32ir" else "complex FP64 LU/Schur")
     out = {
