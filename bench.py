@@ -184,9 +184,10 @@ def main():
     ap.add_argument("--chunk", type=int, default=1024, help="instances per build/LU launch (chunked)")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--n-inst", type=int, default=0, help="limit the batch (0 = all 8192)")
-    ap.add_argument("--workload", choices=["benchmark", "ragged"], default="benchmark",
+    ap.add_argument("--workload", choices=["benchmark", "ragged", "lmax4"], default="benchmark",
                     help="benchmark: 8192 instances at N = 2160 (the metric's workload); ragged: 1024 instances of "
-                         "the vacancy/noise supercell with cutoffs 1.7a-2.1a (N = 1200-2400)")
+                         "the vacancy/noise supercell with cutoffs 1.7a-2.1a (N = 1200-2400); lmax4: the benchmark "
+                         "systems at lmax = 4 (N = 3375)")
     ap.add_argument("--forms", choices=["none", "fp32ir", "all"], default="all",
                     help="also time the other forms on the same instances (persistent launch) and report them "
                          "with their speedup over the FP64 path and their deviation from it")
@@ -219,7 +220,7 @@ def main():
     import inputs
     import paper_2308_16317_amd as P
 
-    w = inputs.config2() if args.workload == "benchmark" else inputs.config4()
+    w = {"benchmark": inputs.config2, "ragged": inputs.config4, "lmax4": inputs.config3}[args.workload]()
     if args.n_inst:
         w = inputs.subset(w, np.arange(args.n_inst))
     log(f"[bench] workload {w.name}: {w.n_inst} instances")
@@ -332,7 +333,8 @@ def main():
         "dtype": "f32+f64" if args.precision == "fp32ir" else "f64",
         "data": "synthetic",
         "config": {"workload": (f"{w.name}: fcc NiAu 50/50, 256 sites x 32 energies = {n_inst} instances, "
-                                f"135-atom LIZ, N=2160, lmax=3, {form}") if args.workload == "benchmark" else
+                                f"135-atom LIZ, N={int(Ns.max())}, lmax={w.lmax}, {form}")
+                   if args.workload != "ragged" else
                                (f"{w.name}: 10x10x10 fcc NiAu supercell, 3% vacancies, 0.02a noise, {n_inst} "
                                 f"(site, E) instances, cutoff 1.7a-2.1a, N={int(Ns.min())}-{int(Ns.max())}, "
                                 f"lmax=3, {form}"),

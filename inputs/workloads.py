@@ -117,7 +117,7 @@ class Workload:
 
     def with_lmax(self, lmax: int) -> "Workload":
         return dataclasses.replace(self, lmax=lmax, delta=phase_shift_table(self.energies, lmax),
-                                   name=f"{self.name}-lmax{lmax}")
+                                   name=f"{self.name.rsplit('-lmax', 1)[0]}-lmax{lmax}")
 
 
 def _children(seed: int):
