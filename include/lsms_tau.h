@@ -113,8 +113,10 @@ typedef struct {
     int32_t max_refine;  /* LSMS_PREC_FP32_IR: refinement steps at most, 0 = 10; 1..100  */
     int32_t reserved;    /* must be 0                                                   */
     double tol;          /* LSMS_PREC_FP32_IR: stop once the last correction of the central
-                            block is at most tol times the block (Frobenius norms);
-                            0 = 1e-12; otherwise 1e-15 .. 1e-3                          */
+                            block is at most tol times the block (Frobenius norms), or
+                            once the contraction of the last two steps (at most 1/2)
+                            predicts that the next one would be; 0 = 1e-12; otherwise
+                            1e-15 .. 1e-3                                               */
 } lsms_opts;
 
 /* Create a handle bound to HIP device `device`: uploads the real Gaunt
