@@ -35,15 +35,17 @@ TRAFFIC_PER_INSTANCE = {("fp64", "08af91cf900550a5"): 2.031e9, ("fp32ir", "08af9
 KERNEL_SOURCES = ("kkr_device.h", "lu_device.h", "lu_fp64.hip", "lsms_common.h")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the fused kernel's sources with comments and white space
-    removed, so that an edit of comments alone keeps the measured figures."""
+def kernel_source_hash(csrc: str = "") -> str:
+    """Hash of the fused kernel's sources (in `csrc`, default the package's)
+    with comments and white space removed, so that an edit of comments alone
+    keeps the measured figures."""
     import hashlib
     import re
 
+    csrc = csrc or os.path.join(ROOT, "paper_2308_16317_amd", "csrc")
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2308_16317_amd", "csrc", f), encoding="utf-8") as fh:
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
             src = fh.read()
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
         src = re.sub(r"//[^\n]*", " ", src)

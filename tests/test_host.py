@@ -49,3 +49,22 @@ def test_paper_speedups_match_their_wall_clock_times():
         gpu_s, cpu_s = row["seconds"]
         assert row["speedup"] == pytest.approx(cpu_s / gpu_s, rel=5e-3), row
         assert "EPYC 7742" in row["cpu"] and ("A100" in row["gpu"] or "V100" in row["gpu"])
+
+
+def test_kernel_hash_ignores_comments_only(tmp_path):
+    import shutil
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    csrc = os.path.join(ROOT, "paper_2308_16317_amd", "csrc")
+    for f in bench.KERNEL_SOURCES:
+        shutil.copy(os.path.join(csrc, f), tmp_path / f)
+    h0 = bench.kernel_source_hash(str(tmp_path))
+    assert h0 == bench.kernel_source_hash()
+    p = tmp_path / "lu_device.h"
+    src = p.read_text()
+    p.write_text("// a new comment line\n" + src.replace("\n", "  \n", 3) + "/* block\ncomment */\n")
+    assert bench.kernel_source_hash(str(tmp_path)) == h0
+    p.write_text(src + "\nstatic int extra_symbol;\n")
+    assert bench.kernel_source_hash(str(tmp_path)) != h0
