@@ -78,23 +78,128 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, n_threads: int):
-    """The oracle on a bounded sample of the same workload: one instance per
-    thread (OpenMP over instances), at both contour ends and mid-contour."""
+def host_cores() -> int:
+    """Cores the CPU legs use: the cores this process may run on, at most 16
+    (the CPU share of one GPU on the benchmark hosts, whatever the machine's
+    total core count)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_sample_indices(w, n_sites: int = 2):
+    """The oracle sample: every contour energy of the first Ni and the first
+    Au centre of the workload (2 sites x 32 energies = 64 instances of the
+    benchmark workload)."""
+    sites = []
+    for sp in (0, 1):
+        cand = [c for c in np.unique(w.centre) if w.atom_species[c] == sp]
+        if cand:
+            sites.append(int(cand[0]))
+    idx = [i for i in range(w.n_inst) if int(w.centre[i]) in sites[:n_sites]]
+    return np.asarray(idx, dtype=int)
+
+
+def cpu_baseline(w, n_threads: int, idx):
+    """The oracle on a bounded sample of the same workload (the instances
+    `idx`), OpenMP over instances, in batches of one instance per thread;
+    returns the baseline record and the oracle's tau00 of the sample."""
     import inputs
     import oracle
 
-    n = max(1, n_threads)
-    idx = np.linspace(0, w.n_inst - 1, n).astype(int)
     ws = inputs.subset(w, idx)
     liz_off, pos, spec = oracle.liz_batch(ws)
     oracle.set_threads(n_threads)
-    t0 = time.perf_counter()
-    tau, info = oracle.tau00_batch(ws.lmax, liz_off, pos, spec, ws.energies, ws.e_idx, ws.delta, refine=2)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "solves/s", "cores": n_threads, "kind": "oracle",
-            "sample": f"{n} instances of the same workload (N=2160), one per OpenMP thread, "
-                      f"{dt:.1f} s wall"}
+    taus, infos, rates = [], [], []
+    t_all = time.perf_counter()
+    for b0 in range(0, len(idx), n_threads):
+        sl = slice(b0, min(len(idx), b0 + n_threads))
+        wb = inputs.subset(ws, np.arange(sl.start, sl.stop))
+        lo, po, sp = oracle.liz_batch(wb)
+        t0 = time.perf_counter()
+        tau, info = oracle.tau00_batch(wb.lmax, lo, po, sp, wb.energies, wb.e_idx, wb.delta, refine=2)
+        rates.append((sl.stop - sl.start) / (time.perf_counter() - t0))
+        taus.append(tau)
+        infos.append(info)
+    dt = time.perf_counter() - t_all
+    rec = {"value": float(np.median(rates)), "unit": "solves/s", "cores": n_threads, "kind": "oracle",
+           "sample": f"{len(idx)} instances of the same workload (every contour energy of two sites, N="
+                     f"{w.kk * int(np.diff(liz_off).max())}), in {len(rates)} batches of one instance per "
+                     f"OpenMP thread; value = median batch rate, {dt:.1f} s wall",
+           "batch_rates": [float(r) for r in rates]}
+    return rec, np.concatenate(taus), np.concatenate(infos)
+
+
+def cpu_lapack(w, n_threads: int, idx, n_mats: int = 8):
+    """Second CPU number: LAPACK zgetrf + zgetrs with kk right-hand sides (the
+    first block column of M^-1) on matrices built by the oracle, BLAS threads
+    over the same cores; the analog of the paper's AOCL CPU path."""
+    import numpy
+    import scipy
+    from scipy.linalg import lapack
+    from threadpoolctl import threadpool_limits
+
+    import inputs
+    import oracle
+
+    ws = inputs.subset(w, idx[np.linspace(0, len(idx) - 1, n_mats).astype(int)])
+    liz_off, pos, spec = oracle.liz_batch(ws)
+    C, _ = oracle.gaunt(ws.lmax)
+    kk = ws.kk
+    dts = []
+    with threadpool_limits(limits=n_threads):
+        for i in range(ws.n_inst):
+            a, b = liz_off[i], liz_off[i + 1]
+            e = int(ws.e_idx[i])
+            M, _ = oracle.build_m(ws.lmax, pos[a:b], spec[a:b], ws.energies[e], ws.delta[:, e, :], C)
+            B = np.zeros((M.shape[0], kk), np.complex128, order="F")
+            B[:kk, :kk] = np.eye(kk)
+            t0 = time.perf_counter()
+            lu, piv, inf = lapack.zgetrf(M, overwrite_a=True)
+            x, inf2 = lapack.zgetrs(lu, piv, B, overwrite_b=True)
+            dts.append(time.perf_counter() - t0)
+    cfg = scipy.show_config(mode="dicts")["Build Dependencies"]["lapack"]
+    return {"value": float(1.0 / np.median(dts)), "unit": "solves/s", "cores": n_threads, "kind": "lapack",
+            "routine": "zgetrf + zgetrs, 16 right-hand sides" if kk == 16 else f"zgetrf + zgetrs, {kk} rhs",
+            "lapack": f"{cfg.get('name')} {cfg.get('version')}", "numpy": numpy.__version__,
+            "sample": f"{ws.n_inst} matrices of the same workload, one at a time with BLAS threads over the "
+                      f"cores; value = 1 / median time per matrix (factor + solve, build excluded)"}
+
+
+def oracle_check(w, idx, ref, rinfo, tau, info, precision, outputs):
+    """Compares the timed run's tau00 (and each other form's) on the oracle's
+    sample: per-instance rel_F and the elementwise error of [M^-1]_00 =
+    tau00 diag(t_0)^-1 relative to its largest entry; the bar is 1e-12 for
+    the FP64 path and 1e-10 for the other forms."""
+    import oracle
+
+    kk = w.kk
+    lv = np.floor(np.sqrt(np.arange(kk)) + 1e-9).astype(int)
+    t0 = np.stack([oracle.tmat(w.lmax, w.energies[w.e_idx[i]], w.delta[w.atom_species[w.centre[i]], w.e_idx[i]])[lv]
+                   for i in idx])
+    res = {"instances": int(len(idx)), "oracle_info_nonzero": int(np.count_nonzero(rinfo)), "pass": True}
+    runs = {"timed_" + precision: (tau, 1e-12 if precision == "fp64" else 1e-10)}
+    for k, v in outputs.items():
+        runs[k] = (v, 1e-10)
+    for name, (t, bar) in runs.items():
+        got = t.view(-1, kk * kk)[torch_index(idx, t)].cpu().numpy().reshape(-1, kk, kk).transpose(0, 2, 1)
+        rf = np.linalg.norm((got - ref).reshape(len(idx), -1), axis=1) / np.linalg.norm(ref.reshape(len(idx), -1),
+                                                                                          axis=1)
+        xe = np.array([np.abs(got[q] / t0[q][None, :] - ref[q] / t0[q][None, :]).max() /
+                       np.abs(ref[q] / t0[q][None, :]).max() for q in range(len(idx))])
+        ok = bool(rf.max() <= bar and xe.max() <= bar)
+        res[name] = {"max_rel_F_vs_oracle": float(rf.max()), "max_M_inv_00_err_vs_oracle": float(xe.max()),
+                     "bar": bar, "pass": ok}
+        res["pass"] = res["pass"] and ok
+    return res
+
+
+def torch_index(idx, t):
+    import torch
+
+    return torch.as_tensor(np.asarray(idx), device=t.device)
 
 
 def rel_f_rows(a, b):
@@ -103,10 +208,11 @@ def rel_f_rows(a, b):
     return (torch.linalg.vector_norm(a - b, dim=1) / torch.linalg.vector_norm(b, dim=1)).max().item()
 
 
-def time_forms(args, P, h, w, liz, energy, e_idx, delta, max_liz, tau64, fp64_rate):
+def time_forms(args, P, h, w, liz, energy, e_idx, delta, max_liz, tau64, fp64_rate, outputs):
     """The precision and learned forms on the same instances (one warm-up and
     one timed pass each, persistent launch), with their speedup over the FP64
-    path and the largest per-instance deviation of their tau00 from it."""
+    path and the largest per-instance deviation of their tau00 from it; each
+    form's tau00 goes to outputs[form] (device)."""
     import torch
 
     import inputs
@@ -135,6 +241,7 @@ def time_forms(args, P, h, w, liz, energy, e_idx, delta, max_liz, tau64, fp64_ra
                          "max_rel_F_vs_fp64": rel_f_rows(t32, tau64), "fp64_fallbacks": fb,
                          "errors": int((i32 != 0).sum().item()) - fb,
                          "peak_tflops": FP32_PEAK_TFLOPS}
+        outputs["fp32ir"] = t32
         log(f"[bench] fp32ir: {res['fp32ir']}")
     except Exception as e:  # reported, not fatal: the FP64 line stands on its own
         res["fp32ir"] = {"error": repr(e)}
@@ -165,6 +272,7 @@ def time_forms(args, P, h, w, liz, energy, e_idx, delta, max_liz, tau64, fp64_ra
                               "mean_gmres_block_steps": float(sl.double().mean().item()),
                               "train_loss_first_last": [losses[0], float(np.mean(losses[-50:]))],
                               "train_seconds": t_train, "restart": restart}
+            outputs["learned"] = tl.view(-1, 256)
             log(f"[bench] learned: {res['learned']}")
         except Exception as e:
             res["learned"] = {"error": repr(e)}
@@ -193,8 +301,11 @@ def main():
     ap.add_argument("--forms", choices=["none", "fp32ir", "all"], default="all",
                     help="also time the other forms on the same instances (persistent launch) and report them "
                          "with their speedup over the FP64 path and their deviation from it")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU legs (oracle baseline, LAPACK number) and the oracle check of tau00")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="threads of the CPU legs (0 = host_cores())")
+    ap.add_argument("--cpu-sample", type=int, default=64,
+                    help="oracle sample: at most this many instances (every contour energy of two sites)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run three plain device copies of MIB MiB (the reference kernel whose "
                          "FETCH_SIZE / WRITE_SIZE counters scale the HBM-traffic measurement) and exit")
@@ -307,7 +418,7 @@ def main():
     fallback = int((info == P.INFO_FP64_FALLBACK).sum().item()) if args.precision == "fp32ir" else 0
     bad = int((info != 0).sum().item()) - fallback
     if bad:
-        raise RuntimeError(f"{bad} instances reported an error in info")
+        raise RuntimeError(f"{bad} instances reported an error in info (values {torch.unique(info).tolist()})")
     n_inst = w.n_inst
     Ns = kk * sizes.astype(np.float64)
     flops_step = float(np.sum(8.0 / 3.0 * Ns ** 3))
@@ -316,11 +427,17 @@ def main():
     lu_flops = [float(np.sum(8.0 / 3.0 * (Nc.double().cpu().numpy()) ** 3)) for (_, _, _, Nc) in events]
     ach = float(np.sum(lu_flops) / (np.sum(lu_ms) * 1e-3) / 1e12)
     peak = FP32_PEAK_TFLOPS if args.precision == "fp32ir" else FP64_PEAK_TFLOPS
-    per_inst = TRAFFIC_PER_INSTANCE.get((args.precision, kernel_source_hash()))
+    src_hash = kernel_source_hash()
+    per_inst = TRAFFIC_PER_INSTANCE.get((args.precision, src_hash))
     # measured on the N = 2160 benchmark instances only
     traffic = None if (per_inst is None or args.mode == "chunked" or args.workload != "benchmark") else per_inst * chunk
+    # bound: algorithmic intensity (8/3 N^3 flops over the 32 N^2 bytes of
+    # reading and writing M once) against the ridge peak / 8 TB/s
+    intensity = float(np.sum(8.0 / 3.0 * Ns ** 3) / np.sum(32.0 * Ns ** 2))
+    bound = "mfma" if intensity > peak / 8.0 else "hbm"
     form = ("complex FP32 LU + FP64 iterative refinement to 1e-12 (FP64 fallback per instance)"
             if args.precision == "fp32ir" else "complex FP64 LU/Schur")
+    lu_s = np.asarray(lu_ms) * 1e-3
     out = {
         "metric": METRIC,
         "value": n_inst * args.steps / dt,
@@ -344,19 +461,41 @@ def main():
                    "precision": args.precision, "instances_per_launch": chunk,
                    "fp64_fallbacks": fallback},
         "tflops": flops_step / (ms * 1e-3) / 1e12,
-        "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+        "solves_per_s_median_launch": float(np.median([e[2] / t for e, t in zip(events, lu_s)])),
+        "roofline": {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                      "frac": ach / peak, "traffic": traffic,
+                     "traffic_source": (f"rocprofv3 FETCH_SIZE/WRITE_SIZE per instance, calibrated on a copy "
+                                        f"kernel, profiles/{'tau00_mixed_persistent' if args.precision == 'fp32ir' else 'tau00_persistent_fp64'}"
+                                        f"_n2160_hbm_traffic.md, kernel source hash {src_hash}")
+                                       if traffic is not None else
+                                       f"no counters for kernel source hash {src_hash} on this workload",
+                     "algorithmic_intensity_flop_per_byte": intensity,
                      "kernel": kernel, "ms_per_launch": float(np.mean(lu_ms)),
+                     "ms_per_launch_median": float(np.median(lu_ms)),
                      "instances_per_launch": chunk},
     }
+    outputs = {}
     if args.forms != "none" and args.precision == "fp64" and args.mode != "chunked":
-        out["forms"] = time_forms(args, P, h, w, liz, energy, e_idx, delta, max_liz, tau, n_inst * args.steps / dt)
+        out["forms"] = time_forms(args, P, h, w, liz, energy, e_idx, delta, max_liz, tau, n_inst * args.steps / dt,
+                                  outputs)
     if not args.no_cpu:
-        nthr = args.cpu_threads or min(16, os.cpu_count() or 1)
-        log(f"[bench] cpu baseline: oracle on {nthr} threads")
-        out["cpu_baseline"] = cpu_baseline(w, nthr)
+        nthr = args.cpu_threads or host_cores()
+        idx = cpu_sample_indices(w)[:args.cpu_sample]
+        log(f"[bench] cpu baseline: oracle on {nthr} threads, {len(idx)} instances")
+        out["cpu_baseline"], ref, rinfo = cpu_baseline(w, nthr, idx)
+        log(f"[bench] cpu baseline: {out['cpu_baseline']}")
+        out["oracle_check"] = oracle_check(w, idx, ref, rinfo, tau, info, args.precision, outputs)
+        log(f"[bench] oracle check: {out['oracle_check']}")
+        try:
+            out["cpu_lapack"] = cpu_lapack(w, nthr, idx)
+            log(f"[bench] cpu lapack: {out['cpu_lapack']}")
+        except Exception as e:  # reported, not fatal
+            out["cpu_lapack"] = {"error": repr(e)}
     out["paper_speedups"] = PAPER_SPEEDUPS
     print(json.dumps(out), flush=True)
+    if "oracle_check" in out and not out["oracle_check"]["pass"]:
+        log("[bench] tau00 outside the tolerance against the oracle")
+        sys.exit(1)
 
 
 if __name__ == "__main__":

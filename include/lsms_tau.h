@@ -28,15 +28,22 @@
  *
  * Per-instance info[i]
  *    0  success
- *   256 (LSMS_INFO_FP64_FALLBACK, LSMS_PREC_FP32_IR only) success, computed
- *       by the FP64 path after the refinement did not converge
- *   k>0 (k < 256) an exactly zero pivot at elimination step k (1-based, in the
- *       library's elimination order: non-central columns first, the central
- *       block last); tau00 of the instance is NaN
+ *   k>0, k < 2^20: an exactly zero pivot at elimination step k (1-based, in
+ *       the library's elimination order: non-central columns first, the
+ *       central block last, so k <= N); tau00 of the instance is NaN
  *   -1  non-finite tau00 (non-finite energy or phase shift, overflow)
  *   -2  two LIZ sites closer than 1e-8 bohr (M undefined); tau00 is NaN
  *   -3  invalid instance: empty LIZ, LIZ larger than max_liz, energy index
  *       or species out of range; tau00 is NaN and M is not written
+ *   Fallback flags, ORed onto the non-negative info of the FP64 path that
+ *   recomputed the instance (a negative code is reported as it is):
+ *   LSMS_INFO_FP64_FALLBACK (bit 20, LSMS_PREC_FP32_IR): the refinement did
+ *       not converge and the FP64 path solved the instance; info equal to the
+ *       flag alone is a success, flag | k a zero pivot at step k of the FP64
+ *       path.
+ *   LSMS_INFO_LU_FALLBACK (bit 21, tau00_gmres): likewise for GMRES.
+ *   lsms_info_pivot(info) = info & (2^20 - 1) is the zero-pivot step (0 if
+ *   none) for non-negative info.
  */
 #ifndef LSMS_TAU_H
 #define LSMS_TAU_H
@@ -59,19 +66,22 @@ extern "C" {
                                mixed-precision scheme (Carson and Higham, SIAM J. Sci.
                                Comput. 40 (2018) A817); tau00_solve only */
 
-/* info value of tau00_gmres when GMRES did not reach its tolerance and the
- * instance was solved by the FP64 path */
-#define LSMS_INFO_LU_FALLBACK 512
+/* info flag of tau00_gmres when GMRES did not reach its tolerance and the
+ * instance was solved by the FP64 path (ORed onto that path's info) */
+#define LSMS_INFO_LU_FALLBACK (1 << 21)
 
 /* learned form: parameters of the seed network and floats of activations
  * kept per sample by lsms_mlp_forward */
 #define LSMS_MLP_PARAMS 399616
 #define LSMS_MLP_ACT 2560
 
-/* info bit set by LSMS_PREC_FP32_IR when the refinement did not reach tol
+/* info flag set by LSMS_PREC_FP32_IR when the refinement did not reach tol
  * within max_refine steps (or the FP32 factorisation met an exactly zero
- * pivot) and the instance was recomputed by the FP64 path */
-#define LSMS_INFO_FP64_FALLBACK 256
+ * pivot) and the instance was recomputed by the FP64 path (ORed onto that
+ * path's info) */
+#define LSMS_INFO_FP64_FALLBACK (1 << 20)
+/* mask of the zero-pivot step in a non-negative info */
+#define LSMS_INFO_PIVOT_MASK ((1 << 20) - 1)
 
 /* lsms_opts.flags */
 #define LSMS_PERSISTENT 1 /* tau00_solve: one persistent fused kernel, work queue in LPT order */
@@ -171,9 +181,14 @@ int build_kkr(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *
  *   tau00  device [n_inst][kk*kk] complex out, column-major kk x kk:
  *          tau00[i][L + kk*L'] = ([M_i^{-1}]_{00} diag(t_0))_{L L'}
  *   info   device [n_inst] out
- *   work / work_bytes: unused (may be NULL / 0).
+ *   work   device or NULL: with at least n_inst * LSMS_BATCHED_WORK_PER_INST
+ *          bytes (the inverses of the two 64 x 64 diagonal blocks of a panel,
+ *          per instance) panels may be up to 128 wide; with NULL, panels are
+ *          at most 64 wide whatever opts->nb asks (work_bytes ignored).
+ *          Too small a workspace returns -9.
  * Only LSMS_PREC_FP64 (the FP32 form needs the matrix unmodified and a
  * workspace: tau00_solve); another precision returns -5. */
+#define LSMS_BATCHED_WORK_PER_INST (2 * 64 * 64 * 16)
 int tau00_batched(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *m_off, const lsms_opts *opts,
                   double *tau00, int32_t *info, void *work, size_t work_bytes, void *stream);
 
@@ -205,18 +220,32 @@ int lsms_workspace_size(lsms_handle_t h, const lsms_problem *p, const lsms_opts 
 int tau00_solve(lsms_handle_t h, const lsms_problem *p, const lsms_opts *opts, double *tau00, int32_t *info,
                 void *work, size_t work_bytes, void *stream);
 
-/* Autotuner: times tau00_solve (with opts->flags) on the problem for panel
- * widths nb = 32, 64, 96, 128 after one warm-up each, stores the fastest as
- * the handle's panel width for matrices of this problem's size bucket
- * (kk*max_liz rounded up to 128), returns it in *best_nb and the four
- * timings (ms, in the order above) in ms_out[4] (host).  Synchronises the
- * stream. */
+/* Autotuner: times tau00_solve (with opts->flags, without LSMS_GRAPH) on the
+ * problem for panel widths nb = 32, 64, 96, 128, each after one warm-up call
+ * and as the median of three timed calls, stores the fastest as the handle's
+ * panel width for matrices of this problem's size bucket (kk*max_liz rounded
+ * up to a multiple of 128) and precision (opts->precision; tuned widths of
+ * the FP64 path and of the precision form are kept apart), returns it in
+ * *best_nb and the four median timings (ms, in the order above) in ms_out[4]
+ * (host, or NULL).  Synchronises the stream. */
 int lsms_autotune(lsms_handle_t h, const lsms_problem *p, const lsms_opts *opts, double *tau00, int32_t *info,
                   void *work, size_t work_bytes, void *stream, int32_t *best_nb, double *ms_out);
 
-/* Sets the handle's panel width for matrices of size n (the bucket of
- * lsms_autotune), e.g. from a cached tuning result. */
-int lsms_set_tuned_nb(lsms_handle_t h, int32_t n, int32_t nb);
+/* Sets (get: reads, 0 = not tuned) the handle's panel width for matrices of
+ * size n (1..4096, the bucket of lsms_autotune) in the given precision
+ * (LSMS_PREC_FP64 or LSMS_PREC_FP32_IR), e.g. from a cached tuning result.
+ * nb: 16..128, a multiple of 16. */
+int lsms_set_tuned_nb(lsms_handle_t h, int32_t n, int32_t precision, int32_t nb);
+int lsms_get_tuned_nb(lsms_handle_t h, int32_t n, int32_t precision, int32_t *nb);
+
+/* The handle's tuned panel widths to a file (host path) and back: a JSON
+ * array with one object {"n_max": n, "precision": p, "nb": w} per line, n the
+ * upper end of the size bucket.  lsms_autotune_load sets every entry of that
+ * form it finds (lines of any other form are skipped) and reports their
+ * number in *n_loaded (or NULL).  Return -2 when the file cannot be opened
+ * or written. */
+int lsms_autotune_save(lsms_handle_t h, const char *path);
+int lsms_autotune_load(lsms_handle_t h, const char *path, int32_t *n_loaded);
 
 /* ---------------------------------------------------------------------------
  * Learned form.  The paper solves every instance directly (Sec. 3.2); this

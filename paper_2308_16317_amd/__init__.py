@@ -8,6 +8,7 @@ from .lsms import (  # noqa: F401
     GRAPH,
     INFO_FP64_FALLBACK,
     INFO_LU_FALLBACK,
+    INFO_PIVOT_MASK,
     MLP_ACT,
     MLP_PARAMS,
     PERSISTENT,
@@ -16,9 +17,13 @@ from .lsms import (  # noqa: F401
     Handle,
     Opts,
     Problem,
+    BATCHED_WORK_PER_INST,
     autotune,
+    autotune_load,
+    autotune_save,
     build_kkr,
     build_liz,
+    get_tuned_nb,
     gmres_workspace_size,
     lib,
     mlp_adamw,

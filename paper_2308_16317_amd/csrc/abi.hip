@@ -1,6 +1,8 @@
 // C ABI of liblsms_tau (declared in include/lsms_tau.h): argument
 // validation on the host, the handle (Gaunt tables, tuned panel widths,
 // captured graphs), and the launches.
+#include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -14,7 +16,8 @@ namespace {
 
 constexpr int kMaxLmax = 4;
 constexpr int kMaxSpeciesAbi = 8;
-constexpr int kBuckets = 33;     // tuned panel width per 128-wide bucket of N <= 4096
+constexpr int kBuckets = 33;     // tuned panel width per 128-wide bucket of N <= 4096 and precision
+constexpr int kPrecisions = 2;   // LSMS_PREC_FP64, LSMS_PREC_FP32_IR
 constexpr int kGraphCache = 8;
 
 __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
@@ -96,6 +99,7 @@ struct GraphEntry {
   bool used;
   lsms_problem prob;
   lsms_opts opts;
+  int32_t nb;  // panel width resolved at capture (opts->nb or the tuned value)
   double* tau00;
   int32_t* info;
   void* work;
@@ -110,7 +114,7 @@ struct lsms_handle_s {
   int device;
   lsms_gaunt_dev g[kMaxLmax + 1];
   void* mem[kMaxLmax + 1];
-  int32_t tuned_nb[kBuckets];
+  int32_t tuned_nb[kPrecisions][kBuckets];
   GraphEntry graphs[kGraphCache];
   uint64_t clock;
 };
@@ -122,9 +126,11 @@ struct lsms_handle_s {
 
 namespace {
 
+int prec_index(const lsms_opts* o) { return mixed(o) ? 1 : 0; }
+
 int32_t panel_width(const lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o) {
   if (o && o->nb) return o->nb;
-  const int32_t t = h->tuned_nb[bucket_of((int64_t)(p->lmax + 1) * (p->lmax + 1) * p->max_liz)];
+  const int32_t t = h->tuned_nb[prec_index(o)][bucket_of((int64_t)(p->lmax + 1) * (p->lmax + 1) * p->max_liz)];
   return t ? t : 128;
 }
 
@@ -191,11 +197,11 @@ int enqueue_solve(lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o, d
   return 0;
 }
 
-bool same_args(const GraphEntry& e, const lsms_problem* p, const lsms_opts* o, double* tau00, int32_t* info,
-               void* work, size_t work_bytes) {
+bool same_args(const GraphEntry& e, const lsms_problem* p, const lsms_opts* o, int32_t nb, double* tau00,
+               int32_t* info, void* work, size_t work_bytes) {
   return e.used && std::memcmp(&e.prob, p, sizeof(lsms_problem)) == 0 &&
-         std::memcmp(&e.opts, o, sizeof(lsms_opts)) == 0 && e.tau00 == tau00 && e.info == info && e.work == work &&
-         e.work_bytes == work_bytes;
+         std::memcmp(&e.opts, o, sizeof(lsms_opts)) == 0 && e.nb == nb && e.tau00 == tau00 && e.info == info &&
+         e.work == work && e.work_bytes == work_bytes;
 }
 
 }  // namespace
@@ -292,8 +298,6 @@ extern "C" int build_kkr(lsms_handle_t h, const lsms_problem* p, double* M, cons
 extern "C" int tau00_batched(lsms_handle_t h, const lsms_problem* p, double* M, const int64_t* m_off,
                              const lsms_opts* opts, double* tau00, int32_t* info, void* work, size_t work_bytes,
                              void* stream) {
-  (void)work;
-  (void)work_bytes;
   if (!h) return -1;
   int r = check_problem(p);
   if (r) return r;
@@ -303,10 +307,11 @@ extern "C" int tau00_batched(lsms_handle_t h, const lsms_problem* p, double* M, 
   if (!m_off) return -4;
   if (!tau00) return -6;
   if (!info) return -7;
+  if (work && work_bytes < (size_t)p->n_inst * kLsmsXgBytes) return -9;
   (void)hipSetDevice(h->device);
   const lsms_prob_dev d = to_dev(p);
-  if (lsms_launch_lu_fp64(d, 0, p->n_inst, M, m_off, 0, nullptr, 0, tau00, info, 0, panel_width(h, p, opts),
-                          (hipStream_t)stream) != hipSuccess)
+  if (lsms_launch_lu_fp64(d, 0, p->n_inst, M, m_off, 0, (double*)work, work ? kLsmsXgBytes / 16 : 0, tau00, info,
+                          0, panel_width(h, p, opts), (hipStream_t)stream) != hipSuccess)
     return LSMS_EHIP;
   return 0;
 }
@@ -348,9 +353,12 @@ extern "C" int tau00_solve(lsms_handle_t h, const lsms_problem* p, const lsms_op
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess) return LSMS_EHIP;
   if (cs != hipStreamCaptureStatusNone) return enqueue_solve(h, p, opts, tau00, info, work, work_bytes, s);
+  // the key holds the resolved panel width: a graph captured before the
+  // tuned width changed is not replayed after
+  const int32_t nb = panel_width(h, p, opts);
   GraphEntry* hit = nullptr;
   for (int q = 0; q < kGraphCache; ++q)
-    if (same_args(h->graphs[q], p, opts, tau00, info, work, work_bytes)) hit = &h->graphs[q];
+    if (same_args(h->graphs[q], p, opts, nb, tau00, info, work, work_bytes)) hit = &h->graphs[q];
   if (!hit) {
     // check the arguments outside the capture (errors must not leave a capture open)
     if (opts->flags & LSMS_PERSISTENT) {
@@ -384,6 +392,7 @@ extern "C" int tau00_solve(lsms_handle_t h, const lsms_problem* p, const lsms_op
     slot->used = true;
     slot->prob = *p;
     slot->opts = *opts;
+    slot->nb = nb;
     slot->tau00 = tau00;
     slot->info = info;
     slot->work = work;
@@ -395,11 +404,21 @@ extern "C" int tau00_solve(lsms_handle_t h, const lsms_problem* p, const lsms_op
   return hipGraphLaunch(hit->exec, s) == hipSuccess ? 0 : LSMS_EHIP;
 }
 
-extern "C" int lsms_set_tuned_nb(lsms_handle_t h, int32_t n, int32_t nb) {
+extern "C" int lsms_set_tuned_nb(lsms_handle_t h, int32_t n, int32_t precision, int32_t nb) {
   if (!h) return -1;
   if (n < 1 || n > 4096) return -2;
-  if (nb < 16 || nb > 128 || nb % 16) return -3;
-  h->tuned_nb[bucket_of(n)] = nb;
+  if (precision != LSMS_PREC_FP64 && precision != LSMS_PREC_FP32_IR) return -3;
+  if (nb < 16 || nb > 128 || nb % 16) return -4;
+  h->tuned_nb[precision][bucket_of(n)] = nb;
+  return 0;
+}
+
+extern "C" int lsms_get_tuned_nb(lsms_handle_t h, int32_t n, int32_t precision, int32_t* nb) {
+  if (!h) return -1;
+  if (n < 1 || n > 4096) return -2;
+  if (precision != LSMS_PREC_FP64 && precision != LSMS_PREC_FP32_IR) return -3;
+  if (!nb) return -4;
+  *nb = h->tuned_nb[precision][bucket_of(n)];
   return 0;
 }
 
@@ -419,19 +438,24 @@ extern "C" int lsms_autotune(lsms_handle_t h, const lsms_problem* p, const lsms_
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   const int32_t cand[4] = {32, 64, 96, 128};
+  constexpr int kSamples = 3;
   int32_t best = 128;
   float best_ms = 0.0f;
   for (int c = 0; c < 4; ++c) {
     o.nb = cand[c];
-    int er = tau00_solve(h, p, &o, tau00, info, work, work_bytes, stream);
+    int er = tau00_solve(h, p, &o, tau00, info, work, work_bytes, stream);  // warm-up
     if (er) return er;
-    HIP_TRY(hipEventRecord(e0, s));
-    er = tau00_solve(h, p, &o, tau00, info, work, work_bytes, stream);
-    if (er) return er;
-    HIP_TRY(hipEventRecord(e1, s));
-    HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    float t[kSamples];
+    for (int k = 0; k < kSamples; ++k) {
+      HIP_TRY(hipEventRecord(e0, s));
+      er = tau00_solve(h, p, &o, tau00, info, work, work_bytes, stream);
+      if (er) return er;
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      HIP_TRY(hipEventElapsedTime(&t[k], e0, e1));
+    }
+    std::sort(t, t + kSamples);
+    const float ms = t[kSamples / 2];  // median of the samples
     if (ms_out) ms_out[c] = ms;
     if (c == 0 || ms < best_ms) {
       best_ms = ms;
@@ -440,8 +464,51 @@ extern "C" int lsms_autotune(lsms_handle_t h, const lsms_problem* p, const lsms_
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  h->tuned_nb[bucket_of((int64_t)(p->lmax + 1) * (p->lmax + 1) * p->max_liz)] = best;
+  h->tuned_nb[prec_index(&o)][bucket_of((int64_t)(p->lmax + 1) * (p->lmax + 1) * p->max_liz)] = best;
   *best_nb = best;
+  return 0;
+}
+
+// Tuning cache file: a JSON array with one object per line,
+//   {"n_max": 2176, "precision": 0, "nb": 128}
+// (n_max the upper end of the 128-wide bucket of N).  lsms_autotune_load reads
+// the lines of that form (as lsms_autotune_save writes them) and ignores
+// every other line.
+extern "C" int lsms_autotune_save(lsms_handle_t h, const char* path) {
+  if (!h) return -1;
+  if (!path) return -2;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return -2;
+  std::fprintf(f, "[\n");
+  bool first = true;
+  for (int pr = 0; pr < kPrecisions; ++pr)
+    for (int b = 0; b < kBuckets; ++b)
+      if (h->tuned_nb[pr][b]) {
+        std::fprintf(f, "%s{\"n_max\": %d, \"precision\": %d, \"nb\": %d}", first ? "" : ",\n",
+                     b == 0 ? 1 : 128 * b, pr, h->tuned_nb[pr][b]);
+        first = false;
+      }
+  std::fprintf(f, "%s]\n", first ? "" : "\n");
+  return std::fclose(f) == 0 ? 0 : -2;
+}
+
+extern "C" int lsms_autotune_load(lsms_handle_t h, const char* path, int32_t* n_loaded) {
+  if (!h) return -1;
+  if (!path) return -2;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return -2;
+  char line[256];
+  int n = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    int nmax = 0, pr = -1, nb = 0;
+    const char* q = std::strchr(line, '{');
+    if (!q || std::sscanf(q, "{\"n_max\": %d, \"precision\": %d, \"nb\": %d}", &nmax, &pr, &nb) != 3) continue;
+    if (nmax < 1 || nmax > 4096 || (pr != 0 && pr != 1) || nb < 16 || nb > 128 || nb % 16) continue;
+    h->tuned_nb[pr][bucket_of(nmax)] = nb;
+    ++n;
+  }
+  std::fclose(f);
+  if (n_loaded) *n_loaded = n;
   return 0;
 }
 

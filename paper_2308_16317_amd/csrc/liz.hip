@@ -9,7 +9,8 @@
 // FP contraction off so that membership and order depend only on IEEE-rounded
 // products and sums.
 //
-// Three launches: count per instance, exclusive scan into offsets, fill.
+// Three launches: count per instance, exclusive scan into offsets, fill.  A
+// LIZ larger than max_liz keeps its max_liz nearest sites (the same order).
 #include "lsms_common.h"
 
 using namespace lsms;
@@ -135,6 +136,35 @@ __global__ __launch_bounds__(kLizThreads) void liz_fill_kernel(
     liz_pos[3 * base + 2] = 0.0;
     liz_species[base] = atom_species[c];
     if (liz_atom) liz_atom[base] = c;
+  }
+  if (ncand > kLizCap) {
+    // More candidates than LDS holds: each candidate's rank is counted
+    // against every atom within the cutoff, read again from global memory,
+    // so that the rows kept are the nearest ones, in order, whatever the
+    // order in which the candidates were found.
+    for (int j = threadIdx.x; j < n_atoms; j += kLizThreads) {
+      if (j == c) continue;
+      double d[3], d2;
+      min_image(pos, j, p0, bx, by, bz, d, d2);
+      if (!(d2 <= rc2)) continue;
+      const Cand me{d2, d[0], d[1], d[2], j};
+      int rank = 0;
+      for (int o = 0; o < n_atoms; ++o) {
+        if (o == c) continue;
+        double e[3], e2;
+        min_image(pos, o, p0, bx, by, bz, e, e2);
+        rank += (e2 <= rc2) && cand_less(Cand{e2, e[0], e[1], e[2], o}, me);
+      }
+      const int row = 1 + rank;
+      if (row < cap) {
+        liz_pos[3 * (base + row) + 0] = me.dx;
+        liz_pos[3 * (base + row) + 1] = me.dy;
+        liz_pos[3 * (base + row) + 2] = me.dz;
+        liz_species[base + row] = atom_species[me.idx];
+        if (liz_atom) liz_atom[base + row] = me.idx;
+      }
+    }
+    return;
   }
   for (int q = threadIdx.x; q < n; q += kLizThreads) {
     const Cand me = cand[q];

@@ -234,7 +234,9 @@ __global__ __launch_bounds__(kThreads) void tau00_persistent_kernel(lsms_prob_de
 // FP64 Schur path on its unmodified FP64 matrix and flagged in info (bit 8).
 // ======================================================================
 
-constexpr int kInfoIrFallback = 256;
+// Fallback flag of the precision form: bit 20, above every elimination step
+// (N < 2^20), ORed onto the fallback's own non-negative info.
+constexpr int kInfoIrFallback = 1 << 20;
 
 struct MixedBufs {
   LSMS_GLOBAL zf* A32;        // N x N FP32 factors, same physical layout as M
@@ -744,7 +746,7 @@ __device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd
     __syncthreads();
   } else {
     lu_instance<kR, kWL>(p, inst, A64, b.xg, tau00, info, nb, *reinterpret_cast<LuSmemD*>(smem));
-    if (tid == 0 && info[inst] == 0) info[inst] = kInfoIrFallback;
+    if (tid == 0 && info[inst] >= 0) info[inst] |= kInfoIrFallback;
     __syncthreads();
   }
 }
@@ -865,7 +867,8 @@ __global__ __launch_bounds__(kThreads) void tau00_mixed_persistent_kernel(
 // (kk = 16, one 16-column block).
 // ======================================================================
 
-constexpr int kInfoLuFallback = 512;
+// Fallback flag of the GMRES form: bit 21, ORed like kInfoIrFallback.
+constexpr int kInfoLuFallback = 1 << 21;
 constexpr int kGmMaxM = 8;  // block Arnoldi steps per restart, at most
 
 struct GmresBufs {
@@ -1339,7 +1342,7 @@ __global__ __launch_bounds__(kThreads) void tau00_gmres_persistent_kernel(
         __syncthreads();
       } else {
         lu_instance<kR, kWL>(p, inst, M, xg, tau00, info, nb, *reinterpret_cast<LuSmemD*>(smem_raw));
-        if (threadIdx.x == 0 && info[inst] == 0) info[inst] = kInfoLuFallback;
+        if (threadIdx.x == 0 && info[inst] >= 0) info[inst] |= kInfoLuFallback;
         __syncthreads();
       }
     } else {

@@ -52,20 +52,23 @@ class Opts(ctypes.Structure):
 
 PREC_FP64 = 0
 PREC_FP32_IR = 1
-INFO_FP64_FALLBACK = 256
+INFO_FP64_FALLBACK = 1 << 20
+INFO_PIVOT_MASK = (1 << 20) - 1
 PERSISTENT = 1
 GRAPH = 2
 
 
 SYMBOLS = ("lsms_create", "lsms_destroy", "lsms_build_liz", "build_kkr", "tau00_batched",
-           "lsms_workspace_size", "tau00_solve", "lsms_autotune", "lsms_set_tuned_nb",
+           "lsms_workspace_size", "tau00_solve", "lsms_autotune", "lsms_set_tuned_nb", "lsms_get_tuned_nb",
+           "lsms_autotune_save", "lsms_autotune_load",
            "lsms_mlp_features", "lsms_mlp_cast", "lsms_mlp_forward", "lsms_mlp_backward", "lsms_mlp_mse",
            "lsms_mlp_adamw", "lsms_mlp_seed", "lsms_mlp_targets", "lsms_mlp_norm_stats",
            "lsms_gmres_workspace_size", "tau00_gmres")
 
+BATCHED_WORK_PER_INST = 2 * 64 * 64 * 16
 MLP_PARAMS = 399616
 MLP_ACT = 2560
-INFO_LU_FALLBACK = 512
+INFO_LU_FALLBACK = 1 << 21
 
 
 def lib():
@@ -88,7 +91,10 @@ def lib():
         L.lsms_autotune.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(Opts), _P, _P, _P,
                                     ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_double)]
-        L.lsms_set_tuned_nb.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
+        L.lsms_set_tuned_nb.argtypes = [_P, _I32, _I32, _I32]
+        L.lsms_get_tuned_nb.argtypes = [_P, _I32, _I32, ctypes.POINTER(ctypes.c_int32)]
+        L.lsms_autotune_save.argtypes = [_P, ctypes.c_char_p]
+        L.lsms_autotune_load.argtypes = [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
         PP = ctypes.POINTER(_Problem)
         L.lsms_mlp_features.argtypes = [_P, PP, ctypes.c_double, _P, _P]
         L.lsms_mlp_cast.argtypes = [_P, _P, _P, _P]
@@ -224,9 +230,10 @@ def _tau_view(tau: torch.Tensor, kk: int) -> torch.Tensor:
 
 
 def tau00_batched(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tensor, opts: Opts | None = None,
-                  tau=None, info=None):
+                  tau=None, info=None, work=None):
     """tau00_batched on caller-built M (overwritten); returns (tau00 [n, kk, kk], info).
-    `tau` / `info` may be given as contiguous device buffers of n*kk*kk complex128 / n int32."""
+    `tau` / `info` may be given as contiguous device buffers of n*kk*kk complex128 / n int32;
+    `work` (a device byte buffer of n * BATCHED_WORK_PER_INST bytes) allows panels wider than 64."""
     kk = prob.kk
     if tau is None:
         tau = torch.empty(max(prob.n_inst, 1) * kk * kk, dtype=torch.complex128, device="cuda")
@@ -235,8 +242,9 @@ def tau00_batched(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tensor
     assert tau.is_contiguous() and info.is_contiguous()
     ps = prob.struct()
     o = opts if opts is not None else Opts()
+    wb = 0 if work is None else work.numel() * work.element_size()
     _check(lib().tau00_batched(h.ptr, ctypes.byref(ps), _ptr(M), _ptr(m_off), ctypes.byref(o), _ptr(tau),
-                               _ptr(info), None, 0, _stream()), "tau00_batched")
+                               _ptr(info), _ptr(work), wb, _stream()), "tau00_batched")
     return _tau_view(tau, kk)[:prob.n_inst], info[:prob.n_inst]
 
 
@@ -290,8 +298,24 @@ def autotune(h: Handle, prob: Problem, work: torch.Tensor, opts: Opts | None = N
     return int(best.value), dict(zip((32, 64, 96, 128), list(ms)))
 
 
-def set_tuned_nb(h: Handle, n: int, nb: int):
-    _check(lib().lsms_set_tuned_nb(h.ptr, int(n), int(nb)), "lsms_set_tuned_nb")
+def set_tuned_nb(h: Handle, n: int, nb: int, precision: int = PREC_FP64):
+    _check(lib().lsms_set_tuned_nb(h.ptr, int(n), int(precision), int(nb)), "lsms_set_tuned_nb")
+
+
+def get_tuned_nb(h: Handle, n: int, precision: int = PREC_FP64) -> int:
+    nb = ctypes.c_int32()
+    _check(lib().lsms_get_tuned_nb(h.ptr, int(n), int(precision), ctypes.byref(nb)), "lsms_get_tuned_nb")
+    return int(nb.value)
+
+
+def autotune_save(h: Handle, path: str):
+    _check(lib().lsms_autotune_save(h.ptr, os.fsencode(path)), "lsms_autotune_save")
+
+
+def autotune_load(h: Handle, path: str) -> int:
+    n = ctypes.c_int32()
+    _check(lib().lsms_autotune_load(h.ptr, os.fsencode(path), ctypes.byref(n)), "lsms_autotune_load")
+    return int(n.value)
 
 
 # ------------------------------------------------------------ learned form

@@ -39,13 +39,16 @@ def test_header_constants_match_binding():
     from paper_2308_16317_amd import lsms
 
     src = open(HEADER).read()
-    defs = dict(re.findall(r"#define\s+(LSMS_\w+)\s+\(?(-?\d+)\)?", src))
+    defs = {}
+    for k, v in re.findall(r"#define\s+(LSMS_\w+)\s+([-()<\d\s]+?)\s*(?:/\*|$)", src, flags=re.M):
+        defs[k] = eval(v)  # integer constants and shifts only (the pattern admits nothing else)
     assert int(defs["LSMS_PREC_FP64"]) == lsms.PREC_FP64
     assert int(defs["LSMS_PREC_FP32_IR"]) == lsms.PREC_FP32_IR
     assert int(defs["LSMS_INFO_FP64_FALLBACK"]) == lsms.INFO_FP64_FALLBACK
     assert int(defs["LSMS_PERSISTENT"]) == lsms.PERSISTENT
     assert int(defs["LSMS_GRAPH"]) == lsms.GRAPH
     assert int(defs["LSMS_INFO_LU_FALLBACK"]) == lsms.INFO_LU_FALLBACK
+    assert int(defs["LSMS_INFO_PIVOT_MASK"]) == lsms.INFO_PIVOT_MASK
     assert int(defs["LSMS_MLP_PARAMS"]) == lsms.MLP_PARAMS
     assert int(defs["LSMS_MLP_ACT"]) == lsms.MLP_ACT
 
@@ -66,3 +69,17 @@ def test_null_handle_rejected_without_gpu():
     L = P.lib()
     assert L.lsms_destroy(None) == -1
     assert L.tau00_solve(None, None, None, None, None, None, 0, None) == -1
+
+
+def test_info_flags_above_every_pivot_step():
+    # a zero pivot reports its elimination step k <= N in the low bits; the
+    # fallback flags sit above every step and decode apart from it
+    from paper_2308_16317_amd import lsms
+
+    for flag in (lsms.INFO_FP64_FALLBACK, lsms.INFO_LU_FALLBACK):
+        assert flag & lsms.INFO_PIVOT_MASK == 0 and flag & (flag - 1) == 0
+        assert flag > 25 * 1024  # kk * max_liz, the largest N the ABI admits
+    assert lsms.INFO_FP64_FALLBACK != lsms.INFO_LU_FALLBACK
+    for k in (1, 256, 512, 4096):
+        info = lsms.INFO_FP64_FALLBACK | k
+        assert info & lsms.INFO_PIVOT_MASK == k and info & lsms.INFO_FP64_FALLBACK

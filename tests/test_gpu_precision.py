@@ -13,6 +13,7 @@ import pytest
 
 import inputs
 import oracle
+from parity import check_tau, config2_two_sites, config3_sample, config4_sample, oracle_cached, rel_f
 
 pytestmark = pytest.mark.gpu
 
@@ -41,21 +42,8 @@ def h(P):
     return P.Handle()
 
 
-def rel_f(got, ref):
-    got = np.asarray(got)
-    ref = np.asarray(ref)
-    num = np.linalg.norm((got - ref).reshape(got.shape[0], -1), axis=1)
-    den = np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)
-    return num / den
-
-
-_CACHE = {}
-
-
 def _ref(key, w):
-    if key not in _CACHE:
-        _CACHE[key] = oracle.tau00_workload(w)
-    return _CACHE[key]
+    return oracle_cached(key, w)
 
 
 def _solve(P, h, w, flags=0, nb=0, chunk=0, tol=0.0, max_refine=0):
@@ -78,9 +66,8 @@ def test_ir_config1_all(P, h, flags):
     tau, info = _solve(P, h, w, flags=flags)
     assert np.all(rinfo == 0)
     assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK)), np.unique(info)
-    err = rel_f(tau, ref)
-    print("config1 IR rel_F max", err.max(), "fallbacks", int((info != 0).sum()))
-    assert err.max() <= TOL_IR
+    print("config1 IR fallbacks", int((info != 0).sum()))
+    check_tau(tau, ref, w, TOL_IR, "config1 IR")
     # mid-contour instances converge without the FP64 fallback
     assert (info == 0).mean() >= 0.9
 
@@ -91,7 +78,7 @@ def test_ir_panel_widths(P, h, nb, chunk):
     ref, _ = oracle.tau00_workload(w)
     tau, info = _solve(P, h, w, nb=nb, chunk=chunk)
     assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK))
-    assert rel_f(tau, ref).max() <= TOL_IR
+    check_tau(tau, ref, w, TOL_IR, f"IR nb={nb} chunk={chunk}")
 
 
 def test_ir_lmax4_persistent(P, h):
@@ -100,28 +87,26 @@ def test_ir_lmax4_persistent(P, h):
     ref, _ = oracle.tau00_workload(w)
     tau, info = _solve(P, h, w, flags=P.PERSISTENT)
     assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK))
-    assert rel_f(tau, ref).max() <= TOL_IR
+    check_tau(tau, ref, w, TOL_IR, "IR lmax=4 tiny")
 
 
 def test_ir_ragged_config4(P, h):
-    w = inputs.subset(inputs.config4(n_inst=1024), [0, 1, 2, 500, 1023])
-    ref, _ = oracle.tau00_workload(w)
+    w = config4_sample(32)
+    ref, _ = _ref("cfg4-32", w)
     tau, info = _solve(P, h, w, flags=P.PERSISTENT)
     assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK))
-    assert rel_f(tau, ref).max() <= TOL_IR
+    check_tau(tau, ref, w, TOL_IR, "IR config4 32-instance sample")
 
 
 def test_ir_config2_full_size_sample(P, h):
-    # N = 2160 at both contour ends and mid-contour, persistent launch as benchmarked
-    w2 = inputs.config2()
-    w = inputs.subset(w2, [0, 16, 31, 77 * 32 + 1, 200 * 32 + 30])
-    ref, _ = oracle.tau00_workload(w)
+    # N = 2160, all 32 energies of two sites, persistent launch as benchmarked
+    w = config2_two_sites()
+    ref, _ = _ref("cfg2-2sites", w)
     for nb in (0, 128):
         tau, info = _solve(P, h, w, flags=P.PERSISTENT, nb=nb)
-        err = rel_f(tau, ref)
-        print("config2 IR rel_F", nb, err, "info", info)
+        print("config2 IR info", np.unique(info))
         assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK))
-        assert err.max() <= TOL_IR
+        check_tau(tau, ref, w, TOL_IR, f"config2 IR two sites nb={nb}")
 
 
 def test_ir_fallback_path(P, h):
@@ -132,7 +117,7 @@ def test_ir_fallback_path(P, h):
     for flags in (0, 1):
         tau, info = _solve(P, h, w, flags=flags, tol=1e-15, max_refine=1)
         assert np.all(info == P.INFO_FP64_FALLBACK), info
-        assert rel_f(tau, ref).max() <= TOL_FP64
+        check_tau(tau, ref, w, TOL_FP64, f"forced fallback flags={flags}")
 
 
 def test_ir_error_codes(P, h):
@@ -155,7 +140,7 @@ def test_ir_error_codes(P, h):
         tau = tau.cpu().numpy()
         assert info[1] == -2 and np.all(np.isnan(tau[1]))
         assert info[0] in (0, P.INFO_FP64_FALLBACK) and info[2] in (0, P.INFO_FP64_FALLBACK)
-        assert rel_f(tau[[0, 2]], ref[[0, 2]]).max() <= TOL_IR
+        check_tau(tau[[0, 2]], ref[[0, 2]], inputs.subset(w, [0, 2]), TOL_IR, "IR error path, good instances")
 
 
 def test_ir_rejected_where_unsupported(P, h):
@@ -178,11 +163,11 @@ def test_ir_rejected_where_unsupported(P, h):
 
 
 def test_ir_lmax4_full_size(P, h):
-    # the config-2 systems at lmax = 4 (N = 3375), both contour ends and
-    # mid-contour, FP64 path and precision form against the oracle
+    # the config-2 systems at lmax = 4 (N = 3375), 8 instances at both contour
+    # ends and mid-contour, FP64 path and precision form against the oracle
     torch = _torch()
-    w = inputs.subset(inputs.config3(), [0, 15, 31])
-    ref, rinfo = oracle.tau00_workload(w)
+    w = config3_sample()
+    ref, rinfo = _ref("cfg3-8", w)
     assert np.all(rinfo == 0)
     prob = P.problem_for_workload(h, w)
     for prec, bar in ((P.PREC_FP64, TOL_FP64), (P.PREC_FP32_IR, TOL_IR)):
@@ -192,25 +177,25 @@ def test_ir_lmax4_full_size(P, h):
         tau, info = P.tau00_solve(h, prob, work, opts)
         torch.cuda.synchronize()
         info = info.cpu().numpy()
-        err = rel_f(tau.cpu().numpy(), ref)
-        print("lmax=4 N=3375", prec, "info", info, "rel_F", err)
+        print("lmax=4 N=3375", prec, "info", info)
         assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK))
-        assert err.max() <= bar
+        check_tau(tau.cpu().numpy(), ref, w, bar, f"lmax=4 N=3375 precision={prec}")
         del work
 
 
 def test_ir_error_per_energy(P, h):
     # one site of the benchmark alloy at all 32 contour energies: the
     # precision form's error per energy point
-    w = inputs.subset(inputs.config2(), np.arange(32) + 32 * 77)
-    ref, _ = oracle.tau00_workload(w)
+    w = config2_two_sites()
+    ref, _ = _ref("cfg2-2sites", w)
     tau, info = _solve(P, h, w, flags=P.PERSISTENT)
-    err = rel_f(tau, ref)
+    rf, xe = check_tau(tau, ref, w, TOL_IR, "IR per energy")
     E = w.energies[w.e_idx]
-    for e, x, i in zip(E, err, info):
-        print(f"E = {e.real:+.4f}{e.imag:+.4f}i  rel_F = {x:.2e}  info = {i}")
+    for k in range(32):
+        e = E[k]
+        print(f"E = {e.real:+.4f}{e.imag:+.4f}i  rel_F = {max(rf[k], rf[k + 32]):.2e}  "
+              f"[M^-1]00 = {max(xe[k], xe[k + 32]):.2e}  info = {info[k]}, {info[k + 32]}")
     assert np.all((info == 0) | (info == P.INFO_FP64_FALLBACK))
-    assert err.max() <= TOL_IR
 
 
 def test_ir_graph_replay_and_autotune(P, h):
@@ -240,8 +225,7 @@ def test_ir_graph_replay_and_autotune(P, h):
             s.synchronize()
             iv = i.cpu().numpy()
             assert np.all((iv == 0) | (iv == P.INFO_FP64_FALLBACK))
-            err = rel_f(t.cpu().numpy(), ref if rep < 2 else ref2)
-            assert err.max() <= TOL_IR, (rep, err.max())
+            check_tau(t.cpu().numpy(), ref if rep < 2 else ref2, w if rep < 2 else w2, TOL_IR, f"IR replay {rep}")
         del junk
         prob.e_idx.copy_(torch.as_tensor(w.e_idx, device="cuda"))
         o2 = P.Opts(P.PREC_FP32_IR, 0, 0, P.PERSISTENT, 0, 0, 0.0)
@@ -250,4 +234,4 @@ def test_ir_graph_replay_and_autotune(P, h):
         assert best in (32, 64, 96, 128) and all(v > 0 for v in ms.values())
         t, i = P.tau00_solve(h, prob, work, o2)
         s.synchronize()
-        assert rel_f(t.cpu().numpy(), ref).max() <= TOL_IR
+        check_tau(t.cpu().numpy(), ref, w, TOL_IR, "IR after autotune")
