@@ -192,6 +192,22 @@ int build_kkr(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *
 int tau00_batched(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *m_off, const lsms_opts *opts,
                   double *tau00, int32_t *info, void *work, size_t work_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tau00_batched
+ * without the workspace argument and without any allocation.  The wide-panel
+ * blocks live in a scratch array of the library, 32 MiB per device (room for
+ * 256 instances), held from lsms_create until the process ends; the batch is
+ * processed in stream-ordered passes of at most 256 instances, so n_inst has
+ * no upper limit beyond tau00_batched's own checks (kk * max_liz <= 4096,
+ * -2 above).  Panels up to 128 wide (opts->nb, or the tuned width).  The call
+ * enqueues kernel launches only (no hipMalloc, hipFree, memset or copy).
+ * Every call on one device shares that device's array: calls that overlap in
+ * time on one device (different streams, or threads) race and give undefined
+ * results; calls ordered on one stream do not.  Arguments, outputs and errors
+ * as tau00_batched (LSMS_PREC_FP64 only, else -5). */
+int tau00_batched_noalloc(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *m_off,
+                          const lsms_opts *opts, double *tau00, int32_t *info, void *stream);
+
 /* Workspace of tau00_solve.  Without LSMS_PERSISTENT: `chunk` instances per
  * pass, one slot per instance.  With LSMS_PERSISTENT (chunk ignored): one
  * 256-byte-aligned slot per resident workgroup of the persistent kernel (one

@@ -3,7 +3,7 @@
 This package prepares what the path takes as input: fcc NiAu-shaped
 supercells (positions, species, vacancies, positional noise), the list of
 (site, energy) instances with their LIZ cutoff radii, the complex energy
-contour and the square-well phase shifts that stand in for real muffin-tin
+contour (nodes and quadrature weights) and the square-well phase shifts that stand in for real muffin-tin
 potentials.  It contains no step of the path itself (no LIZ extraction, no
 t-matrix, no structure constants, no factorisation); both the product path
 and the oracle take their inputs from here.  The learned form's initial
@@ -21,6 +21,8 @@ from .workloads import (  # noqa: F401
     config3,
     config4,
     contour_energies,
+    contour_ends,
+    contour_weights,
     fcc_supercell,
     mlp_init,
     phase_shift_table,

@@ -54,6 +54,25 @@ def contour_energies(n_e: int) -> np.ndarray:
     return e[np.argsort(e.real)]
 
 
+def contour_weights(n_e: int) -> np.ndarray:
+    """Complex quadrature weights of the same contour, in the order of
+    contour_energies: sum_k w_k f(E_k) approximates the integral of f along
+    the arc from its left end E(pi - theta0) to its right end E(theta0)
+    through the upper half plane (Gauss-Legendre weights times dE/dx)."""
+    x, wx = np.polynomial.legendre.leggauss(n_e)
+    th0 = np.arcsin(_IM_MIN / _E_RADIUS)
+    th = th0 + (np.pi - 2.0 * th0) * (1.0 - x) / 2.0
+    e = _E_CENTRE + _E_RADIUS * np.exp(1j * th)
+    w = wx * (1j * _E_RADIUS * np.exp(1j * th)) * (-(np.pi - 2.0 * th0) / 2.0)
+    return w[np.argsort(e.real)]
+
+
+def contour_ends() -> tuple:
+    """The contour's end points (left, right), Im E = 0.01 Ry each."""
+    th0 = np.arcsin(_IM_MIN / _E_RADIUS)
+    return (_E_CENTRE + _E_RADIUS * np.exp(1j * (np.pi - th0)), _E_CENTRE + _E_RADIUS * np.exp(1j * th0))
+
+
 def square_well_delta(energies, lmax: int, v0: float, r_mt: float = R_MT) -> np.ndarray:
     """Complex phase shifts delta_l(E) of a square well V = -v0 for r < r_mt.
 

@@ -60,6 +60,8 @@ def lib():
         L.orc_max_threads.restype = _I
         L.orc_tau00_schur.restype = _I
         L.orc_tau00_schur.argtypes = [_I, _I, _P, _P, _P, _P, _I, _P, _P]
+        L.orc_tau_row_batch.argtypes = [_I, _I, _P, _P, _P, _P, _P, _P, _I, _I, _I, _P, _P, _P]
+        L.orc_logdet_batch.argtypes = [_I, _I, _P, _P, _P, _P, _P, _P, _I, _I, _P, _P]
         _lib = L
     return _lib
 
@@ -221,3 +223,79 @@ def tau00_workload(w, refine: int = 2):
     """Oracle tau00 for every instance of an inputs.Workload."""
     liz_off, pos, spec = liz_batch(w)
     return tau00_batch(w.lmax, liz_off, pos, spec, w.energies, w.e_idx, w.delta, refine)
+
+
+# ------------------------------------------------ block row of tau, ln det M
+def tau_row_batch(lmax: int, liz_off, pos, species, energies, e_idx, delta, refine: int = 2):
+    """Block rows tau^{0j} = [M^-1]_{0j} t_j of every instance: a list of
+    [kk, N_i] arrays (natural [L, column] indexing, column = j*kk + L') and
+    info [n_inst]."""
+    liz_off = _c(liz_off, np.int64)
+    pos = _c(pos, np.float64)
+    species = _c(species, np.int32)
+    energies = _c(energies, np.complex128)
+    e_idx = _c(e_idx, np.int32)
+    delta = _c(delta, np.complex128)
+    n = e_idx.shape[0]
+    kk = (lmax + 1) ** 2
+    N = kk * np.diff(liz_off)
+    row_off = np.concatenate([[0], np.cumsum(kk * N)[:-1]]).astype(np.int64)
+    out = np.zeros(int((kk * N).sum()), np.complex128)
+    info = np.zeros(n, np.int32)
+    lib().orc_tau_row_batch(lmax, n, _ptr(liz_off), _ptr(pos), _ptr(species), _ptr(energies), _ptr(e_idx),
+                            _ptr(delta), delta.shape[0], delta.shape[1], int(refine), _ptr(row_off), _ptr(out),
+                            _ptr(info))
+    rows = [out[row_off[i]:row_off[i] + kk * N[i]].reshape(N[i], kk).T.copy() for i in range(n)]
+    return rows, info
+
+
+def tau_row_workload(w, refine: int = 2):
+    liz_off, pos, spec = liz_batch(w)
+    return tau_row_batch(w.lmax, liz_off, pos, spec, w.energies, w.e_idx, w.delta, refine)
+
+
+def logdet_batch(lmax: int, liz_off, pos, species, energies, e_idx, delta):
+    """ln det M of every instance (principal logarithm: imaginary part in
+    (-pi, pi]) and info [n_inst]."""
+    liz_off = _c(liz_off, np.int64)
+    pos = _c(pos, np.float64)
+    species = _c(species, np.int32)
+    energies = _c(energies, np.complex128)
+    e_idx = _c(e_idx, np.int32)
+    delta = _c(delta, np.complex128)
+    n = e_idx.shape[0]
+    ld = np.zeros(n, np.complex128)
+    info = np.zeros(n, np.int32)
+    lib().orc_logdet_batch(lmax, n, _ptr(liz_off), _ptr(pos), _ptr(species), _ptr(energies), _ptr(e_idx),
+                           _ptr(delta), delta.shape[0], delta.shape[1], _ptr(ld), _ptr(info))
+    return ld, info
+
+
+def logdet_workload(w):
+    liz_off, pos, spec = liz_batch(w)
+    return logdet_batch(w.lmax, liz_off, pos, spec, w.energies, w.e_idx, w.delta)
+
+
+# ---------------------------------------------------- energy integration
+def contour_integral(values, weights):
+    """sum_k w_k f(E_k) over the first axis of `values`: the quadrature of
+    the contour integral of f along the energy contour whose nodes and
+    weights are given (the energy integral of eq. Density taken on a complex
+    contour)."""
+    v = np.asarray(values)
+    w = np.asarray(weights)
+    return np.tensordot(w, v, axes=(0, 0))
+
+
+def lloyd_ms_idos(logdets):
+    """Multiple-scattering part of the integrated density of states along a
+    contour, from ln det M at its nodes in contour order: Lloyd's formula
+    gives N_ms(E) = -(1/pi) Im ln det M(E) with the branch followed
+    continuously from the contour's first node, so N_ms(E_k) - N_ms(E_0) =
+    -(phi_k - phi_0)/pi, phi the phase of det M unwrapped node by node (each
+    step taken as the principal difference, which assumes the phase moves by
+    less than pi between neighbouring nodes)."""
+    ph = np.asarray(logdets).imag
+    steps = np.angle(np.exp(1j * np.diff(ph)))
+    phi = np.concatenate([[0.0], np.cumsum(steps)])
+    return -phi / np.pi

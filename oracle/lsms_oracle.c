@@ -25,6 +25,14 @@
  *   - The Schur-complement route of Sec. 2.2 (only the first block of the
  *     inverse is needed) is provided separately so that tests can check that
  *     both give the same block.
+ *   - The block row tau^{0j} = [M^{-1}]_{0j} t_j of the multiple-scattering
+ *     matrix tau = M^{-1} t (eq. Dyson_equation: (t^{-1} - g0)^{-1} =
+ *     (1 - t g0)^{-1} t), whose blocks feed the Green's function of
+ *     eq. Green_KKR: rows 0..kk-1 of M^{-1} from M^T Z = E_0, refined as above.
+ *   - ln det M from the same LU (the sum of the logarithms of U's diagonal and
+ *     i pi per row interchange), the quantity Lloyd's formula turns into the
+ *     multiple-scattering part of the integrated density of states behind
+ *     eq. Density.
  *
  * Units: Rydberg atomic units (E in Ry, lengths in bohr).  Complex matrices
  * are column-major, interleaved (re, im).
@@ -597,4 +605,152 @@ int orc_tau00_schur(int lmax, int n_liz, const double *rel, const int32_t *spec,
     free(S);
     free(M);
     return info;
+}
+
+/* ------------------------------------------------------------------ */
+/* Block row of tau and ln det M                                       */
+/* ------------------------------------------------------------------ */
+
+/* tau^{0j} for every LIZ site j of one instance: out is kk x n column-major,
+ * out[L + kk*(j*kk + L')] = [M^{-1}]_{0j}(L, L') t_{s(j), l(L')}.  The rows
+ * 0..kk-1 of M^{-1} are Z^T with M^T Z = E_0 (E_0 the first kk unit columns),
+ * solved by the LU of M^T and refined twice with 80-bit residuals.  Returns
+ * as orc_tau00_one; out is NaN on a nonzero return. */
+static int orc_tau_row_one(int lmax, int n_liz, const double *rel, const int32_t *spec, zc E,
+                           const zc *dl, int n_species, const double *gaunt, int refine, zc *out)
+{
+    const int kk = (lmax + 1) * (lmax + 1);
+    const int n = kk * n_liz;
+    const size_t nn = (size_t)n * n;
+    int info = 0;
+    for (size_t q = 0; q < (size_t)kk * n; ++q) out[q] = NAN + I * NAN;
+    if (!isfinite(creal(E)) || !isfinite(cimag(E)) || !orc_finite(dl, (size_t)n_species * (lmax + 1)))
+        return -1;
+    zc *M = (zc *)malloc(sizeof(zc) * nn);
+    zc *MT = (zc *)malloc(sizeof(zc) * nn);
+    zc *LU = (zc *)malloc(sizeof(zc) * nn);
+    zc *Z = (zc *)calloc((size_t)n * kk, sizeof(zc));
+    zc *E0 = (zc *)calloc((size_t)n * kk, sizeof(zc));
+    zc *R = (zc *)malloc(sizeof(zc) * (size_t)n * kk);
+    int32_t *ipiv = (int32_t *)malloc(sizeof(int32_t) * n);
+    info = orc_build_m_z(lmax, n_liz, rel, spec, E, dl, n_species, gaunt, M);
+    if (info == 0 && !orc_finite(M, nn)) info = -1;
+    if (info == 0) {
+        for (int c = 0; c < n; ++c)
+            for (int r = 0; r < n; ++r) MT[r + (size_t)n * c] = M[c + (size_t)n * r];
+        memcpy(LU, MT, sizeof(zc) * nn);
+        info = orc_lu_factor(n, (double *)LU, ipiv);
+    }
+    if (info == 0) {
+        for (int c = 0; c < kk; ++c) E0[c + (size_t)n * c] = 1.0;
+        memcpy(Z, E0, sizeof(zc) * (size_t)n * kk);
+        orc_lu_solve(n, (const double *)LU, ipiv, kk, (double *)Z);
+        for (int it = 0; it < refine; ++it) {
+            orc_residual_ld(n, kk, MT, Z, E0, R);
+            orc_lu_solve(n, (const double *)LU, ipiv, kk, (double *)R);
+            for (size_t q = 0; q < (size_t)n * kk; ++q) Z[q] += R[q];
+        }
+        const zc kap = csqrt(E);
+        for (int j = 0; j < n_liz; ++j)
+            for (int Lp = 0; Lp < kk; ++Lp) {
+                const int col = j * kk + Lp;
+                const zc d = dl[spec[j] * (lmax + 1) + orc_lof(Lp)];
+                const zc tj = -csin(d) * cexp(I * d) / kap;
+                /* [M^{-1}]_{0, col}(L) = Z(col, L) */
+                for (int L = 0; L < kk; ++L) out[L + (size_t)kk * col] = Z[col + (size_t)n * L] * tj;
+            }
+        if (!orc_finite(out, (size_t)kk * n)) info = -1;
+    }
+    if (info != 0)
+        for (size_t q = 0; q < (size_t)kk * n; ++q) out[q] = NAN + I * NAN;
+    free(M); free(MT); free(LU); free(Z); free(E0); free(R); free(ipiv);
+    return info;
+}
+
+/* ln det M of one instance from the LU of M with row partial pivoting:
+ * sum_k log U_kk plus i pi for every row interchange, the imaginary part
+ * reduced to (-pi, pi] (the principal logarithm of det M).  Returns as
+ * orc_tau00_one (a zero pivot gives k > 0 and ld = NaN). */
+static int orc_logdet_one(int lmax, int n_liz, const double *rel, const int32_t *spec, zc E,
+                          const zc *dl, int n_species, const double *gaunt, zc *ld)
+{
+    const int kk = (lmax + 1) * (lmax + 1);
+    const int n = kk * n_liz;
+    const size_t nn = (size_t)n * n;
+    *ld = NAN + I * NAN;
+    if (!isfinite(creal(E)) || !isfinite(cimag(E)) || !orc_finite(dl, (size_t)n_species * (lmax + 1)))
+        return -1;
+    zc *M = (zc *)malloc(sizeof(zc) * nn);
+    int32_t *ipiv = (int32_t *)malloc(sizeof(int32_t) * n);
+    int info = orc_build_m_z(lmax, n_liz, rel, spec, E, dl, n_species, gaunt, M);
+    if (info == 0 && !orc_finite(M, nn)) info = -1;
+    if (info == 0) info = orc_lu_factor(n, (double *)M, ipiv);
+    if (info == 0) {
+        double re = 0.0, ph = 0.0;
+        int swaps = 0;
+        for (int k = 0; k < n; ++k) {
+            const zc u = M[k + (size_t)n * k];
+            re += log(cabs(u));
+            ph += carg(u);
+            swaps += ipiv[k] != k;
+        }
+        if (swaps & 1) ph += ORC_PI;
+        ph = remainder(ph, 2.0 * ORC_PI);           /* [-pi, pi] */
+        if (ph <= -ORC_PI) ph += 2.0 * ORC_PI;      /* (-pi, pi] */
+        *ld = re + I * ph;
+        if (!isfinite(re)) info = -1;
+    }
+    free(M); free(ipiv);
+    return info;
+}
+
+static zc *orc_instance_delta(int lmax, const zc *dz, int n_species, int n_energy, int e)
+{
+    zc *dl = (zc *)malloc(sizeof(zc) * (size_t)n_species * (lmax + 1));
+    for (int s = 0; s < n_species; ++s)
+        for (int l = 0; l <= lmax; ++l) dl[s * (lmax + 1) + l] = dz[((size_t)s * n_energy + e) * (lmax + 1) + l];
+    return dl;
+}
+
+/* Batched block rows: instance i's kk x N_i block row at out + 2*row_off[i]
+ * doubles (complex offsets), problem layout as orc_tau00_batch. */
+void orc_tau_row_batch(int lmax, int n_inst, const int64_t *liz_off, const double *pos, const int32_t *species,
+                       const double *energy, const int32_t *e_idx, const double *delta, int n_species, int n_energy,
+                       int refine, const int64_t *row_off, double *out, int32_t *info)
+{
+    const int kk = (lmax + 1) * (lmax + 1);
+    const int kk2 = (2 * lmax + 1) * (2 * lmax + 1);
+    double *gaunt = (double *)malloc(sizeof(double) * (size_t)kk * kk * kk2);
+    orc_gaunt(lmax, gaunt);
+    const zc *Ez = (const zc *)energy;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < n_inst; ++i) {
+        zc *dl = orc_instance_delta(lmax, (const zc *)delta, n_species, n_energy, e_idx[i]);
+        const int n_liz = (int)(liz_off[i + 1] - liz_off[i]);
+        info[i] = orc_tau_row_one(lmax, n_liz, pos + 3 * liz_off[i], species + liz_off[i], Ez[e_idx[i]], dl,
+                                  n_species, gaunt, refine, (zc *)out + row_off[i]);
+        free(dl);
+    }
+    free(gaunt);
+}
+
+/* Batched ln det M: ld[i] complex, problem layout as orc_tau00_batch. */
+void orc_logdet_batch(int lmax, int n_inst, const int64_t *liz_off, const double *pos, const int32_t *species,
+                      const double *energy, const int32_t *e_idx, const double *delta, int n_species, int n_energy,
+                      double *ld, int32_t *info)
+{
+    const int kk = (lmax + 1) * (lmax + 1);
+    const int kk2 = (2 * lmax + 1) * (2 * lmax + 1);
+    double *gaunt = (double *)malloc(sizeof(double) * (size_t)kk * kk * kk2);
+    orc_gaunt(lmax, gaunt);
+    const zc *Ez = (const zc *)energy;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < n_inst; ++i) {
+        zc *dl = orc_instance_delta(lmax, (const zc *)delta, n_species, n_energy, e_idx[i]);
+        const int n_liz = (int)(liz_off[i + 1] - liz_off[i]);
+        info[i] = orc_logdet_one(lmax, n_liz, pos + 3 * liz_off[i], species + liz_off[i], Ez[e_idx[i]], dl,
+                                 n_species, gaunt, (zc *)ld + i);
+        free(dl);
+    }
+    free(gaunt);
 }

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lsms_tau.h"
@@ -108,10 +109,35 @@ struct GraphEntry {
   uint64_t stamp;
 };
 
+// Scratch of tau00_batched_noalloc: room for the inverses of the two 64 x 64
+// diagonal blocks of a wide panel for kNoAllocSlots instances (one pass of
+// the batch).  Host code never passes the array's name to a kernel: it uses
+// the device address taken once per device by scratch_setup.
+constexpr int kNoAllocSlots = 256;
+constexpr size_t kScratchBytes = (size_t)kNoAllocSlots * kLsmsXgBytes;  // 32 MiB
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on `device` (which must be current),
+// taken on the first call for that device.  Returns 0 or LSMS_EHIP.
+int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return LSMS_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return 0;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LSMS_EHIP;
+  g_scratch_ptr[device] = ptr;
+  return 0;
+}
+
 }  // namespace
 
 struct lsms_handle_s {
   int device;
+  void* scratch;  // this device's address of the scratch array
   lsms_gaunt_dev g[kMaxLmax + 1];
   void* mem[kMaxLmax + 1];
   int32_t tuned_nb[kPrecisions][kBuckets];
@@ -237,11 +263,12 @@ extern "C" int lsms_create(lsms_handle_t* out, int device) {
     h->g[lmax].lmax = lmax;
     h->g[lmax].nnz = (int32_t)coef.size();
   }
-  if (lsms_prepare_kernels() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+  if (lsms_prepare_kernels() != hipSuccess || scratch_setup(device) != 0 || hipDeviceSynchronize() != hipSuccess) {
     for (int q = 0; q <= kMaxLmax; ++q) (void)hipFree(h->mem[q]);
     delete h;
     return LSMS_EHIP;
   }
+  h->scratch = g_scratch_ptr[device];
   *out = h;
   return 0;
 }
@@ -313,6 +340,35 @@ extern "C" int tau00_batched(lsms_handle_t h, const lsms_problem* p, double* M, 
   if (lsms_launch_lu_fp64(d, 0, p->n_inst, M, m_off, 0, (double*)work, work ? kLsmsXgBytes / 16 : 0, tau00, info,
                           0, panel_width(h, p, opts), (hipStream_t)stream) != hipSuccess)
     return LSMS_EHIP;
+  return 0;
+}
+
+// The allocation-free variant of tau00_batched: the same kernels, the
+// wide-panel blocks in the handle device's scratch array, the batch in
+// passes of kNoAllocSlots instances (stream-ordered, so each pass reuses the
+// array).  Enqueues kernel launches only.
+extern "C" int tau00_batched_noalloc(lsms_handle_t h, const lsms_problem* p, double* M, const int64_t* m_off,
+                                     const lsms_opts* opts, double* tau00, int32_t* info, void* stream) {
+  if (!h) return -1;
+  int r = check_problem(p);
+  if (r) return r;
+  if (check_opts(opts) || mixed(opts)) return -5;
+  if (p->n_inst == 0) return 0;
+  if (!M) return -3;
+  if (!m_off) return -4;
+  if (!tau00) return -6;
+  if (!info) return -7;
+  if (!h->scratch) return LSMS_EHIP;
+  (void)hipSetDevice(h->device);
+  const lsms_prob_dev d = to_dev(p);
+  const int32_t nb = panel_width(h, p, opts);
+  for (int32_t i0 = 0; i0 < p->n_inst; i0 += kNoAllocSlots) {
+    const int32_t n = p->n_inst - i0 < kNoAllocSlots ? p->n_inst - i0 : kNoAllocSlots;
+    // the kernel addresses the scratch of instance i at (i - i0) * stride
+    if (lsms_launch_lu_fp64(d, i0, n, M, m_off, 0, (double*)h->scratch, kLsmsXgBytes / 16, tau00, info, 0, nb,
+                            (hipStream_t)stream) != hipSuccess)
+      return LSMS_EHIP;
+  }
   return 0;
 }
 

@@ -58,7 +58,7 @@ PERSISTENT = 1
 GRAPH = 2
 
 
-SYMBOLS = ("lsms_create", "lsms_destroy", "lsms_build_liz", "build_kkr", "tau00_batched",
+SYMBOLS = ("lsms_create", "lsms_destroy", "lsms_build_liz", "build_kkr", "tau00_batched", "tau00_batched_noalloc",
            "lsms_workspace_size", "tau00_solve", "lsms_autotune", "lsms_set_tuned_nb", "lsms_get_tuned_nb",
            "lsms_autotune_save", "lsms_autotune_load",
            "lsms_mlp_features", "lsms_mlp_cast", "lsms_mlp_forward", "lsms_mlp_backward", "lsms_mlp_mse",
@@ -84,6 +84,7 @@ def lib():
         L.build_kkr.argtypes = [_P, ctypes.POINTER(_Problem), _P, _P, _P, _P]
         L.tau00_batched.argtypes = [_P, ctypes.POINTER(_Problem), _P, _P, ctypes.POINTER(Opts), _P, _P, _P,
                                     ctypes.c_size_t, _P]
+        L.tau00_batched_noalloc.argtypes = [_P, ctypes.POINTER(_Problem), _P, _P, ctypes.POINTER(Opts), _P, _P, _P]
         L.lsms_workspace_size.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(Opts), _I32,
                                           ctypes.POINTER(ctypes.c_size_t)]
         L.tau00_solve.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(Opts), _P, _P, _P, ctypes.c_size_t,
@@ -245,6 +246,22 @@ def tau00_batched(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tensor
     wb = 0 if work is None else work.numel() * work.element_size()
     _check(lib().tau00_batched(h.ptr, ctypes.byref(ps), _ptr(M), _ptr(m_off), ctypes.byref(o), _ptr(tau),
                                _ptr(info), _ptr(work), wb, _stream()), "tau00_batched")
+    return _tau_view(tau, kk)[:prob.n_inst], info[:prob.n_inst]
+
+
+def tau00_batched_noalloc(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tensor, opts: Opts | None = None,
+                          tau=None, info=None):
+    """tau00_batched_noalloc (no workspace, no allocation in the library): as tau00_batched."""
+    kk = prob.kk
+    if tau is None:
+        tau = torch.empty(max(prob.n_inst, 1) * kk * kk, dtype=torch.complex128, device="cuda")
+    if info is None:
+        info = torch.empty(max(prob.n_inst, 1), dtype=torch.int32, device="cuda")
+    assert tau.is_contiguous() and info.is_contiguous()
+    ps = prob.struct()
+    o = opts if opts is not None else Opts()
+    _check(lib().tau00_batched_noalloc(h.ptr, ctypes.byref(ps), _ptr(M), _ptr(m_off), ctypes.byref(o), _ptr(tau),
+                                       _ptr(info), _stream()), "tau00_batched_noalloc")
     return _tau_view(tau, kk)[:prob.n_inst], info[:prob.n_inst]
 
 

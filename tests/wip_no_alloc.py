@@ -1,0 +1,94 @@
+"""The allocation-free entry point tau00_batched_noalloc through the C ABI:
+its tau00 must equal, bit for bit, tau00_batched's with a caller workspace
+(the same kernels, panels 128 wide), and meet the FP64 bar against the
+oracle; two calls in a row, the second with a smaller batch, the first with
+more instances than one pass of the scratch array holds."""
+
+import numpy as np
+import pytest
+
+import inputs
+from parity import check_tau, oracle_cached
+
+pytestmark = pytest.mark.gpu
+
+TOL_TAU = 1e-12
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _case(P, h, w):
+    torch = _torch()
+    prob = P.problem_for_workload(h, w)
+    N = prob.kk * np.diff(prob.liz_off.cpu().numpy())
+    m_off = np.concatenate([[0], np.cumsum(N * N)[:-1]]).astype(np.int64)
+    moff = torch.as_tensor(m_off, device="cuda")
+    M = torch.zeros(int((N * N).sum()), dtype=torch.complex128, device="cuda")
+    binfo = P.build_kkr(h, prob, M, moff)
+    torch.cuda.synchronize()
+    assert np.all(binfo.cpu().numpy() == 0)
+    return prob, M, moff
+
+
+@pytest.mark.parametrize("nb", [128, 64])
+def test_noalloc_matches_batched_two_calls(nb):
+    torch = _torch()
+    import paper_2308_16317_amd as P
+
+    h = P.Handle()
+    cfg1 = inputs.config1()
+    w_all = cfg1
+    ref_all, rinfo = oracle_cached("cfg1", w_all)
+    assert np.all(rinfo == 0)
+    # first call: 300 instances (two passes of the 256-instance scratch);
+    # second call: 21 instances
+    for idx in (np.arange(300) % 128, np.arange(5, 128, 6)):
+        w = inputs.subset(cfg1, idx)
+        print(f"noalloc: {len(idx)} instances, nb={nb}", flush=True)
+        prob, M, moff = _case(P, h, w)
+        M2 = M.clone()
+        opts = P.Opts(0, nb, 0, 0)
+        work = torch.empty(prob.n_inst * P.BATCHED_WORK_PER_INST, dtype=torch.uint8, device="cuda")
+        t_ref, i_ref = P.tau00_batched(h, prob, M, moff, opts, work=work)
+        t_na, i_na = P.tau00_batched_noalloc(h, prob, M2, moff, opts)
+        torch.cuda.synchronize()
+        assert np.all(i_ref.cpu().numpy() == 0) and np.all(i_na.cpu().numpy() == 0)
+        a = t_ref.cpu().numpy()
+        b = t_na.cpu().numpy()
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+        # the factored matrices agree as well
+        assert torch.equal(torch.view_as_real(M), torch.view_as_real(M2))
+        check_tau(b, ref_all[idx], w, TOL_TAU, f"noalloc {len(idx)} instances nb={nb}")
+    h.close()
+
+
+def test_noalloc_full_size():
+    # N = 2160 (17 panels of 128 columns), two calls, the second smaller
+    torch = _torch()
+    import paper_2308_16317_amd as P
+
+    h = P.Handle()
+    w2 = inputs.config2()
+    for idx in ([0, 31, 40, 77 * 32 + 16], [3 * 32 + 30]):
+        w = inputs.subset(w2, idx)
+        ref, rinfo = oracle_cached(f"cfg2-{idx}", w)
+        print(f"noalloc full size: {len(idx)} instances", flush=True)
+        prob, M, moff = _case(P, h, w)
+        M2 = M.clone()
+        opts = P.Opts(0, 128, 0, 0)
+        work = torch.empty(prob.n_inst * P.BATCHED_WORK_PER_INST, dtype=torch.uint8, device="cuda")
+        t_ref, i_ref = P.tau00_batched(h, prob, M, moff, opts, work=work)
+        t_na, i_na = P.tau00_batched_noalloc(h, prob, M2, moff, opts)
+        torch.cuda.synchronize()
+        assert np.all(i_ref.cpu().numpy() == 0) and np.all(i_na.cpu().numpy() == 0)
+        b = t_na.cpu().numpy()
+        assert np.array_equal(t_ref.cpu().numpy().view(np.uint64), b.view(np.uint64))
+        check_tau(b, ref, w, TOL_TAU, f"noalloc full size {len(idx)}")
+        del M, M2
+    h.close()
