@@ -21,6 +21,11 @@ TOL_TAU = 1e-12
 TOL_M = 1e-13
 
 
+def _bits(x):
+    # the raw 64-bit words of a complex array (any strides)
+    return np.ascontiguousarray(x).view(np.uint64)
+
+
 def _torch():
     import torch
 
@@ -467,10 +472,10 @@ def test_graph_follows_tuned_width(P, h):
             d, di = P.tau00_solve(h, prob, work, P.Opts(0, nb, 0, P.PERSISTENT))
             s.synchronize()
             assert np.all(i.cpu().numpy() == 0) and np.all(di.cpu().numpy() == 0)
-            assert np.array_equal(got.view(np.uint64), d.cpu().numpy().view(np.uint64)), nb
+            assert np.array_equal(_bits(got), _bits(d.cpu().numpy())), nb
             check_tau(got, ref, w, TOL_TAU, f"graph with tuned nb={nb}")
             out[nb] = got
-    assert not np.array_equal(out[32].view(np.uint64), out[128].view(np.uint64))
+    assert not np.array_equal(_bits(out[32]), _bits(out[128]))
 
 
 @pytest.mark.parametrize("max_liz", [300, 1024])
