@@ -15,6 +15,11 @@ pytestmark = pytest.mark.gpu
 TOL_TAU = 1e-12
 
 
+def _bits(x):
+    # the raw 64-bit words of a complex array (any strides)
+    return np.ascontiguousarray(x).view(np.uint64)
+
+
 def _torch():
     import torch
 
@@ -61,7 +66,7 @@ def test_noalloc_matches_batched_two_calls(nb):
         assert np.all(i_ref.cpu().numpy() == 0) and np.all(i_na.cpu().numpy() == 0)
         a = t_ref.cpu().numpy()
         b = t_na.cpu().numpy()
-        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+        assert np.array_equal(_bits(a), _bits(b))
         # the factored matrices agree as well
         assert torch.equal(torch.view_as_real(M), torch.view_as_real(M2))
         check_tau(b, ref_all[idx], w, TOL_TAU, f"noalloc {len(idx)} instances nb={nb}")
@@ -88,7 +93,7 @@ def test_noalloc_full_size():
         torch.cuda.synchronize()
         assert np.all(i_ref.cpu().numpy() == 0) and np.all(i_na.cpu().numpy() == 0)
         b = t_na.cpu().numpy()
-        assert np.array_equal(t_ref.cpu().numpy().view(np.uint64), b.view(np.uint64))
+        assert np.array_equal(_bits(t_ref.cpu().numpy()), _bits(b))
         check_tau(b, ref, w, TOL_TAU, f"noalloc full size {len(idx)}")
         del M, M2
     h.close()
