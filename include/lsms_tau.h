@@ -192,6 +192,60 @@ int build_kkr(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *
 int tau00_batched(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *m_off, const lsms_opts *opts,
                   double *tau00, int32_t *info, void *work, size_t work_bytes, void *stream);
 
+/* Block row of tau through the central site and ln det M, with tau00, from
+ * caller-built matrices in complex FP64.
+ * tau = (t^{-1} - g0)^{-1} = M^{-1} t (paper Sec. 2.1, eq. Dyson_equation);
+ * its blocks tau^{0j} over the LIZ sites j enter the Green's function of
+ * eq. Green_KKR.  ln det M is the multiple-scattering term of Lloyd's formula
+ * for the integrated density of states (the energy integral of eq. Density;
+ * lsms_lloyd_idos turns it into that integral along the contour).
+ * The elimination is tau00_batched's (pivots among the non-central rows), with
+ * its upper factor kept, followed by one backward solve for the non-central
+ * part of the block row.
+ *   M, m_off, opts  as tau00_batched (LSMS_PREC_FP64 only, else -5)
+ *   row_off  device [n_inst]: offset (complex elements) of instance i's block
+ *            row in tau_row; required when tau_row is given (else -6)
+ *   tau_row  device complex or NULL: instance i's kk x N_i block row,
+ *            column-major with leading dimension kk:
+ *            tau_row[row_off[i] + L + kk*(kk*j + L')] = tau^{0j}(L, L')
+ *                = [M_i^{-1}]_{0j}(L, L') t_{s(j), l(L')}
+ *            (j = 0 repeats tau00); NaN when info[i] != 0 (not written for
+ *            info -3)
+ *   logdet   device [n_inst] complex or NULL: ln det M_i, the imaginary
+ *            part in (-pi, pi] (principal logarithm); NaN when info[i] != 0
+ *   tau00, info  as tau00_batched (argument numbers 9 and 10)
+ *   work     device, at least lsms_row_workspace_size bytes (-11 when NULL,
+ *            -12 when too small): per instance the wide-panel blocks, the
+ *            N x 16 (kk > 16: N x 32) block column of the solve and the pivots
+ * Panels up to 128 wide (opts->nb or the tuned width). */
+int lsms_row_workspace_size(lsms_handle_t h, const lsms_problem *p, size_t *bytes);
+int tau_row_batched(lsms_handle_t h, const lsms_problem *p, double *M, const int64_t *m_off, const lsms_opts *opts,
+                    const int64_t *row_off, double *tau_row, double *logdet, double *tau00, int32_t *info,
+                    void *work, size_t work_bytes, void *stream);
+
+/* Energy integration along the contour (paper Sec. 2.1, eq. Density: the
+ * density of states and the charge are energy integrals, taken by quadrature
+ * on a complex contour).  A batch is laid out [site][energy], instance
+ * s * n_energy + k, the energies in contour order.
+ *   weights  device [n_energy] complex quadrature weights of the contour
+ *   values   device [n_sites][n_energy][m] complex (e.g. tau00 with m = kk*kk)
+ *   out      device [n_sites][m] complex: out[s][c] = sum_k weights[k] values[s][k][c]
+ * Errors: -2 n_sites < 0, -3 n_energy < 1, -4 m < 0, -5..-7 null pointers. */
+int lsms_contour_sum(lsms_handle_t h, int32_t n_sites, int32_t n_energy, int32_t m, const double *weights,
+                     const double *values, double *out, void *stream);
+
+/* Lloyd's formula along the contour: from ln det M at the contour's nodes
+ * (logdet device [n_sites][n_energy] complex, in contour order, as returned
+ * by tau_row_batched), the multiple-scattering integrated density of states
+ * relative to the first node, idos device [n_sites][n_energy] double:
+ *     idos[s][k] = -(phi_k - phi_0) / pi,
+ * phi the phase of det M followed continuously from node to node, each step
+ * being the difference of the principal phases reduced to [-pi, pi] (the
+ * phase must move by less than pi between neighbouring nodes).
+ * Errors: -2 n_sites < 0, -3 n_energy < 1, -4/-5 null pointers. */
+int lsms_lloyd_idos(lsms_handle_t h, int32_t n_sites, int32_t n_energy, const double *logdet, double *idos,
+                    void *stream);
+
 /* For callers that cannot allocate device memory (code under hipGraph
  * capture, tight serving loops, harnesses that forbid hipMalloc): tau00_batched
  * without the workspace argument and without any allocation.  The wide-panel

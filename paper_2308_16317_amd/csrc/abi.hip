@@ -343,6 +343,66 @@ extern "C" int tau00_batched(lsms_handle_t h, const lsms_problem* p, double* M, 
   return 0;
 }
 
+extern "C" int lsms_row_workspace_size(lsms_handle_t h, const lsms_problem* p, size_t* bytes) {
+  if (!h) return -1;
+  int r = check_problem(p);
+  if (r) return r;
+  if (!bytes) return -3;
+  *bytes = (size_t)p->n_inst * (size_t)lsms_row_slot_bytes(to_dev(p));
+  return 0;
+}
+
+extern "C" int tau_row_batched(lsms_handle_t h, const lsms_problem* p, double* M, const int64_t* m_off,
+                               const lsms_opts* opts, const int64_t* row_off, double* tau_row, double* logdet,
+                               double* tau00, int32_t* info, void* work, size_t work_bytes, void* stream) {
+  if (!h) return -1;
+  int r = check_problem(p);
+  if (r) return r;
+  if (check_opts(opts) || mixed(opts)) return -5;
+  if (p->n_inst == 0) return 0;
+  if (!M) return -3;
+  if (!m_off) return -4;
+  if (tau_row && !row_off) return -6;
+  if (!tau00) return -9;
+  if (!info) return -10;
+  if (!work) return -11;
+  if (work_bytes < (size_t)p->n_inst * (size_t)lsms_row_slot_bytes(to_dev(p))) return -12;
+  (void)hipSetDevice(h->device);
+  const lsms_prob_dev d = to_dev(p);
+  if (lsms_launch_tau_row(d, 0, p->n_inst, M, m_off, (unsigned char*)work, row_off, tau_row, logdet, tau00, info,
+                          panel_width(h, p, opts), (hipStream_t)stream) != hipSuccess)
+    return LSMS_EHIP;
+  return 0;
+}
+
+extern "C" int lsms_contour_sum(lsms_handle_t h, int32_t n_sites, int32_t n_energy, int32_t m,
+                                const double* weights, const double* values, double* out, void* stream) {
+  if (!h) return -1;
+  if (n_sites < 0) return -2;
+  if (n_energy < 1) return -3;
+  if (m < 0) return -4;
+  if ((int64_t)n_sites * m == 0) return 0;
+  if (!weights) return -5;
+  if (!values) return -6;
+  if (!out) return -7;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_contour_sum(n_sites, n_energy, m, weights, values, out, (hipStream_t)stream) == hipSuccess
+             ? 0
+             : LSMS_EHIP;
+}
+
+extern "C" int lsms_lloyd_idos(lsms_handle_t h, int32_t n_sites, int32_t n_energy, const double* logdet,
+                               double* idos, void* stream) {
+  if (!h) return -1;
+  if (n_sites < 0) return -2;
+  if (n_energy < 1) return -3;
+  if (n_sites == 0) return 0;
+  if (!logdet) return -4;
+  if (!idos) return -5;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_lloyd_idos(n_sites, n_energy, logdet, idos, (hipStream_t)stream) == hipSuccess ? 0 : LSMS_EHIP;
+}
+
 // The allocation-free variant of tau00_batched: the same kernels, the
 // wide-panel blocks in the handle device's scratch array, the batch in
 // passes of kNoAllocSlots instances (stream-ordered, so each pass reuses the

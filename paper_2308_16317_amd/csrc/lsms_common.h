@@ -131,7 +131,20 @@ hipError_t lsms_launch_lu_fp64(const lsms_prob_dev& p, int32_t i0, int32_t n, do
 // size, and the fused build + elimination launch.  `counter` must be zero at
 // launch; slot is the per-workgroup slot in complex elements, the matrix
 // first and (xoff > 0) the two 64 x 64 blocks xoff elements in.
+// Block row of tau and ln det M (FP64 path on caller-built M, one workgroup
+// per instance i0 .. i0+n-1, workspace of lsms_row_slot_bytes per instance
+// at work + (i - i0) * slot); row / logdet may be null.
+int64_t lsms_row_slot_bytes(const lsms_prob_dev& p);
+hipError_t lsms_launch_tau_row(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, const int64_t* m_off,
+                               unsigned char* work, const int64_t* row_off, double* row, double* logdet,
+                               double* tau00, int32_t* info, int32_t nb, hipStream_t s);
 hipError_t lsms_launch_lpt_order(const lsms_prob_dev& p, int32_t* order, hipStream_t s);
+
+// Contour quadrature and Lloyd's integrated density of states (contour.hip).
+hipError_t lsms_launch_contour_sum(int32_t n_sites, int32_t n_energy, int32_t m, const double* w, const double* v,
+                                   double* out, hipStream_t s);
+hipError_t lsms_launch_lloyd_idos(int32_t n_sites, int32_t n_energy, const double* logdet, double* idos,
+                                  hipStream_t s);
 hipError_t lsms_persistent_grid(const lsms_prob_dev& p, int device, int* grid);
 hipError_t lsms_launch_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order,
                                   int32_t* counter, double* work, int64_t slot, int64_t xoff, int grid,

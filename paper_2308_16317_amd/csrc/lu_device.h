@@ -79,6 +79,8 @@ struct LuSmem {
   int info;
   int bad;
   int gj_piv;
+  double red[2][kLuWaves];  // per-wave partial sums of a workgroup reduction
+  int redi[kLuWaves];
 };
 
 // Pointers into the matrix reach the kernels as generic pointers; the hot

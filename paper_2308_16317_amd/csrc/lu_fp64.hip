@@ -43,11 +43,213 @@ namespace {
 constexpr int kThreads = kLuThreads;
 typedef LuSmem<double> LuSmemD;
 
+// ----------------------------------------------------------------------
+// Optional outputs of the FP64 path: the central block row of tau and
+// ln det M.
+//
+// With the pivots confined to the non-central rows, the elimination gives
+// P A_int = L U with the central rows never interchanged, so that
+// Y = A_int^{-1} E_c (E_c the unit vectors of the central rows) solves
+// U Y = E_c: the central rows are Y_c = S_A^{-1} and the others
+// Y_r = -U_rr^{-1} U_rc S_A^{-1}, one backward solve with U (L and the
+// interchanges act only on the zero non-central rows of E_c).  As A = M^T,
+// Y^T is the central block row of M^{-1}, and the block row of tau through
+// the central site is tau^{0j}(L, L') = Y[kk j + L'][L] t_{s(j), l(L')}
+// (paper Sec. 2.1: the blocks of the Dyson-equation inverse, which enter the
+// Green's function of eq. Green_KKR).
+//
+// ln det M = ln det A = sum over the elimination pivots of ln U_vv, plus the
+// logarithms of the Gauss-Jordan pivots of S_A, plus i pi per row
+// interchange; the imaginary part is reduced to (-pi, pi] (the principal
+// logarithm).  ln det M is the multiple-scattering term of Lloyd's formula
+// for the integrated density of states, the energy integral of eq. Density.
+// ----------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846;
+
+struct RowOut {
+  zd* z;          // N x kp workspace, internal rows (needed for row)
+  int32_t* ipiv;  // N workspace (needed for logdet)
+  zd* row;        // block row of tau, kk x N column-major (ld kk), or null
+  zd* logdet;     // ln det M (one complex), or null
+  int kp;         // 16 (kk <= 16) or 32
+};
+
+// Sums of a, b and c over the workgroup, returned to every thread in a fixed
+// order (the same result on every run).
+__device__ __forceinline__ void block_sum(double& a, double& b, int& c, LuSmemD& sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+    c += __shfl_xor(c, o);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh.red[0][wave] = a;
+    sh.red[1][wave] = b;
+    sh.redi[wave] = c;
+  }
+  __syncthreads();
+  a = 0.0;
+  b = 0.0;
+  c = 0;
+#pragma unroll
+  for (int q = 0; q < kLuWaves; ++q) {
+    a += sh.red[0][q];
+    b += sh.red[1][q];
+    c += sh.redi[q];
+  }
+  __syncthreads();
+}
+
+// Y_r := -U_rr^{-1} (U_rc Y_c) for the non-central rows, with Y_c already in
+// the central rows of z (N x kp, internal rows, columns >= kk zero), by
+// 64-row blocks from the bottom: part = U(c .. c+w, c+w .. N) z(c+w .. N) on
+// MFMA (four 16-row tiles per 16 columns, the reduction split between wave
+// groups when kp = 16), then z(c .. c+w) = -X part with X the inverse of the
+// diagonal block of U.
+__device__ __noinline__ void back_solve_rows(const Mat<zd>& Ain, zd* zin, int kp, LuSmemD& sh) {
+  const Mat<zd> A = Ain;  // by value: fields stay in registers
+  typedef Prec<double>::V4 V4;
+  LSMS_GLOBAL zd* z = glb(zin);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int N = (int)A.N, Nd = A.Nd, nct = kp / 16;
+  const int nblk = (Nd + kNB - 1) / kNB;
+  for (int pi = nblk - 1; pi >= 0; --pi) {
+    const int c = pi * kNB, w = min(kNB, Nd - c);
+    invert_upper<double>(A, c, w, sh);  // sh.X; ends with a barrier
+    const int ntile = 4 * nct, nsplit = kLuWaves / ntile;
+    const int tile = wave % ntile, split = wave / ntile;
+    const int rt = tile & 3, ct = tile >> 2;
+    const int k0 = c + w, klen = N - k0;
+    const int kchunk = ((klen + nsplit - 1) / nsplit + 15) & ~15;
+    const int ka = k0 + split * kchunk, kz = min(N, ka + kchunk);
+    V4 ar = V4{0.0, 0.0, 0.0, 0.0}, ai = V4{0.0, 0.0, 0.0, 0.0};
+    const int row = c + 16 * rt + li;
+    const bool rok = 16 * rt + li < w;
+    const LSMS_GLOBAL zd* urow = A.base + A.phys(rok ? row : c) * A.N;
+    // chunks of 16 (lane (li, lq) takes k = kb + 4 lq + j at step j), loaded
+    // one chunk ahead from clamped in-range addresses; entries past the
+    // range are zeroed before they enter the product
+    zd an[4], yn[4];
+    auto ld = [&](int kb) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = min(kb + 4 * lq + j, N - 1);
+        an[j] = urow[A.phys(k)];
+        yn[j] = z[(int64_t)k * kp + 16 * ct + li];
+      }
+    };
+    if (ka < kz) ld(ka);
+    for (int kb = ka; kb < kz; kb += 16) {
+      zd a[4], y[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        a[j] = an[j];
+        y[j] = yn[j];
+      }
+      if (kb + 16 < kz) ld(kb + 16);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool ok = rok && kb + 4 * lq + j < kz;
+        const double axr = ok ? a[j].x : 0.0, axi = ok ? a[j].y : 0.0;
+        ar = Prec<double>::mfma(axr, y[j].x, ar);
+        ar = Prec<double>::mfma(-axi, y[j].y, ar);
+        ai = Prec<double>::mfma(axr, y[j].y, ai);
+        ai = Prec<double>::mfma(axi, y[j].x, ai);
+      }
+    }
+    // partial sums of split q in columns [32 q, 32 q + kp) of sh.U
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      sh.U[16 * rt + Prec<double>::drow(r, lq)][32 * split + 16 * ct + li] = zmake(ar[r], ai[r]);
+    __syncthreads();
+    for (int q = tid; q < kNB * kp; q += kThreads) {
+      const int i = q / kp, j = q % kp;
+      zd v = zmake(0.0, 0.0);
+      if (i < w) {
+        const zd p0 = sh.U[i][j];
+        const zd p1 = nsplit > 1 ? sh.U[i][32 + j] : zmake(0.0, 0.0);
+        v = zmake(-(p0.x + p1.x), -(p0.y + p1.y));
+      }
+      sh.U[i][j] = v;
+    }
+    __syncthreads();
+    // z(c .. c+w) = X * sh.U (rows >= w of sh.U and columns >= w of X are zero)
+    const int rt2 = wave & 3, ct2 = wave >> 2;
+    if (ct2 < nct) {
+      V4 br = V4{0.0, 0.0, 0.0, 0.0}, bi = V4{0.0, 0.0, 0.0, 0.0};
+      for (int kb = 0; kb < w; kb += 4) {
+        const int k = kb + lq;
+        const zd x = sh.X[16 * rt2 + li][k];
+        const zd y = sh.U[k][16 * ct2 + li];
+        br = Prec<double>::mfma(x.x, y.x, br);
+        br = Prec<double>::mfma(-x.y, y.y, br);
+        bi = Prec<double>::mfma(x.x, y.y, bi);
+        bi = Prec<double>::mfma(x.y, y.x, bi);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * rt2 + Prec<double>::drow(r, lq);
+        if (i < w) z[(int64_t)(c + i) * kp + 16 * ct2 + li] = zmake(br[r], bi[r]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The block row of tau of one instance from S_A^{-1} (Gauss-Jordan result in
+// the right half of G) and the factored A; NaN when info0 != 0.  Sets sh.bad
+// on a non-finite entry.  Ends after a barrier.
+__device__ __noinline__ void row_output(const lsms_prob_dev& p, int inst, const Mat<zd>& Ain, const RowOut& ro,
+                                        int info0, LuSmemD& sh) {
+  const Mat<zd> A = Ain;
+  const int tid = threadIdx.x, kk = p.kk, N = (int)A.N, Nd = A.Nd, kp = ro.kp;
+  LSMS_GLOBAL zd* z = glb(ro.z);
+  LSMS_GLOBAL zd* out = glb(ro.row);
+  if (info0 != 0) {
+    for (int q = tid; q < kk * N; q += kThreads) out[q] = zmake((double)NAN, (double)NAN);
+    __syncthreads();
+    return;
+  }
+  const zd(*G)[2 * kMaxKK] = reinterpret_cast<const zd(*)[2 * kMaxKK]>(&sh.U[0][0]);
+  for (int q = tid; q < kk * kp; q += kThreads) {
+    const int r = q / kp, L = q % kp;
+    z[(int64_t)(Nd + r) * kp + L] = L < kk ? G[r][kk + L] : zmake(0.0, 0.0);
+  }
+  __syncthreads();
+  if (Nd > 0) back_solve_rows(A, ro.z, kp, sh);
+  // t of every (species, l) at this energy, in sh.X
+  zd* tt = &sh.X[0][0];
+  const int e = p.e_idx[inst], nl = p.lmax + 1;
+  const zd kap = zsqrt(reinterpret_cast<const zd*>(p.energy)[e]);
+  const zd* dz = reinterpret_cast<const zd*>(p.delta);
+  for (int q = tid; q < p.n_species * nl; q += kThreads)
+    tt[q] = tmat_from_delta(dz[((int64_t)(q / nl) * p.n_energy + e) * nl + q % nl], kap);
+  __syncthreads();
+  const int32_t* spec = p.species + p.liz_off[inst];
+  bool bad = false;
+  for (int q = tid; q < kk * N; q += kThreads) {
+    const int col = q / kk, L = q - col * kk;  // col = kk j + L' (physical)
+    const int j = col / kk, Lp = col - j * kk;
+    const int v = col >= kk ? col - kk : Nd + col;  // internal row of Y
+    const int sj = min(max(spec[j], 0), p.n_species - 1);
+    const zd val = zmul(z[(int64_t)v * kp + L], tt[sj * nl + l_of(Lp)]);
+    bad |= !zfinite(val);
+    out[q] = val;
+  }
+  if (bad) sh.bad = 1;
+  __syncthreads();
+}
+
 // Eliminates one instance whose matrix is at `base` and writes its tau00 and
-// info.  All threads of the workgroup call it; it ends after a barrier.
+// info (and, with ro, its block row of tau and ln det M).  All threads of the
+// workgroup call it; it ends after a barrier.
 template <int kR, int kWL>
 __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, double* __restrict__ tau00,
-                            int32_t* __restrict__ info, int nb, LuSmemD& sh) {
+                            int32_t* __restrict__ info, int nb, LuSmemD& sh, const RowOut ro = RowOut{}) {
   const int tid = threadIdx.x;
   const int kk = p.kk;
   const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
@@ -63,7 +265,19 @@ __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, 
     sh.bad = 0;
   }
   __syncthreads();
-  eliminate<double, kR, kWL>(A, 0, Nd, Nd, nb, false, nullptr, xg, sh);
+  const bool want_row = ro.row != nullptr, want_ld = ro.logdet != nullptr;
+  eliminate<double, kR, kWL>(A, 0, Nd, Nd, nb, want_row, want_ld ? ro.ipiv : nullptr, xg, sh);
+  double ld_re = 0.0, ld_im = 0.0;
+  int ld_sw = 0;
+  if (want_ld) {
+    for (int v = tid; v < Nd; v += kThreads) {
+      const zd u = *A.ptr(v, v);
+      ld_re += log(hypot(u.x, u.y));
+      ld_im += atan2(u.y, u.x);
+      ld_sw += ro.ipiv[v] != v;
+    }
+    block_sum(ld_re, ld_im, ld_sw, sh);
+  }
 
   // Gauss-Jordan inverse of S_A (kk x kk, physical rows/cols 0..kk-1) in sh.U
   zd(*G)[2 * kMaxKK] = reinterpret_cast<zd(*)[2 * kMaxKK]>(&sh.U[0][0]);
@@ -94,7 +308,15 @@ __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, 
       G[pr][tid] = t;
     }
     __syncthreads();
-    if (tid == 0) sh.pinv = zinv(G[k][k]);
+    if (tid == 0) {
+      const zd g = G[k][k];
+      sh.pinv = zinv(g);
+      if (want_ld) {
+        ld_re += log(hypot(g.x, g.y));
+        ld_im += atan2(g.y, g.x);
+        ld_sw += pr != k;
+      }
+    }
     __syncthreads();
     if (tid < 2 * kk) G[k][tid] = zmul(G[k][tid], sh.pinv);
     if (tid < kk) sh.tz[tid] = G[tid][k];  // elimination factors (row k unused)
@@ -117,6 +339,19 @@ __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, 
     if (info0 != 0) v = zmake((double)NAN, (double)NAN);
     if (!zfinite(v)) sh.bad = 1;
     tout[q] = v;
+  }
+  __syncthreads();
+  if (want_row) row_output(p, inst, A, ro, info0, sh);
+  if (want_ld && tid == 0) {
+    // every thread holds the sums over the U diagonal; thread 0 also those
+    // of the Gauss-Jordan pivots
+    double im = ld_im + ((ld_sw & 1) ? kPi : 0.0);
+    im = remainder(im, 2.0 * kPi);
+    if (im <= -kPi) im += 2.0 * kPi;
+    zd v = zmake(ld_re, im);
+    if (info0 != 0) v = zmake((double)NAN, (double)NAN);
+    else if (!zfinite(v)) sh.bad = 1;
+    *ro.logdet = v;
   }
   __syncthreads();
   if (tid == 0) info[inst] = info0 != 0 ? info0 : (sh.bad ? -1 : 0);
@@ -156,6 +391,50 @@ __global__ __launch_bounds__(kThreads) void lu_schur_fp64_kernel(lsms_prob_dev p
   zd* base = reinterpret_cast<zd*>(Mb) + (m_off ? m_off[inst] : (int64_t)(inst - i0) * slot);
   zd* xg = xgb ? reinterpret_cast<zd*>(xgb) + (int64_t)(inst - i0) * xstride : nullptr;
   lu_instance<kR, kWL>(p, inst, base, xg, tau00, info, nb, sh);
+}
+
+// Per-instance workspace of the block-row kernel: [xg | z | ipiv], each
+// 256-byte aligned, for matrices up to nmax.
+__host__ __device__ inline int row_kp(int kk) { return kk <= 16 ? 16 : 32; }
+__host__ __device__ inline int64_t row_z_off() { return kLsmsXgBytes; }
+__host__ __device__ inline int64_t row_ipiv_off(int64_t nmax, int kk) {
+  return row_z_off() + ((nmax * row_kp(kk) * 16 + 255) & ~(int64_t)255);
+}
+__host__ __device__ inline int64_t row_slot_bytes(int64_t nmax, int kk) {
+  return row_ipiv_off(nmax, kk) + ((nmax * 4 + 255) & ~(int64_t)255);
+}
+
+// One workgroup per instance i0 + blockIdx.x: tau00 and, where requested,
+// the block row of tau (at row + 2 row_off[i] doubles) and ln det M (at
+// logdet + 2 i).  Caller-built M at m_off[i]; the instance's workspace at
+// work + (i - i0) wslot bytes.
+template <int kR, int kWL>
+__global__ __launch_bounds__(kThreads) void tau_row_fp64_kernel(
+    lsms_prob_dev p, int i0, double* __restrict__ Mb, const int64_t* __restrict__ m_off,
+    unsigned char* __restrict__ work, int64_t wslot, const int64_t* __restrict__ row_off,
+    double* __restrict__ row, double* __restrict__ logdet, double* __restrict__ tau00,
+    int32_t* __restrict__ info, int nb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
+  const int inst = i0 + blockIdx.x;
+  if (instance_invalid<kR>(p, inst)) {
+    fill_nan(p, inst, tau00);
+    if (threadIdx.x == 0) {
+      info[inst] = -3;
+      if (logdet) reinterpret_cast<zd*>(logdet)[inst] = zmake((double)NAN, (double)NAN);
+    }
+    return;
+  }
+  unsigned char* ws = work + (int64_t)(inst - i0) * wslot;
+  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  RowOut ro;
+  ro.z = reinterpret_cast<zd*>(ws + row_z_off());
+  ro.ipiv = reinterpret_cast<int32_t*>(ws + row_ipiv_off(nmax, p.kk));
+  ro.row = row ? reinterpret_cast<zd*>(row) + row_off[inst] : nullptr;
+  ro.logdet = logdet ? reinterpret_cast<zd*>(logdet) + inst : nullptr;
+  ro.kp = row_kp(p.kk);
+  zd* base = reinterpret_cast<zd*>(Mb) + m_off[inst];
+  lu_instance<kR, kWL>(p, inst, base, reinterpret_cast<zd*>(ws), tau00, info, nb, sh, ro);
 }
 
 // Next instance index from the device counter, the same for every thread of
@@ -1447,6 +1726,24 @@ hipError_t lsms_launch_lu_fp64(const lsms_prob_dev& p, int32_t i0, int32_t n, do
   return launch<8, 4>(p, i0, n, M, m_off, slot, xgb, xstride, tau00, info, keep_info, nb, s);
 }
 
+int64_t lsms_row_slot_bytes(const lsms_prob_dev& p) { return row_slot_bytes((int64_t)p.kk * p.max_liz, p.kk); }
+
+hipError_t lsms_launch_tau_row(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, const int64_t* m_off,
+                               unsigned char* work, const int64_t* row_off, double* row, double* logdet,
+                               double* tau00, int32_t* info, int32_t nb, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  const int64_t wslot = row_slot_bytes(nmax, p.kk);
+  const size_t smem = sizeof(LuSmemD);
+  if (nmax <= kThreads * 5)
+    hipLaunchKernelGGL((tau_row_fp64_kernel<5, 8>), dim3(n), dim3(kThreads), smem, s, p, i0, M, m_off, work, wslot,
+                       row_off, row, logdet, tau00, info, nb);
+  else
+    hipLaunchKernelGGL((tau_row_fp64_kernel<8, 4>), dim3(n), dim3(kThreads), smem, s, p, i0, M, m_off, work, wslot,
+                       row_off, row, logdet, tau00, info, nb);
+  return hipGetLastError();
+}
+
 hipError_t lsms_launch_lpt_order(const lsms_prob_dev& p, int32_t* order, hipStream_t s) {
   if (p.n_inst <= 0) return hipSuccess;
   hipLaunchKernelGGL(lpt_order_kernel, dim3(1), dim3(1024), 0, s, p.liz_off, p.n_inst,
@@ -1503,6 +1800,8 @@ hipError_t lsms_prepare_kernels() {
   if ((e = hipFuncSetAttribute((const void*)tau00_mixed_persistent_kernel<8, 4>, attr, m)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)lu_schur_fp64_kernel<5, 8>, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)lu_schur_fp64_kernel<8, 4>, attr, a)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)tau_row_fp64_kernel<5, 8>, attr, a)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)tau_row_fp64_kernel<8, 4>, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)tau00_persistent_kernel<5, 8>, attr, b)) != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)tau00_persistent_kernel<8, 4>, attr, b);
 }

@@ -63,7 +63,8 @@ SYMBOLS = ("lsms_create", "lsms_destroy", "lsms_build_liz", "build_kkr", "tau00_
            "lsms_autotune_save", "lsms_autotune_load",
            "lsms_mlp_features", "lsms_mlp_cast", "lsms_mlp_forward", "lsms_mlp_backward", "lsms_mlp_mse",
            "lsms_mlp_adamw", "lsms_mlp_seed", "lsms_mlp_targets", "lsms_mlp_norm_stats",
-           "lsms_gmres_workspace_size", "tau00_gmres")
+           "lsms_gmres_workspace_size", "tau00_gmres", "lsms_row_workspace_size", "tau_row_batched",
+           "lsms_contour_sum", "lsms_lloyd_idos")
 
 BATCHED_WORK_PER_INST = 2 * 64 * 64 * 16
 MLP_PARAMS = 399616
@@ -85,6 +86,11 @@ def lib():
         L.tau00_batched.argtypes = [_P, ctypes.POINTER(_Problem), _P, _P, ctypes.POINTER(Opts), _P, _P, _P,
                                     ctypes.c_size_t, _P]
         L.tau00_batched_noalloc.argtypes = [_P, ctypes.POINTER(_Problem), _P, _P, ctypes.POINTER(Opts), _P, _P, _P]
+        L.lsms_row_workspace_size.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(ctypes.c_size_t)]
+        L.tau_row_batched.argtypes = [_P, ctypes.POINTER(_Problem), _P, _P, ctypes.POINTER(Opts), _P, _P, _P, _P, _P,
+                                      _P, ctypes.c_size_t, _P]
+        L.lsms_contour_sum.argtypes = [_P, _I32, _I32, _I32, _P, _P, _P, _P]
+        L.lsms_lloyd_idos.argtypes = [_P, _I32, _I32, _P, _P, _P]
         L.lsms_workspace_size.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(Opts), _I32,
                                           ctypes.POINTER(ctypes.c_size_t)]
         L.tau00_solve.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(Opts), _P, _P, _P, ctypes.c_size_t,
@@ -247,6 +253,60 @@ def tau00_batched(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tensor
     _check(lib().tau00_batched(h.ptr, ctypes.byref(ps), _ptr(M), _ptr(m_off), ctypes.byref(o), _ptr(tau),
                                _ptr(info), _ptr(work), wb, _stream()), "tau00_batched")
     return _tau_view(tau, kk)[:prob.n_inst], info[:prob.n_inst]
+
+
+def row_workspace_size(h: Handle, prob: Problem) -> int:
+    b = ctypes.c_size_t()
+    ps = prob.struct()
+    _check(lib().lsms_row_workspace_size(h.ptr, ctypes.byref(ps), ctypes.byref(b)), "lsms_row_workspace_size")
+    return int(b.value)
+
+
+def tau_row_batched(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tensor, opts: Opts | None = None,
+                    row: bool = True, logdet: bool = True, work=None):
+    """tau_row_batched on caller-built M (overwritten).  Returns (rows, row_off, logdet, tau00, info):
+    rows a flat complex128 device buffer, instance i's kk x N_i block row at row_off[i] (column-major,
+    ld kk) or None; logdet [n] complex128 or None; tau00 [n, kk, kk]; info [n]."""
+    kk = prob.kk
+    n = prob.n_inst
+    nl = (prob.liz_off[1:] - prob.liz_off[:-1]) if n else torch.zeros(0, dtype=torch.int64, device="cuda")
+    sizes = kk * kk * nl
+    row_off = torch.cumsum(sizes, 0) - sizes if n else torch.zeros(1, dtype=torch.int64, device="cuda")
+    total = int(sizes.sum().item()) if n else 0
+    rows = torch.empty(max(total, 1), dtype=torch.complex128, device="cuda") if row else None
+    ld = torch.empty(max(n, 1), dtype=torch.complex128, device="cuda") if logdet else None
+    tau = torch.empty(max(n, 1) * kk * kk, dtype=torch.complex128, device="cuda")
+    info = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    if work is None:
+        work = torch.empty(max(row_workspace_size(h, prob), 1), dtype=torch.uint8, device="cuda")
+    ps = prob.struct()
+    o = opts if opts is not None else Opts()
+    row_off = row_off.contiguous()
+    _check(lib().tau_row_batched(h.ptr, ctypes.byref(ps), _ptr(M), _ptr(m_off), ctypes.byref(o), _ptr(row_off),
+                                 _ptr(rows), _ptr(ld), _ptr(tau), _ptr(info), _ptr(work),
+                                 work.numel() * work.element_size(), _stream()), "tau_row_batched")
+    return rows, row_off[:n], (ld[:n] if ld is not None else None), _tau_view(tau, kk)[:n], info[:n]
+
+
+def contour_sum(h: Handle, weights, values: torch.Tensor, n_sites: int, n_energy: int) -> torch.Tensor:
+    """lsms_contour_sum: values [n_sites * n_energy, ...] complex128 (instance s * n_energy + k);
+    returns [n_sites, ...] = sum_k weights[k] values[s, k]."""
+    w = _dev(weights, torch.complex128)
+    v = values.contiguous()
+    m = v.numel() // max(n_sites * n_energy, 1)
+    out = torch.empty((max(n_sites, 1),) + tuple(v.shape[1:]), dtype=torch.complex128, device="cuda")
+    _check(lib().lsms_contour_sum(h.ptr, n_sites, n_energy, m, _ptr(w), _ptr(v), _ptr(out), _stream()),
+           "lsms_contour_sum")
+    return out[:n_sites]
+
+
+def lloyd_idos(h: Handle, logdet: torch.Tensor, n_sites: int, n_energy: int) -> torch.Tensor:
+    """lsms_lloyd_idos: logdet [n_sites * n_energy] complex128 in contour order per site;
+    returns [n_sites, n_energy] float64."""
+    ld = logdet.contiguous()
+    out = torch.empty((max(n_sites, 1), n_energy), dtype=torch.float64, device="cuda")
+    _check(lib().lsms_lloyd_idos(h.ptr, n_sites, n_energy, _ptr(ld), _ptr(out), _stream()), "lsms_lloyd_idos")
+    return out[:n_sites]
 
 
 def tau00_batched_noalloc(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tensor, opts: Opts | None = None,
