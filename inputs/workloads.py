@@ -19,6 +19,10 @@ from scipy.special import spherical_jn, spherical_yn
 A_LAT = 7.0                 # fcc lattice constant, bohr
 R_MT = 0.35 * A_LAT         # muffin-tin radius, bohr
 V0_SPECIES = (1.0, 1.4)     # square-well depths (Ry) of Ni and Au
+# exchange splitting of the wells in the spin-canted recipe (Ry): the spin
+# parallel to a site's moment sees the well deepened by half of it, the other
+# spin the well made shallower by half of it (Ni magnetic, Au weakly polarised)
+SPLIT_SPECIES = (0.10, 0.02)
 
 # Semicircle contour: centre 0.1 Ry, radius 0.6 Ry, from -0.5 to 0.7 Ry, with
 # Gauss-Legendre nodes in the angle restricted to [theta0, pi - theta0] so that
@@ -105,6 +109,15 @@ def phase_shift_table(energies, lmax: int, depths=V0_SPECIES) -> np.ndarray:
     return np.stack([square_well_delta(energies, lmax, v0) for v0 in depths])
 
 
+def spin_phase_shift_tables(energies, lmax: int, depths=V0_SPECIES, splits=SPLIT_SPECIES):
+    """(delta_up, delta_dn), each [species][energy][l]: the phase shifts of the
+    spin parallel (well depth v0 + split/2) and antiparallel (v0 - split/2) to
+    a site's moment."""
+    up = np.stack([square_well_delta(energies, lmax, v0 + 0.5 * d) for v0, d in zip(depths, splits)])
+    dn = np.stack([square_well_delta(energies, lmax, v0 - 0.5 * d) for v0, d in zip(depths, splits)])
+    return up, dn
+
+
 @dataclasses.dataclass
 class Workload:
     """Everything the path takes for a batch of (site, energy) instances.
@@ -112,7 +125,10 @@ class Workload:
     atom_pos/atom_species describe the periodic supercell (box lengths in
     `box`); instance i is centred on atom `centre[i]` with LIZ cutoff radius
     `rc[i]` (bohr) at energy `energies[e_idx[i]]`.  `delta` holds the phase
-    shifts [n_species][n_energy][lmax + 1].
+    shifts [n_species][n_energy][lmax + 1].  Spin-canted workloads also carry
+    a unit moment direction per atom (`atom_moment` [n_atoms, 3]) and the
+    phase shifts of the spin antiparallel to the moment (`delta_dn`, layout of
+    `delta`, which then holds the parallel spin).
     """
 
     name: str
@@ -125,6 +141,8 @@ class Workload:
     centre: np.ndarray
     rc: np.ndarray
     e_idx: np.ndarray
+    atom_moment: np.ndarray | None = None
+    delta_dn: np.ndarray | None = None
 
     @property
     def n_inst(self) -> int:
@@ -134,9 +152,16 @@ class Workload:
     def kk(self) -> int:
         return (self.lmax + 1) ** 2
 
+    @property
+    def spin(self) -> bool:
+        return self.atom_moment is not None
+
     def with_lmax(self, lmax: int) -> "Workload":
-        return dataclasses.replace(self, lmax=lmax, delta=phase_shift_table(self.energies, lmax),
-                                   name=f"{self.name.rsplit('-lmax', 1)[0]}-lmax{lmax}")
+        name = f"{self.name.rsplit('-lmax', 1)[0]}-lmax{lmax}"
+        if self.spin:
+            up, dn = spin_phase_shift_tables(self.energies, lmax)
+            return dataclasses.replace(self, lmax=lmax, delta=up, delta_dn=dn, name=name)
+        return dataclasses.replace(self, lmax=lmax, delta=phase_shift_table(self.energies, lmax), name=name)
 
 
 def _children(seed: int):
@@ -175,6 +200,26 @@ def config2(seed: int = 0) -> Workload:
 def config3(seed: int = 0, lmax: int = 4) -> Workload:
     """The config-2 systems at another lmax (lmax = 4 gives N = 3375)."""
     return config2(seed).with_lmax(lmax)
+
+
+def canted_moments(n_atoms: int, seed: int = 0, cone_deg: float = 60.0) -> np.ndarray:
+    """Unit moment directions [n_atoms, 3], canted from +z: polar angle
+    uniform in [0, cone_deg], azimuth uniform in [0, 2 pi)."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(7)[6])
+    th = np.deg2rad(rng.uniform(0.0, cone_deg, n_atoms))
+    ph = rng.uniform(0.0, 2.0 * np.pi, n_atoms)
+    return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1)
+
+
+def config_canted(seed: int = 0, lmax: int = 3) -> Workload:
+    """Spin-canted case: the config-2 systems (135-atom LIZ) with a canted
+    moment on every atom and spin-split square wells; rank 2 kk 135 = 4320
+    at lmax = 3, 6750 at lmax = 4 (the CoCrFeMnNi rank of the paper's
+    spin-canted benchmark).  8192 instances, site-major."""
+    w = config2(seed)
+    up, dn = spin_phase_shift_tables(w.energies, lmax)
+    return dataclasses.replace(w, name=f"fcc-NiAu-canted-135atomLIZ-lmax{lmax}", lmax=lmax, delta=up, delta_dn=dn,
+                               atom_moment=canted_moments(w.atom_pos.shape[0], seed))
 
 
 def config4(seed: int = 0, n_inst: int = 1024) -> Workload:

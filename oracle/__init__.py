@@ -60,6 +60,9 @@ def lib():
         L.orc_max_threads.restype = _I
         L.orc_tau00_schur.restype = _I
         L.orc_tau00_schur.argtypes = [_I, _I, _P, _P, _P, _P, _I, _P, _P]
+        L.orc_build_m_spin.restype = _I
+        L.orc_build_m_spin.argtypes = [_I, _I, _P, _P, _P, _P, _P, _P, _I, _P, _P]
+        L.orc_tau00_spin_batch.argtypes = [_I, _I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I, _I, _P, _P]
         L.orc_tau_row_batch.argtypes = [_I, _I, _P, _P, _P, _P, _P, _P, _I, _I, _I, _P, _P, _P]
         L.orc_logdet_batch.argtypes = [_I, _I, _P, _P, _P, _P, _P, _P, _I, _I, _P, _P]
         _lib = L
@@ -223,6 +226,66 @@ def tau00_workload(w, refine: int = 2):
     """Oracle tau00 for every instance of an inputs.Workload."""
     liz_off, pos, spec = liz_batch(w)
     return tau00_batch(w.lmax, liz_off, pos, spec, w.energies, w.e_idx, w.delta, refine)
+
+
+# ------------------------------------------------------------- spin canting
+def build_m_spin(lmax: int, rel, spec, mom, E: complex, delta_up_e, delta_dn_e, C=None):
+    """Spin-canted M over one LIZ (rank 2 kk n_liz, index 2 kk j + kk s + L);
+    mom [n_liz, 3] unit moment directions, delta_*_e [n_species, lmax + 1] at
+    this energy.  Returns (M, status)."""
+    if C is None:
+        C, _ = gaunt(lmax)
+    rel = _c(rel, np.float64)
+    spec = _c(spec, np.int32)
+    mom = _c(mom, np.float64)
+    du = _c(delta_up_e, np.complex128)
+    dd = _c(delta_dn_e, np.complex128)
+    n_liz = rel.shape[0]
+    N = 2 * (lmax + 1) ** 2 * n_liz
+    M = np.zeros((N, N), np.complex128, order="F")
+    Er = np.array([complex(E).real, complex(E).imag])
+    st = lib().orc_build_m_spin(lmax, n_liz, _ptr(rel), _ptr(spec), _ptr(mom), _ptr(Er), _ptr(du), _ptr(dd),
+                                du.shape[0], _ptr(_c(C, np.float64)), _ptr(M))
+    return M, st
+
+
+def tau00_spin_batch(lmax: int, liz_off, pos, species, moment, energies, e_idx, delta_up, delta_dn,
+                     refine: int = 2):
+    """Spin-canted tau00 [n_inst, 2kk, 2kk] (natural [(s,L), (s',L')] indexing,
+    index kk s + L) and info [n_inst]; moment [liz rows, 3] per LIZ row."""
+    liz_off = _c(liz_off, np.int64)
+    pos = _c(pos, np.float64)
+    species = _c(species, np.int32)
+    moment = _c(moment, np.float64)
+    energies = _c(energies, np.complex128)
+    e_idx = _c(e_idx, np.int32)
+    du = _c(delta_up, np.complex128)
+    dd = _c(delta_dn, np.complex128)
+    n = e_idx.shape[0]
+    kc = 2 * (lmax + 1) ** 2
+    tau = np.zeros((n, kc, kc), np.complex128)
+    info = np.zeros(n, np.int32)
+    lib().orc_tau00_spin_batch(lmax, n, _ptr(liz_off), _ptr(pos), _ptr(species), _ptr(moment), _ptr(energies),
+                               _ptr(e_idx), _ptr(du), _ptr(dd), du.shape[0], du.shape[1], int(refine), _ptr(tau),
+                               _ptr(info))
+    return tau.transpose(0, 2, 1).copy(), info
+
+
+def liz_moments(w):
+    """Moment direction of every LIZ row of a spin-canted workload, in the
+    order of liz_batch."""
+    out = []
+    for c, r in zip(w.centre, w.rc):
+        _, idx = liz(w.atom_pos, w.box, int(c), float(r))
+        out.append(w.atom_moment[idx])
+    return np.concatenate(out).astype(np.float64)
+
+
+def tau00_spin_workload(w, refine: int = 2):
+    """Oracle spin-canted tau00 for every instance of a spin-canted workload."""
+    liz_off, pos, spec = liz_batch(w)
+    return tau00_spin_batch(w.lmax, liz_off, pos, spec, liz_moments(w), w.energies, w.e_idx, w.delta, w.delta_dn,
+                            refine)
 
 
 # ------------------------------------------------ block row of tau, ln det M

@@ -29,6 +29,9 @@
  *     matrix tau = M^{-1} t (eq. Dyson_equation: (t^{-1} - g0)^{-1} =
  *     (1 - t g0)^{-1} t), whose blocks feed the Green's function of
  *     eq. Green_KKR: rows 0..kk-1 of M^{-1} from M^T Z = E_0, refined as above.
+ *   - The spin-canted matrix (rank 2 kk n_liz, Sec. 2.1) and its tau00, with
+ *     the global-frame t of a canted site written out from the rotation of
+ *     its spin-diagonal local t (the reading is stated at that code).
  *   - ln det M from the same LU (the sum of the logarithms of U's diagonal and
  *     i pi per row interchange), the quantity Lloyd's formula turns into the
  *     multiple-scattering part of the integrated density of states behind
@@ -751,6 +754,177 @@ void orc_logdet_batch(int lmax, int n_inst, const int64_t *liz_off, const double
         info[i] = orc_logdet_one(lmax, n_liz, pos + 3 * liz_off[i], species + liz_off[i], Ez[e_idx[i]], dl,
                                  n_species, gaunt, (zc *)ld + i);
         free(dl);
+    }
+    free(gaunt);
+}
+
+/* ------------------------------------------------------------------ */
+/* Spin-canted KKR matrix and tau00                                    */
+/* ------------------------------------------------------------------ */
+/* With spin canting (non-collinear moments) every matrix carries a spin
+ * index and the rank doubles to 2 kk n_liz (paper Sec. 2.1 and 2.2).  The
+ * paper does not spell out how the spin enters; the reading taken here is
+ * the usual one for non-collinear multiple scattering: site i has a unit
+ * moment direction e_i and, in its own frame (spin axis along e_i), the
+ * spin-diagonal t-matrix diag(t_up, t_dn), t_up from the phase shifts of the
+ * spin parallel to the moment.  Rotated to the global frame by the spin-1/2
+ * rotation U that takes z to e_i,
+ *     t_i(L) = U diag(t_up,l, t_dn,l) U^+ = tbar_l 1 + dt_l (e_i . sigma),
+ * tbar = (t_up + t_dn)/2, dt = (t_up - t_dn)/2, sigma the Pauli matrices.
+ * The free propagator does not act on spin (G (x) 1).  Row/column index of
+ * (site j, spin s, L): 2 kk j + kk s + L, s = 0 the spin along global +z.
+ *     M_ii = 1,   M_ij[(s,L),(s',L')] = -t_i(L)_{s s'} G^{ij}_{L L'}
+ *     tau00[(s,L),(s',L')] = sum_s'' [M^{-1}]_{00}[(s,L),(s'',L')] t_0(L')_{s'' s'}
+ */
+
+/* t of one channel in the global frame: t2[2 s + s'] = t(L)_{s s'}. */
+static void orc_spin_t(zc tu, zc td, const double *e, zc *t2)
+{
+    const zc tb = 0.5 * (tu + td), dt = 0.5 * (tu - td);
+    t2[0] = tb + dt * e[2];
+    t2[1] = dt * (e[0] - I * e[1]);
+    t2[2] = dt * (e[0] + I * e[1]);
+    t2[3] = tb - dt * e[2];
+}
+
+/* Spin-canted M over one LIZ (2 kk n_liz square, column-major); mom[n_liz][3]
+ * unit moment directions, dlu / dld the up / down phase shifts
+ * [s*(lmax+1) + l] at this energy.  Returns as orc_build_m_z. */
+static int orc_build_m_spin_z(int lmax, int n_liz, const double *rel, const int32_t *spec, const double *mom,
+                              zc E, const zc *dlu, const zc *dld, int n_species, const double *gaunt, zc *M)
+{
+    const int kk = (lmax + 1) * (lmax + 1);
+    const int nl = lmax + 1;
+    const size_t N = (size_t)2 * kk * n_liz;
+    const zc kap = csqrt(E);
+    zc *tu = (zc *)malloc(sizeof(zc) * (size_t)n_species * nl);
+    zc *td = (zc *)malloc(sizeof(zc) * (size_t)n_species * nl);
+    for (int q = 0; q < n_species * nl; ++q) {
+        tu[q] = -csin(dlu[q]) * cexp(I * dlu[q]) / kap;
+        td[q] = -csin(dld[q]) * cexp(I * dld[q]) / kap;
+    }
+    zc *G = (zc *)malloc(sizeof(zc) * kk * kk);
+    memset(M, 0, sizeof(zc) * N * N);
+    int rc = 0;
+    for (int j = 0; j < n_liz; ++j) {
+        for (int i = 0; i < n_liz; ++i) {
+            if (i == j) {
+                for (int a = 0; a < 2 * kk; ++a) M[(2 * kk * i + a) + N * (2 * kk * j + a)] = 1.0;
+                continue;
+            }
+            double R[3];
+            for (int k = 0; k < 3; ++k) R[k] = rel[3 * i + k] - rel[3 * j + k];
+            if (sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]) < 1e-8) { rc = -2; continue; }
+            orc_gij(lmax, kap, R, gaunt, G);
+            for (int L = 0; L < kk; ++L) {
+                zc t2[4];
+                const int q = spec[i] * nl + orc_lof(L);
+                orc_spin_t(tu[q], td[q], mom + 3 * i, t2);
+                for (int s = 0; s < 2; ++s)
+                    for (int sp = 0; sp < 2; ++sp)
+                        for (int Lp = 0; Lp < kk; ++Lp)
+                            M[(2 * kk * i + kk * s + L) + N * (2 * kk * j + kk * sp + Lp)] =
+                                -t2[2 * s + sp] * G[L + kk * Lp];
+            }
+        }
+    }
+    free(G); free(tu); free(td);
+    return rc;
+}
+
+int orc_build_m_spin(int lmax, int n_liz, const double *rel, const int32_t *spec, const double *mom,
+                     const double *Eri, const double *dlu, const double *dld, int n_species, const double *gaunt,
+                     double *Mri)
+{
+    const zc E = Eri[0] + I * Eri[1];
+    return orc_build_m_spin_z(lmax, n_liz, rel, spec, mom, E, (const zc *)dlu, (const zc *)dld, n_species, gaunt,
+                              (zc *)Mri);
+}
+
+/* Spin-canted tau00 of one instance (2kk x 2kk column-major); LU with row
+ * partial pivoting on the whole M, the first 2 kk unit columns solved and
+ * refined twice with 80-bit residuals, as orc_tau00_one. */
+static int orc_tau00_spin_one(int lmax, int n_liz, const double *rel, const int32_t *spec, const double *mom,
+                              zc E, const zc *dlu, const zc *dld, int n_species, const double *gaunt, int refine,
+                              zc *tau)
+{
+    const int kk = (lmax + 1) * (lmax + 1);
+    const int kc = 2 * kk;
+    const int nl = lmax + 1;
+    const int n = kc * n_liz;
+    const size_t nn = (size_t)n * n;
+    int info = 0;
+    for (int q = 0; q < kc * kc; ++q) tau[q] = NAN + I * NAN;
+    if (!isfinite(creal(E)) || !isfinite(cimag(E)) || !orc_finite(dlu, (size_t)n_species * nl) ||
+        !orc_finite(dld, (size_t)n_species * nl))
+        return -1;
+    zc *M = (zc *)malloc(sizeof(zc) * nn);
+    zc *LU = (zc *)malloc(sizeof(zc) * nn);
+    zc *X = (zc *)calloc((size_t)n * kc, sizeof(zc));
+    zc *E0 = (zc *)calloc((size_t)n * kc, sizeof(zc));
+    zc *R = (zc *)malloc(sizeof(zc) * (size_t)n * kc);
+    int32_t *ipiv = (int32_t *)malloc(sizeof(int32_t) * n);
+    info = orc_build_m_spin_z(lmax, n_liz, rel, spec, mom, E, dlu, dld, n_species, gaunt, M);
+    if (info == 0 && !orc_finite(M, nn)) info = -1;
+    if (info == 0) {
+        memcpy(LU, M, sizeof(zc) * nn);
+        info = orc_lu_factor(n, (double *)LU, ipiv);
+    }
+    if (info == 0) {
+        for (int c = 0; c < kc; ++c) E0[c + (size_t)n * c] = 1.0;
+        memcpy(X, E0, sizeof(zc) * (size_t)n * kc);
+        orc_lu_solve(n, (const double *)LU, ipiv, kc, (double *)X);
+        for (int it = 0; it < refine; ++it) {
+            orc_residual_ld(n, kc, M, X, E0, R);
+            orc_lu_solve(n, (const double *)LU, ipiv, kc, (double *)R);
+            for (size_t q = 0; q < (size_t)n * kc; ++q) X[q] += R[q];
+        }
+        const zc kap = csqrt(E);
+        for (int Lp = 0; Lp < kk; ++Lp) {
+            const int q = spec[0] * nl + orc_lof(Lp);
+            const zc tu = -csin(dlu[q]) * cexp(I * dlu[q]) / kap;
+            const zc td = -csin(dld[q]) * cexp(I * dld[q]) / kap;
+            zc t2[4];
+            orc_spin_t(tu, td, mom, t2);
+            for (int sp = 0; sp < 2; ++sp)
+                for (int a = 0; a < kc; ++a) {
+                    zc v = 0.0;
+                    for (int s2 = 0; s2 < 2; ++s2) v += X[a + (size_t)n * (kk * s2 + Lp)] * t2[2 * s2 + sp];
+                    tau[a + (size_t)kc * (kk * sp + Lp)] = v;
+                }
+        }
+        if (!orc_finite(tau, (size_t)kc * kc)) info = -1;
+    }
+    if (info != 0)
+        for (int q = 0; q < kc * kc; ++q) tau[q] = NAN + I * NAN;
+    free(M); free(LU); free(X); free(E0); free(R); free(ipiv);
+    return info;
+}
+
+/* Batched spin-canted tau00: problem layout as orc_tau00_batch plus moment
+ * [liz rows][3] (unit directions, per LIZ row like pos) and the down-spin
+ * phase shifts delta_dn (same layout as delta, which holds the up spin).
+ * tau00 is [n_inst][(2kk)^2] column-major per instance. */
+void orc_tau00_spin_batch(int lmax, int n_inst, const int64_t *liz_off, const double *pos, const int32_t *species,
+                          const double *moment, const double *energy, const int32_t *e_idx, const double *delta,
+                          const double *delta_dn, int n_species, int n_energy, int refine, double *tau00,
+                          int32_t *info)
+{
+    const int kk = (lmax + 1) * (lmax + 1);
+    const int kk2 = (2 * lmax + 1) * (2 * lmax + 1);
+    double *gaunt = (double *)malloc(sizeof(double) * (size_t)kk * kk * kk2);
+    orc_gaunt(lmax, gaunt);
+    const zc *Ez = (const zc *)energy;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < n_inst; ++i) {
+        zc *du = orc_instance_delta(lmax, (const zc *)delta, n_species, n_energy, e_idx[i]);
+        zc *dd = orc_instance_delta(lmax, (const zc *)delta_dn, n_species, n_energy, e_idx[i]);
+        const int n_liz = (int)(liz_off[i + 1] - liz_off[i]);
+        info[i] = orc_tau00_spin_one(lmax, n_liz, pos + 3 * liz_off[i], species + liz_off[i],
+                                     moment + 3 * liz_off[i], Ez[e_idx[i]], du, dd, n_species, gaunt, refine,
+                                     (zc *)tau00 + (size_t)i * 4 * kk * kk);
+        free(du);
+        free(dd);
     }
     free(gaunt);
 }
