@@ -279,6 +279,152 @@ def time_forms(args, P, h, w, liz, energy, e_idx, delta, max_liz, tau64, fp64_ra
     return res
 
 
+def time_row(args, P, h, w, liz, energy, e_idx, delta, max_liz, n: int = 256):
+    """The block row of tau with ln det M (tau_row_batched) against tau00
+    alone (tau00_batched) on the first n instances of the workload, both on
+    M built by build_kkr (one pass each, HIP events around the elimination
+    launches; M rebuilt before each).  With the CPU legs, the block rows and
+    ln det M of instances 0 and 31 (both contour ends of the first site) are
+    compared with the oracle."""
+    import torch
+
+    import inputs
+    import oracle
+
+    dev = torch.device("cuda:0")
+    prob = P.Problem(w.lmax, liz["liz_off"][:n + 1], liz["pos"], liz["species"], energy, e_idx[:n], delta,
+                     max_liz=max_liz)
+    N = w.kk * (liz["liz_off"][1:n + 1] - liz["liz_off"][:n])
+    m_off = torch.cumsum(N * N, 0) - N * N
+    M = torch.empty(int((N * N).sum().item()), dtype=torch.complex128, device=dev)
+    xg = torch.empty(n * P.BATCHED_WORK_PER_INST, dtype=torch.uint8, device=dev)
+    rw = torch.empty(P.row_workspace_size(h, prob), dtype=torch.uint8, device=dev)
+    opts = P.Opts(0, args.nb, 0, 0)
+
+    def timed(fn):
+        P.build_kkr(h, prob, M, m_off)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1) * 1e-3
+
+    timed(lambda: P.tau00_batched(h, prob, M, m_off, opts, work=xg))
+    _, t_tau = timed(lambda: P.tau00_batched(h, prob, M, m_off, opts, work=xg))
+    (rows, roff, ld, tau, info), t_row = timed(lambda: P.tau_row_batched(h, prob, M, m_off, opts, work=rw))
+    res = {"instances": n, "N": int(N.max().item()), "row_and_logdet_solves_per_s": n / t_row,
+           "tau00_batched_solves_per_s": n / t_tau, "time_ratio_row_over_tau00": t_row / t_tau,
+           "errors": int((info != 0).sum().item()),
+           "kernels": "tau_row_fp64_kernel vs lu_schur_fp64_kernel, one launch each"}
+    if not args.no_cpu:
+        pick = [0, 31]
+        wp = inputs.subset(w, pick)
+        oracle.set_threads(2)
+        ref_rows, rinfo = oracle.tau_row_workload(wp)
+        ref_ld, linfo = oracle.logdet_workload(wp)
+        kk = w.kk
+        r = rows.cpu().numpy()
+        ro = roff.cpu().numpy()
+        Nn = N.cpu().numpy()
+        rf = [float(np.linalg.norm(r[ro[i]:ro[i] + kk * Nn[i]].reshape(Nn[i], kk).T - ref_rows[q]) /
+                    np.linalg.norm(ref_rows[q])) for q, i in enumerate(pick)]
+        ldg = ld.cpu().numpy()[pick]
+        dld = np.abs(ldg.real - ref_ld.real).max(), np.abs(np.angle(np.exp(1j * (ldg.imag - ref_ld.imag)))).max()
+        res["oracle_check"] = {"instances": pick, "max_row_rel_F": max(rf), "max_logdet_abs_err": float(max(dld)),
+                               "bars": [1e-12, 1e-10],
+                               "pass": bool(max(rf) <= 1e-12 and max(dld) <= 1e-10 and np.all(rinfo == 0))}
+    del M, xg, rw
+    return res
+
+
+def bench_canted(args, lmax: int):
+    """The spin-canted path (tau00_spin_solve, persistent fused kernel, FP64)
+    on the spin-canted recipe: the 135-atom-LIZ systems with canted moments,
+    rank 2 kk 135 (4320 at lmax = 3, 6750 at lmax = 4).  The timed batch is
+    the first n instances (every energy of the first n / 32 sites); the
+    instances of tests/golden/canted_tau00.npz are solved by the same call
+    and compared with those oracle values."""
+    import torch
+
+    import inputs
+    import paper_2308_16317_amd as P
+
+    w_all = inputs.config_canted(lmax=lmax)
+    n = args.n_inst or (1024 if lmax == 3 else 256)
+    w = inputs.subset(w_all, np.arange(n))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    h = P.Handle()
+    prob = P.problem_for_workload(h, w)
+    kc = prob.kc
+    opts = P.Opts(0, args.nb, 0, P.PERSISTENT)
+    work = torch.empty(P.spin_workspace_size(h, prob, 0, opts), dtype=torch.uint8, device=dev)
+    tau = torch.empty(n * kc * kc, dtype=torch.complex128, device=dev)
+    info = torch.empty(n, dtype=torch.int32, device=dev)
+    log(f"[bench] canted lmax={lmax}: {n} instances, rank {kc * prob.max_liz}, workspace {work.numel() / 2**30:.1f} GiB")
+    ev = []
+    for it in range(args.warmup + args.steps):
+        if it == args.warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        P.tau00_spin_solve(h, prob, work, opts, tau=tau, info=info)
+        e1.record()
+        if it >= args.warmup:
+            ev.append((e0, e1))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if int((info != 0).sum().item()):
+        raise RuntimeError(f"canted: info values {torch.unique(info).tolist()}")
+    Ns = kc * np.diff(prob.liz_off.cpu().numpy()).astype(np.float64)
+    flops = float(np.sum(8.0 / 3.0 * Ns ** 3))
+    ms = [a.elapsed_time(b) for a, b in ev]
+    ach = flops / (np.mean(ms) * 1e-3) / 1e12
+    del work
+    # oracle values of the golden instances, solved by the same entry point
+    check = {"pass": None}
+    gpath = os.path.join(ROOT, "tests", "golden", "canted_tau00.npz")
+    if os.path.exists(gpath):
+        g = np.load(gpath, allow_pickle=False)
+        gi, gref = g[f"idx_l{lmax}"], g[f"tau_l{lmax}"]
+        wg = inputs.subset(w_all, gi)
+        pg = P.problem_for_workload(h, wg)
+        wk = torch.empty(P.spin_workspace_size(h, pg, 0, opts), dtype=torch.uint8, device=dev)
+        tg, ig = P.tau00_spin_solve(h, pg, wk, opts)
+        torch.cuda.synchronize()
+        tg = tg.cpu().numpy()
+        rf = np.linalg.norm((tg - gref).reshape(len(gi), -1), axis=1) / np.linalg.norm(gref.reshape(len(gi), -1),
+                                                                                          axis=1)
+        check = {"instances": [int(x) for x in gi], "max_rel_F_vs_oracle": float(rf.max()), "bar": 1e-12,
+                 "pass": bool(rf.max() <= 1e-12 and np.all(ig.cpu().numpy() == 0)),
+                 "source": "tests/golden/canted_tau00.npz (oracle)"}
+    out = {
+        "metric": f"spin-canted τ00 solves/s at rank {int(Ns.max())}",
+        "value": n * args.steps / dt, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w_all.name}: fcc NiAu 50/50 with canted moments (cone 60 deg), spin-split "
+                               f"square wells, first {n} (site, E) instances, 135-atom LIZ, rank "
+                               f"{int(Ns.max())}, lmax={lmax}, complex FP64 LU/Schur",
+                   "n_inst": n, "N": int(Ns.max()), "lmax": lmax, "mode": "persistent", "precision": "fp64"},
+        "tflops": flops * args.steps / dt / 1e12,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                     "traffic_source": "no counters taken on this workload",
+                     "kernel": "tau00_persistent_kernel (spin-canted build + elimination)",
+                     "ms_per_launch": float(np.mean(ms)), "instances_per_launch": n},
+        "oracle_check": check,
+    }
+    print(json.dumps(out), flush=True)
+    if check["pass"] is False:
+        log("[bench] canted tau00 outside the tolerance against the oracle")
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,10 +440,12 @@ def main():
     ap.add_argument("--chunk", type=int, default=1024, help="instances per build/LU launch (chunked)")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--n-inst", type=int, default=0, help="limit the batch (0 = all 8192)")
-    ap.add_argument("--workload", choices=["benchmark", "ragged", "lmax4"], default="benchmark",
+    ap.add_argument("--workload", choices=["benchmark", "ragged", "lmax4", "canted", "canted4"],
+                    default="benchmark",
                     help="benchmark: 8192 instances at N = 2160 (the metric's workload); ragged: 1024 instances of "
                          "the vacancy/noise supercell with cutoffs 1.7a-2.1a (N = 1200-2400); lmax4: the benchmark "
-                         "systems at lmax = 4 (N = 3375)")
+                         "systems at lmax = 4 (N = 3375); canted / canted4: the spin-canted path at rank 4320 / "
+                         "6750 (first 1024 / 256 instances unless --n-inst)")
     ap.add_argument("--forms", choices=["none", "fp32ir", "all"], default="all",
                     help="also time the other forms on the same instances (persistent launch) and report them "
                          "with their speedup over the FP64 path and their deviation from it")
@@ -327,6 +475,10 @@ def main():
     if args.precision == "fp32ir" and args.mode == "chunked":
         print(json.dumps({"error": "--precision fp32ir runs through tau00_solve: use --mode persistent or graph"}))
         sys.exit(2)
+
+    if args.workload in ("canted", "canted4"):
+        bench_canted(args, 3 if args.workload == "canted" else 4)
+        return
 
     import torch
 
@@ -478,6 +630,12 @@ def main():
     if args.forms != "none" and args.precision == "fp64" and args.mode != "chunked":
         out["forms"] = time_forms(args, P, h, w, liz, energy, e_idx, delta, max_liz, tau, n_inst * args.steps / dt,
                                   outputs)
+    if args.forms == "all" and args.workload == "benchmark":
+        try:
+            out["block_row_logdet"] = time_row(args, P, h, w, liz, energy, e_idx, delta, max_liz)
+            log(f"[bench] block row: {out['block_row_logdet']}")
+        except Exception as e:  # reported, not fatal
+            out["block_row_logdet"] = {"error": repr(e)}
     if not args.no_cpu:
         nthr = args.cpu_threads or host_cores()
         idx = cpu_sample_indices(w)[:args.cpu_sample]

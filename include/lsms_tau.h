@@ -97,7 +97,11 @@ typedef struct {
     int32_t n_inst;      /* number of instances (>= 0)                                 */
     int32_t n_species;   /* number of species in delta (1..8)                          */
     int32_t n_energy;    /* number of energies in energy/delta (>= 1)                  */
-    int32_t max_liz;     /* upper bound on every LIZ size (>= 1); sizes workspace slots */
+    int32_t max_liz;     /* upper bound on every LIZ size (1..1024); sizes workspace slots.
+                            The matrix bound N = kk * max_liz (2 kk * max_liz with spin
+                            canting) is at most 8192 for the FP64 paths and at most 4096
+                            for LSMS_PREC_FP32_IR, tau00_gmres and tau_row_batched (-2
+                            above)                                                      */
     int32_t reserved;
     const int64_t *liz_off;  /* device [n_inst+1]: instance i owns LIZ rows liz_off[i] ..
                                 liz_off[i+1]-1 (non-decreasing, liz_off[0] = 0)       */
@@ -223,6 +227,58 @@ int tau_row_batched(lsms_handle_t h, const lsms_problem *p, double *M, const int
                     const int64_t *row_off, double *tau_row, double *logdet, double *tau00, int32_t *info,
                     void *work, size_t work_bytes, void *stream);
 
+/* Spin canting (paper Sec. 2.1 and 2.2: with canted moments every matrix
+ * carries a spin index and the KKR matrix of a LIZ has rank
+ * 2 N_LIZ (lmax+1)^2).  The paper gives only the rank; the library takes the
+ * usual non-collinear form: site i has a unit moment direction e_i and, in
+ * its own spin frame, the spin-diagonal t-matrix diag(t_up, t_dn) (t_up from
+ * the phase shifts of the spin parallel to the moment); in the global frame
+ *     t_i(L) = tbar_l 1 + dt_l (e_i . sigma),  tbar = (t_up + t_dn)/2,
+ *     dt = (t_up - t_dn)/2,  sigma the Pauli matrices,
+ * and the free propagator does not act on spin.  Row/column of (LIZ site j,
+ * spin s, L): kc j + kk s + L with kc = 2 kk (s = 0: spin along global +z).
+ *     M_jj = 1,  M_ij[(s,L),(s',L')] = -t_i(L)_{s s'} G^{ij}_{LL'}
+ *     tau00 = [M^{-1}]_{00} t_0   (kc x kc, column-major)
+ * With every moment along +z, tau00 is block-diagonal with the two plain
+ * tau00 of the up and down phase shifts. */
+typedef struct {
+    const double *moment;    /* device [liz_off[n_inst]][3]: unit moment direction of each LIZ
+                                site, per LIZ row like lsms_problem.pos (lsms_liz_moments)   */
+    const double *delta_dn;  /* device [n_species][n_energy][lmax+1] complex: phase shifts of
+                                the spin antiparallel to the site's moment (lsms_problem.delta
+                                then holds the parallel spin)                               */
+} lsms_spin;
+
+/* liz_moment[r] = atom_moment[liz_atom[r]] (3 doubles per row) for the rows of
+ * lsms_build_liz (liz_atom its optional output); NaN for an atom index
+ * outside [0, n_atoms).  Errors: -2 n_rows < 0, -3/-4/-6 null, -5 n_atoms < 1. */
+int lsms_liz_moments(lsms_handle_t h, int64_t n_rows, const int32_t *liz_atom, const double *atom_moment,
+                     int32_t n_atoms, double *liz_moment, void *stream);
+
+/* build_kkr with spin canting: instance i is a kc N_LIZ square at M + 2*m_off[i]
+ * doubles (N_i = 2 kk N_LIZ,i <= 8192).  Arguments as build_kkr, spin third
+ * (-3 when NULL or, for a nonempty batch, with a NULL member). */
+int build_kkr_spin(lsms_handle_t h, const lsms_problem *p, const lsms_spin *spin, double *M, const int64_t *m_off,
+                   int32_t *info, void *stream);
+
+/* tau00_batched with spin canting: tau00 [n_inst][kc*kc] complex, column-major
+ * per instance, tau00[i][a + kc*b] = tau00_i(a, b), a = kk s + L.  FP64 only
+ * (another precision or invalid opts: -6); work as tau00_batched (-10 when
+ * too small). */
+int tau00_spin_batched(lsms_handle_t h, const lsms_problem *p, const lsms_spin *spin, double *M,
+                       const int64_t *m_off, const lsms_opts *opts, double *tau00, int32_t *info, void *work,
+                       size_t work_bytes, void *stream);
+
+/* Workspace and fused build + solve (as lsms_workspace_size / tau00_solve:
+ * chunked passes or LSMS_PERSISTENT) with spin canting; FP64 only, no
+ * LSMS_GRAPH (-4 otherwise).  A slot holds one kc N_LIZ square matrix
+ * (298 MB at rank 4320, 729 MB at rank 6750).  tau00_spin_solve returns -8
+ * when work_bytes is too small. */
+int lsms_spin_workspace_size(lsms_handle_t h, const lsms_problem *p, const lsms_spin *spin, const lsms_opts *opts,
+                             int32_t chunk, size_t *bytes);
+int tau00_spin_solve(lsms_handle_t h, const lsms_problem *p, const lsms_spin *spin, const lsms_opts *opts,
+                     double *tau00, int32_t *info, void *work, size_t work_bytes, void *stream);
+
 /* Energy integration along the contour (paper Sec. 2.1, eq. Density: the
  * density of states and the charge are energy integrals, taken by quadrature
  * on a complex contour).  A batch is laid out [site][energy], instance
@@ -252,7 +308,7 @@ int lsms_lloyd_idos(lsms_handle_t h, int32_t n_sites, int32_t n_energy, const do
  * blocks live in a scratch array of the library, 32 MiB per device (room for
  * 256 instances), held from lsms_create until the process ends; the batch is
  * processed in stream-ordered passes of at most 256 instances, so n_inst has
- * no upper limit beyond tau00_batched's own checks (kk * max_liz <= 4096,
+ * no upper limit beyond tau00_batched's own checks (kk * max_liz <= 8192,
  * -2 above).  Panels up to 128 wide (opts->nb, or the tuned width).  The call
  * enqueues kernel launches only (no hipMalloc, hipFree, memset or copy).
  * Every call on one device shares that device's array: calls that overlap in

@@ -33,18 +33,34 @@ hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-int check_problem(const lsms_problem* p) {
+// Largest matrix of the FP64 elimination (leaf registers, kR = 16) and of the
+// precision form, the learned form and the block-row solve (kR = 8).
+constexpr int64_t kMaxN = 8192;
+constexpr int64_t kMaxNSmall = 4096;
+
+int64_t n_max(const lsms_problem* p, int nspin = 1) {
+  return (int64_t)nspin * (p->lmax + 1) * (p->lmax + 1) * p->max_liz;
+}
+
+int check_problem(const lsms_problem* p, int nspin = 1) {
   if (!p) return -2;
   if (p->lmax < 0 || p->lmax > kMaxLmax) return -2;
   if (p->n_inst < 0 || p->n_species < 1 || p->n_species > kMaxSpeciesAbi || p->n_energy < 1) return -2;
   if (p->max_liz < 1 || p->max_liz > 1024) return -2;
-  if ((int64_t)(p->lmax + 1) * (p->lmax + 1) * p->max_liz > 4096) return -2;
+  if (n_max(p, nspin) > kMaxN) return -2;
   if (p->n_inst > 0 && (!p->liz_off || !p->pos || !p->species || !p->energy || !p->e_idx || !p->delta))
     return -2;
   return 0;
 }
 
-lsms_prob_dev to_dev(const lsms_problem* p) {
+// check_problem for the entry points whose kernels hold at most 4096 rows.
+int check_problem_small(const lsms_problem* p) {
+  const int r = check_problem(p);
+  if (r) return r;
+  return n_max(p) > kMaxNSmall ? -2 : 0;
+}
+
+lsms_prob_dev to_dev(const lsms_problem* p, const lsms_spin* sp = nullptr) {
   lsms_prob_dev d;
   d.lmax = p->lmax;
   d.kk = (p->lmax + 1) * (p->lmax + 1);
@@ -58,6 +74,10 @@ lsms_prob_dev to_dev(const lsms_problem* p) {
   d.energy = p->energy;
   d.e_idx = p->e_idx;
   d.delta = p->delta;
+  d.nspin = sp ? 2 : 1;
+  d.kc = d.nspin * d.kk;
+  d.moment = sp ? sp->moment : nullptr;
+  d.delta_dn = sp ? sp->delta_dn : nullptr;
   return d;
 }
 
@@ -74,9 +94,8 @@ int check_opts(const lsms_opts* o) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t slot_elems(const lsms_problem* p) {
-  const size_t kk = (size_t)(p->lmax + 1) * (p->lmax + 1);
-  const size_t n = kk * (size_t)p->max_liz;
+size_t slot_elems(const lsms_problem* p, const lsms_spin* sp = nullptr) {
+  const size_t n = (size_t)n_max(p, sp ? 2 : 1);
   return n * n;
 }
 
@@ -85,10 +104,10 @@ bool mixed(const lsms_opts* o) { return o && o->precision == LSMS_PREC_FP32_IR; 
 // Bytes of one instance slot: the FP64 matrix (256-byte aligned), then the
 // two 64 x 64 blocks of wide panels (FP64 form) or the buffers of the
 // precision form (which include those blocks).
-size_t m_bytes(const lsms_problem* p) { return align256(slot_elems(p) * 16); }
+size_t m_bytes(const lsms_problem* p, const lsms_spin* sp = nullptr) { return align256(slot_elems(p, sp) * 16); }
 
-size_t slot_bytes(const lsms_problem* p, const lsms_opts* o) {
-  return m_bytes(p) + (mixed(o) ? (size_t)lsms_mixed_extra_bytes(to_dev(p)) : (size_t)kLsmsXgBytes);
+size_t slot_bytes(const lsms_problem* p, const lsms_opts* o, const lsms_spin* sp = nullptr) {
+  return m_bytes(p, sp) + (mixed(o) ? (size_t)lsms_mixed_extra_bytes(to_dev(p)) : (size_t)kLsmsXgBytes);
 }
 
 double ir_tol(const lsms_opts* o) { return o->tol > 0.0 ? o->tol : 1e-12; }
@@ -154,9 +173,10 @@ namespace {
 
 int prec_index(const lsms_opts* o) { return mixed(o) ? 1 : 0; }
 
-int32_t panel_width(const lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o) {
+int32_t panel_width(const lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o,
+                    const lsms_spin* sp = nullptr) {
   if (o && o->nb) return o->nb;
-  const int32_t t = h->tuned_nb[prec_index(o)][bucket_of((int64_t)(p->lmax + 1) * (p->lmax + 1) * p->max_liz)];
+  const int32_t t = h->tuned_nb[prec_index(o)][bucket_of(n_max(p, sp ? 2 : 1))];
   return t ? t : 128;
 }
 
@@ -165,26 +185,30 @@ struct PersistLayout {
   size_t order_off, slots_off, slot_stride, total;  // bytes
 };
 
-int persist_layout(const lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o, PersistLayout* L) {
-  const lsms_prob_dev d = to_dev(p);
+int persist_layout(const lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o, PersistLayout* L,
+                   const lsms_spin* sp = nullptr) {
+  const lsms_prob_dev d = to_dev(p, sp);
   const hipError_t e = mixed(o) ? lsms_mixed_persistent_grid(d, h->device, &L->grid)
                                 : lsms_persistent_grid(d, h->device, &L->grid);
   if (e != hipSuccess) return LSMS_EHIP;
+  // no more resident workgroups (and slots) than instances
+  if (L->grid > p->n_inst) L->grid = p->n_inst > 0 ? p->n_inst : 1;
   L->order_off = 256;
   L->slots_off = align256(256 + 4 * (size_t)p->n_inst);
-  L->slot_stride = slot_bytes(p, o);
+  L->slot_stride = slot_bytes(p, o, sp);
   L->total = L->slots_off + (size_t)L->grid * L->slot_stride;
   return 0;
 }
 
-// Enqueue the launches of one tau00_solve call (no graph handling).
+// Enqueue the launches of one tau00_solve call (no graph handling); sp: spin
+// canting (FP64 only), or null.
 int enqueue_solve(lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o, double* tau00, int32_t* info,
-                  void* work, size_t work_bytes, hipStream_t s) {
-  const lsms_prob_dev d = to_dev(p);
-  const int32_t nb = panel_width(h, p, o);
+                  void* work, size_t work_bytes, hipStream_t s, const lsms_spin* sp = nullptr) {
+  const lsms_prob_dev d = to_dev(p, sp);
+  const int32_t nb = panel_width(h, p, o, sp);
   if (o && (o->flags & LSMS_PERSISTENT)) {
     PersistLayout L;
-    if (persist_layout(h, p, o, &L)) return LSMS_EHIP;
+    if (persist_layout(h, p, o, &L, sp)) return LSMS_EHIP;
     if (work_bytes < L.total) return -7;
     char* w = (char*)work;
     int32_t* counter = (int32_t*)w;
@@ -196,12 +220,12 @@ int enqueue_solve(lsms_handle_s* h, const lsms_problem* p, const lsms_opts* o, d
                                                 (int64_t)L.slot_stride, (int64_t)m_bytes(p), L.grid, tau00, info, nb,
                                                 ir_tol(o), ir_steps(o), s)
                  : lsms_launch_persistent(d, h->g[p->lmax], order, counter, (double*)(w + L.slots_off),
-                                          (int64_t)(L.slot_stride / 16), (int64_t)(m_bytes(p) / 16), L.grid,
+                                          (int64_t)(L.slot_stride / 16), (int64_t)(m_bytes(p, sp) / 16), L.grid,
                                           tau00, info, nb, s);
     return e == hipSuccess ? 0 : LSMS_EHIP;
   }
   // chunked: M slots first, then the per-instance extra buffers
-  const size_t mb = m_bytes(p), slot_b = slot_bytes(p, o);
+  const size_t mb = m_bytes(p, sp), slot_b = slot_bytes(p, o, sp);
   if (work_bytes < slot_b) return -7;
   int64_t chunk = (int64_t)(work_bytes / slot_b);
   if (o && o->chunk > 0 && o->chunk < chunk) chunk = o->chunk;
@@ -345,7 +369,7 @@ extern "C" int tau00_batched(lsms_handle_t h, const lsms_problem* p, double* M, 
 
 extern "C" int lsms_row_workspace_size(lsms_handle_t h, const lsms_problem* p, size_t* bytes) {
   if (!h) return -1;
-  int r = check_problem(p);
+  int r = check_problem_small(p);
   if (r) return r;
   if (!bytes) return -3;
   *bytes = (size_t)p->n_inst * (size_t)lsms_row_slot_bytes(to_dev(p));
@@ -356,7 +380,7 @@ extern "C" int tau_row_batched(lsms_handle_t h, const lsms_problem* p, double* M
                                const lsms_opts* opts, const int64_t* row_off, double* tau_row, double* logdet,
                                double* tau00, int32_t* info, void* work, size_t work_bytes, void* stream) {
   if (!h) return -1;
-  int r = check_problem(p);
+  int r = check_problem_small(p);
   if (r) return r;
   if (check_opts(opts) || mixed(opts)) return -5;
   if (p->n_inst == 0) return 0;
@@ -403,6 +427,105 @@ extern "C" int lsms_lloyd_idos(lsms_handle_t h, int32_t n_sites, int32_t n_energ
   return lsms_launch_lloyd_idos(n_sites, n_energy, logdet, idos, (hipStream_t)stream) == hipSuccess ? 0 : LSMS_EHIP;
 }
 
+// ---------------------------------------------------------- spin canting
+int check_spin(const lsms_problem* p, const lsms_spin* sp) {
+  if (!sp) return -3;
+  if (p->n_inst > 0 && (!sp->moment || !sp->delta_dn)) return -3;
+  return 0;
+}
+
+extern "C" int lsms_liz_moments(lsms_handle_t h, int64_t n_rows, const int32_t* liz_atom,
+                                const double* atom_moment, int32_t n_atoms, double* liz_moment, void* stream) {
+  if (!h) return -1;
+  if (n_rows < 0) return -2;
+  if (n_rows == 0) return 0;
+  if (!liz_atom) return -3;
+  if (!atom_moment) return -4;
+  if (n_atoms < 1) return -5;
+  if (!liz_moment) return -6;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_gather3(n_rows, liz_atom, atom_moment, n_atoms, liz_moment, (hipStream_t)stream) == hipSuccess
+             ? 0
+             : LSMS_EHIP;
+}
+
+extern "C" int build_kkr_spin(lsms_handle_t h, const lsms_problem* p, const lsms_spin* spin, double* M,
+                              const int64_t* m_off, int32_t* info, void* stream) {
+  if (!h) return -1;
+  int r = check_problem(p, 2);
+  if (r) return r;
+  if ((r = check_spin(p, spin))) return r;
+  if (p->n_inst == 0) return 0;
+  if (!M) return -4;
+  if (!m_off) return -5;
+  if (!info) return -6;
+  (void)hipSetDevice(h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const lsms_prob_dev d = to_dev(p, spin);
+  if (fill_i32(info, 0, p->n_inst, s) != hipSuccess) return LSMS_EHIP;
+  if (lsms_launch_build(d, h->g[p->lmax], 0, p->n_inst, M, m_off, 0, info, s) != hipSuccess) return LSMS_EHIP;
+  return 0;
+}
+
+extern "C" int tau00_spin_batched(lsms_handle_t h, const lsms_problem* p, const lsms_spin* spin, double* M,
+                                  const int64_t* m_off, const lsms_opts* opts, double* tau00, int32_t* info,
+                                  void* work, size_t work_bytes, void* stream) {
+  if (!h) return -1;
+  int r = check_problem(p, 2);
+  if (r) return r;
+  if ((r = check_spin(p, spin))) return r;
+  if (check_opts(opts) || mixed(opts)) return -6;
+  if (p->n_inst == 0) return 0;
+  if (!M) return -4;
+  if (!m_off) return -5;
+  if (!tau00) return -7;
+  if (!info) return -8;
+  if (work && work_bytes < (size_t)p->n_inst * kLsmsXgBytes) return -10;
+  (void)hipSetDevice(h->device);
+  const lsms_prob_dev d = to_dev(p, spin);
+  if (lsms_launch_lu_fp64(d, 0, p->n_inst, M, m_off, 0, (double*)work, work ? kLsmsXgBytes / 16 : 0, tau00, info,
+                          0, panel_width(h, p, opts, spin), (hipStream_t)stream) != hipSuccess)
+    return LSMS_EHIP;
+  return 0;
+}
+
+extern "C" int lsms_spin_workspace_size(lsms_handle_t h, const lsms_problem* p, const lsms_spin* spin,
+                                        const lsms_opts* opts, int32_t chunk, size_t* bytes) {
+  if (!h) return -1;
+  int r = check_problem(p, 2);
+  if (r) return r;
+  if ((r = check_spin(p, spin))) return r;
+  if (check_opts(opts) || mixed(opts) || (opts && (opts->flags & LSMS_GRAPH))) return -4;
+  if (!bytes) return -6;
+  if (opts && (opts->flags & LSMS_PERSISTENT)) {
+    (void)hipSetDevice(h->device);
+    PersistLayout L;
+    if (persist_layout(h, p, opts, &L, spin)) return LSMS_EHIP;
+    *bytes = L.total;
+    return 0;
+  }
+  if (chunk < 1) return -5;
+  *bytes = (size_t)chunk * slot_bytes(p, opts, spin);
+  return 0;
+}
+
+extern "C" int tau00_spin_solve(lsms_handle_t h, const lsms_problem* p, const lsms_spin* spin,
+                                const lsms_opts* opts, double* tau00, int32_t* info, void* work, size_t work_bytes,
+                                void* stream) {
+  if (!h) return -1;
+  int r = check_problem(p, 2);
+  if (r) return r;
+  if ((r = check_spin(p, spin))) return r;
+  if (check_opts(opts) || mixed(opts) || (opts && (opts->flags & LSMS_GRAPH))) return -4;
+  if (p->n_inst == 0) return 0;
+  if (!tau00) return -5;
+  if (!info) return -6;
+  if (!work) return -7;
+  (void)hipSetDevice(h->device);
+  const int er = enqueue_solve(h, p, opts, tau00, info, work, work_bytes, (hipStream_t)stream, spin);
+  return er == -7 ? -8 : er;
+}
+
 // The allocation-free variant of tau00_batched: the same kernels, the
 // wide-panel blocks in the handle device's scratch array, the batch in
 // passes of kNoAllocSlots instances (stream-ordered, so each pass reuses the
@@ -438,6 +561,7 @@ extern "C" int lsms_workspace_size(lsms_handle_t h, const lsms_problem* p, const
   int r = check_problem(p);
   if (r) return r;
   if (check_opts(opts)) return -3;
+  if (mixed(opts) && n_max(p) > kMaxNSmall) return -2;
   if (!bytes) return -5;
   if (opts && (opts->flags & LSMS_PERSISTENT)) {
     (void)hipSetDevice(h->device);
@@ -457,6 +581,7 @@ extern "C" int tau00_solve(lsms_handle_t h, const lsms_problem* p, const lsms_op
   int r = check_problem(p);
   if (r) return r;
   if (check_opts(opts)) return -3;
+  if (mixed(opts) && n_max(p) > kMaxNSmall) return -2;
   if (p->n_inst == 0) return 0;
   if (!tau00) return -4;
   if (!info) return -5;
@@ -545,6 +670,7 @@ extern "C" int lsms_autotune(lsms_handle_t h, const lsms_problem* p, const lsms_
   int r = check_problem(p);
   if (r) return r;
   if (check_opts(opts)) return -3;
+  if (mixed(opts) && n_max(p) > kMaxNSmall) return -2;
   if (!best_nb) return -9;
   (void)hipSetDevice(h->device);
   hipStream_t s = (hipStream_t)stream;
@@ -640,6 +766,7 @@ struct GmresLayout {
 int gmres_layout(const lsms_handle_s* h, const lsms_problem* p, int restart, GmresLayout* L) {
   const lsms_prob_dev d = to_dev(p);
   if (lsms_gmres_grid(d, h->device, &L->grid) != hipSuccess) return LSMS_EHIP;
+  if (L->grid > p->n_inst) L->grid = p->n_inst > 0 ? p->n_inst : 1;
   L->order_off = 256;
   L->slots_off = align256(256 + 4 * (size_t)p->n_inst);
   L->slot_stride = m_bytes(p) + (size_t)lsms_gmres_extra_bytes(d, restart);
@@ -651,7 +778,7 @@ int gmres_layout(const lsms_handle_s* h, const lsms_problem* p, int restart, Gmr
 
 extern "C" int lsms_gmres_workspace_size(lsms_handle_t h, const lsms_problem* p, int32_t restart, size_t* bytes) {
   if (!h) return -1;
-  int r = check_problem(p);
+  int r = check_problem_small(p);
   if (r) return r;
   if (p->lmax != 3) return -2;
   if (restart < 1 || restart > lsms_gmres_max_restart()) return -3;
@@ -667,7 +794,7 @@ extern "C" int tau00_gmres(lsms_handle_t h, const lsms_problem* p, const double*
                            int32_t max_cycles, double tol, double* tau00, int32_t* info, int32_t* steps, void* work,
                            size_t work_bytes, void* stream) {
   if (!h) return -1;
-  int r = check_problem(p);
+  int r = check_problem_small(p);
   if (r) return r;
   if (p->lmax != 3) return -2;
   if (restart < 1 || restart > lsms_gmres_max_restart()) return -4;

@@ -28,6 +28,8 @@ struct BuildSmem {
   double nlm[kBMaxL2 + 1][kBMaxL2 + 1];  // sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!)
   double rcp[kBMaxL2 + 2];               // 1/k
   zd t[kBMaxSpecies][kBMaxLm];
+  zd tdn[kBMaxSpecies][kBMaxLm];  // spin canting: the spin antiparallel to the moment
+  double mom[kBuildChunk][3];      // spin canting: moment of each row block of the chunk
   double coef[kBMaxNnz];
   int32_t rp[kBMaxKK * kBMaxKK + 1];
   int16_t lpp[kBMaxNnz];
@@ -104,6 +106,10 @@ __device__ void build_setup(const lsms_prob_dev& p, const lsms_gaunt_dev& g, int
     const int s = tid / (lmax + 1), l = tid % (lmax + 1);
     const zd d = reinterpret_cast<const zd*>(p.delta)[((int64_t)s * p.n_energy + e) * (lmax + 1) + l];
     sb.t[s][l] = tmat_from_delta(d, kap);
+    if (p.nspin == 2) {
+      const zd dd = reinterpret_cast<const zd*>(p.delta_dn)[((int64_t)s * p.n_energy + e) * (lmax + 1) + l];
+      sb.tdn[s][l] = tmat_from_delta(dd, kap);
+    }
   }
   for (int q = tid; q <= kkp; q += kNT) sb.rp[q] = g.row_ptr[q];
   for (int q = tid; q < g.nnz; q += kNT) {
@@ -126,6 +132,65 @@ __device__ void build_setup(const lsms_prob_dev& p, const lsms_gaunt_dev& g, int
   __syncthreads();
 }
 
+// Spin canting: the 2 kk columns of site j.  Entry (s, L; s', L') of row
+// block i is -t_i(L)_{s s'} G^{ij}_{LL'} (t_i the global-frame t of site i,
+// spin_t), at row kc i + kk s + L and column kc j + kk s' + L'; the diagonal
+// block is the identity.  Sums as build_column_body; a thread takes one L
+// and two row blocks.
+template <int kNT>
+__device__ __forceinline__ void build_spin_phase_b(const lsms_prob_dev& p, int j, int ib, int nb, int64_t N,
+                                                   zd pref, zd* __restrict__ M, const BuildSmem& sb) {
+  const int tid = threadIdx.x;
+  const int kk = p.kk, kc = p.kc;
+  const int npair = (nb + 1) >> 1;
+  for (int t = tid; t < npair * kk; t += kNT) {
+    const int ip = t / kk;
+    const int L = t - ip * kk;
+    const int i0 = 2 * ip, i1 = min(2 * ip + 1, nb - 1);
+    const bool two = 2 * ip + 1 < nb;
+    const int iw0 = ib + i0, iw1 = ib + i1;
+    const int l = l_of(L);
+    zd ta[4], tb[4];
+    spin_t(sb.t[sb.spec[i0]][l], sb.tdn[sb.spec[i0]][l], sb.mom[i0][0], sb.mom[i0][1], sb.mom[i0][2], ta);
+    spin_t(sb.t[sb.spec[i1]][l], sb.tdn[sb.spec[i1]][l], sb.mom[i1][0], sb.mom[i1][1], sb.mom[i1][2], tb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ta[q] = zmul(ta[q], pref);
+      tb[q] = zmul(tb[q], pref);
+    }
+    const int64_t r0 = (int64_t)kc * iw0 + L, r1 = (int64_t)kc * iw1 + L;
+    for (int Lp = 0; Lp < kk; ++Lp) {
+      double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
+      const int pidx = L + kk * Lp;
+      const int e0 = sb.rp[pidx], e1 = sb.rp[pidx + 1];
+      for (int k = e0; k < e1; ++k) {
+        const double c = sb.coef[k];
+        const int lp = sb.lpp[k], lo = sb.lof[k];
+        const double cy0 = c * sb.Y[i0][lp], cy1 = c * sb.Y[i1][lp];
+        const zd h0 = sb.h[i0][lo], h1 = sb.h[i1][lo];
+        sr0 += cy0 * h0.x;
+        si0 += cy0 * h0.y;
+        sr1 += cy1 * h1.x;
+        si1 += cy1 * h1.y;
+      }
+      const zd g0 = zmake(sr0, si0), g1 = zmake(sr1, si1);
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+          const int64_t col = (int64_t)kc * j + kk * sp + Lp;
+          const zd one = zmake((s == sp && L == Lp) ? 1.0 : 0.0, 0.0);
+          const zd v0 = iw0 == j ? one : zmul(zmake(-ta[2 * s + sp].x, -ta[2 * s + sp].y), g0);
+          M[col * N + r0 + kk * s] = v0;
+          if (two) {
+            const zd v1 = iw1 == j ? one : zmul(zmake(-tb[2 * s + sp].x, -tb[2 * s + sp].y), g1);
+            M[col * N + r1 + kk * s] = v1;
+          }
+        }
+    }
+  }
+}
+
 // Block column j of M, in chunks of kBuildChunk LIZ row blocks.  Phase A:
 // for each row block i of the chunk, 2 lmax + 2 tasks: one per order
 // m = 0 .. 2 lmax of Y_L''(R_ij) and one for the Hankel functions
@@ -141,7 +206,7 @@ __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int in
   const int64_t a = p.liz_off[inst];
   const int nliz = (int)(p.liz_off[inst + 1] - a);
   const int kk = p.kk, l2 = 2 * p.lmax;
-  const int64_t N = (int64_t)kk * nliz;
+  const int64_t N = (int64_t)p.kc * nliz;
   const zd kap = zsqrt(reinterpret_cast<const zd*>(p.energy)[p.e_idx[inst]]);
   const double* rel = p.pos + 3 * a;
   const int32_t* spec = p.species + a;
@@ -158,6 +223,12 @@ __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int in
         const int sp = spec[iw];
         if (sp < 0 || sp >= p.n_species) sb.bad_species = 1;
         sb.spec[il] = (sp >= 0 && sp < p.n_species) ? sp : 0;
+        if (p.nspin == 2) {
+          const double* e = p.moment + 3 * (a + iw);
+          sb.mom[il][0] = e[0];
+          sb.mom[il][1] = e[1];
+          sb.mom[il][2] = e[2];
+        }
       }
       if (iw != j) {
         const double Rx = rel[3 * iw] - rjx, Ry = rel[3 * iw + 1] - rjy, Rz = rel[3 * iw + 2] - rjz;
@@ -173,6 +244,11 @@ __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int in
       }
     }
     __syncthreads();
+    if (p.nspin == 2) {
+      build_spin_phase_b<kNT>(p, j, ib, nb, N, pref, M, sb);
+      __syncthreads();
+      continue;
+    }
     // a thread takes one L and two row blocks 2 ip, 2 ip + 1 of the chunk,
     // which share the Gaunt list of every (L, L')
     const int npair = (nb + 1) >> 1;

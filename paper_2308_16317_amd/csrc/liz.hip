@@ -183,6 +183,30 @@ __global__ __launch_bounds__(kLizThreads) void liz_fill_kernel(
 
 }  // namespace
 
+namespace {
+
+// out[r] = src[idx[r]] (three doubles per row); NaN for an index outside
+// [0, n_src).
+__global__ __launch_bounds__(256) void gather3_kernel(int64_t n, const int32_t* __restrict__ idx,
+                                                      const double* __restrict__ src, int32_t n_src,
+                                                      double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  const int32_t a = idx[r];
+  const bool ok = a >= 0 && a < n_src;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out[3 * r + k] = ok ? src[3 * (int64_t)a + k] : (double)NAN;
+}
+
+}  // namespace
+
+hipError_t lsms_launch_gather3(int64_t n, const int32_t* idx, const double* src, int32_t n_src, double* out,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather3_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, idx, src, n_src, out);
+  return hipGetLastError();
+}
+
 hipError_t lsms_launch_liz(const double* atom_pos, const int32_t* atom_species, int32_t n_atoms, double bx,
                            double by, double bz, const int32_t* centre, const double* rc, int32_t n_inst,
                            int32_t max_liz, int32_t* liz_n, int64_t* liz_off, double* liz_pos,

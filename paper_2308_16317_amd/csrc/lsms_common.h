@@ -102,7 +102,29 @@ struct lsms_prob_dev {
   const double* energy;  // complex
   const int32_t* e_idx;
   const double* delta;   // complex [n_species][n_energy][lmax+1]
+  // Spin canting: nspin = 2 doubles every site block (kc = 2 kk rows and
+  // columns per LIZ site, index kk s + L within a site); delta then holds the
+  // phase shifts of the spin parallel to a site's moment and delta_dn those
+  // of the antiparallel spin.  nspin = 1: kc = kk, moment and delta_dn null.
+  int32_t nspin, kc;
+  const double* moment;    // [liz rows][3] unit moment directions
+  const double* delta_dn;  // complex, layout of delta
 };
+
+// Global-frame t of one channel of a site with moment e (spin-diagonal
+// diag(tu, td) in the site's own frame, rotated by the spin-1/2 rotation
+// that takes z to e): t = tbar 1 + dt (e . sigma), tbar = (tu + td)/2,
+// dt = (tu - td)/2; t2[2 s + s'] = t_{s s'}.
+namespace lsms {
+__device__ __forceinline__ void spin_t(zd tu, zd td, double ex, double ey, double ez, zd* t2) {
+  const zd tb = zmake(0.5 * (tu.x + td.x), 0.5 * (tu.y + td.y));
+  const zd dt = zmake(0.5 * (tu.x - td.x), 0.5 * (tu.y - td.y));
+  t2[0] = zmake(tb.x + dt.x * ez, tb.y + dt.y * ez);
+  t2[1] = zmul(dt, zmake(ex, -ey));
+  t2[2] = zmul(dt, zmake(ex, ey));
+  t2[3] = zmake(tb.x - dt.x * ez, tb.y - dt.y * ez);
+}
+}  // namespace lsms
 
 hipError_t lsms_launch_liz(const double* atom_pos, const int32_t* atom_species, int32_t n_atoms,
                            double bx, double by, double bz, const int32_t* centre, const double* rc,
@@ -139,6 +161,10 @@ hipError_t lsms_launch_tau_row(const lsms_prob_dev& p, int32_t i0, int32_t n, do
                                unsigned char* work, const int64_t* row_off, double* row, double* logdet,
                                double* tau00, int32_t* info, int32_t nb, hipStream_t s);
 hipError_t lsms_launch_lpt_order(const lsms_prob_dev& p, int32_t* order, hipStream_t s);
+
+// out[r][0..2] = src[idx[r]][0..2] (liz.hip): per-row moments of the LIZs.
+hipError_t lsms_launch_gather3(int64_t n, const int32_t* idx, const double* src, int32_t n_src, double* out,
+                               hipStream_t s);
 
 // Contour quadrature and Lloyd's integrated density of states (contour.hip).
 hipError_t lsms_launch_contour_sum(int32_t n_sites, int32_t n_energy, int32_t m, const double* w, const double* v,

@@ -31,6 +31,7 @@ constexpr int kPanelMax = 128;  // maximum panel width (two triangular blocks)
 template <typename R>
 constexpr int kSWp = sizeof(R) == 4 ? 128 : kSW;
 constexpr int kMaxKK = 25;
+constexpr int kMaxKC = 2 * kMaxKK;  // rows per LIZ site with spin canting
 constexpr int kMaxWL = 8;
 
 template <typename R>
@@ -70,7 +71,7 @@ struct LuSmem {
   C cand[2][kLuWaves][kMaxWL];  // each wave's pivot candidate row (two buffers)
   R candv[2][kLuWaves];         // its magnitude |Re| + |Im|
   int candi[2][kLuWaves];       // its row
-  zd tz[kMaxKK];
+  zd tz[kMaxKC];
   zd pinv;
   int ipiv[kPanelMax];
   int lrow[2 * kMaxWL];  // rows touched by a leaf's interchanges

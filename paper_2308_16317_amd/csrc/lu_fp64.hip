@@ -66,6 +66,12 @@ typedef LuSmem<double> LuSmemD;
 // ----------------------------------------------------------------------
 constexpr double kPi = 3.14159265358979323846;
 
+// The Gauss-Jordan workspace [S_A | 1] (kc x 2 kc, row stride 2 kMaxKC) at
+// the start of sh.X, whose 128 KB with sh.U hold it for kc up to 50.
+typedef zd GjRow[2 * kMaxKC];
+static_assert(sizeof(GjRow) * kMaxKC <= sizeof(LuSmemD::X) + sizeof(LuSmemD::U), "Gauss-Jordan workspace");
+__device__ __forceinline__ GjRow* gj_view(LuSmemD& sh) { return reinterpret_cast<GjRow*>(&sh.X[0][0]); }
+
 struct RowOut {
   zd* z;          // N x kp workspace, internal rows (needed for row)
   int32_t* ipiv;  // N workspace (needed for logdet)
@@ -206,7 +212,7 @@ __device__ __noinline__ void back_solve_rows(const Mat<zd>& Ain, zd* zin, int kp
 __device__ __noinline__ void row_output(const lsms_prob_dev& p, int inst, const Mat<zd>& Ain, const RowOut& ro,
                                         int info0, LuSmemD& sh) {
   const Mat<zd> A = Ain;
-  const int tid = threadIdx.x, kk = p.kk, N = (int)A.N, Nd = A.Nd, kp = ro.kp;
+  const int tid = threadIdx.x, kk = A.kk, N = (int)A.N, Nd = A.Nd, kp = ro.kp;
   LSMS_GLOBAL zd* z = glb(ro.z);
   LSMS_GLOBAL zd* out = glb(ro.row);
   if (info0 != 0) {
@@ -214,7 +220,7 @@ __device__ __noinline__ void row_output(const lsms_prob_dev& p, int inst, const 
     __syncthreads();
     return;
   }
-  const zd(*G)[2 * kMaxKK] = reinterpret_cast<const zd(*)[2 * kMaxKK]>(&sh.U[0][0]);
+  const GjRow* G = gj_view(sh);
   for (int q = tid; q < kk * kp; q += kThreads) {
     const int r = q / kp, L = q % kp;
     z[(int64_t)(Nd + r) * kp + L] = L < kk ? G[r][kk + L] : zmake(0.0, 0.0);
@@ -251,15 +257,15 @@ template <int kR, int kWL>
 __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, double* __restrict__ tau00,
                             int32_t* __restrict__ info, int nb, LuSmemD& sh, const RowOut ro = RowOut{}) {
   const int tid = threadIdx.x;
-  const int kk = p.kk;
+  const int kk = p.kk, kc = p.kc;  // kc = kk, or 2 kk with spin canting
   const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
-  const int N = kk * nliz, Nd = N - kk;
-  zd* tout = reinterpret_cast<zd*>(tau00) + (int64_t)inst * kk * kk;
+  const int N = kc * nliz, Nd = N - kc;
+  zd* tout = reinterpret_cast<zd*>(tau00) + (int64_t)inst * kc * kc;
   Mat<zd> A;
   A.base = glb(base);
   A.N = N;
   A.Nd = Nd;
-  A.kk = kk;
+  A.kk = kc;
   if (tid == 0) {
     sh.info = 0;
     sh.bad = 0;
@@ -279,18 +285,18 @@ __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, 
     block_sum(ld_re, ld_im, ld_sw, sh);
   }
 
-  // Gauss-Jordan inverse of S_A (kk x kk, physical rows/cols 0..kk-1) in sh.U
-  zd(*G)[2 * kMaxKK] = reinterpret_cast<zd(*)[2 * kMaxKK]>(&sh.U[0][0]);
-  for (int q = tid; q < kk * 2 * kk; q += kThreads) {
-    const int r = q / (2 * kk), col = q % (2 * kk);
-    G[r][col] = col < kk ? A.base[(int64_t)r * N + col] : zmake(col - kk == r ? 1.0 : 0.0, 0.0);
+  // Gauss-Jordan inverse of S_A (kc x kc, physical rows/cols 0..kc-1)
+  GjRow* G = gj_view(sh);
+  for (int q = tid; q < kc * 2 * kc; q += kThreads) {
+    const int r = q / (2 * kc), col = q % (2 * kc);
+    G[r][col] = col < kc ? A.base[(int64_t)r * N + col] : zmake(col - kc == r ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
-  for (int k = 0; k < kk; ++k) {
+  for (int k = 0; k < kc; ++k) {
     if (tid == 0) {
       int pr = k;
       double best = zcabs1(G[k][k]);
-      for (int r = k + 1; r < kk; ++r) {
+      for (int r = k + 1; r < kc; ++r) {
         const double v = zcabs1(G[r][k]);
         if (v > best) {
           best = v;
@@ -302,7 +308,7 @@ __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, 
     }
     __syncthreads();
     const int pr = sh.gj_piv;
-    if (pr != k && tid < 2 * kk) {
+    if (pr != k && tid < 2 * kc) {
       const zd t = G[k][tid];
       G[k][tid] = G[pr][tid];
       G[pr][tid] = t;
@@ -318,24 +324,38 @@ __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, 
       }
     }
     __syncthreads();
-    if (tid < 2 * kk) G[k][tid] = zmul(G[k][tid], sh.pinv);
-    if (tid < kk) sh.tz[tid] = G[tid][k];  // elimination factors (row k unused)
+    if (tid < 2 * kc) G[k][tid] = zmul(G[k][tid], sh.pinv);
+    if (tid < kc) sh.tz[tid] = G[tid][k];  // elimination factors (row k unused)
     __syncthreads();
-    for (int q = tid; q < kk * 2 * kk; q += kThreads) {
-      const int r = q / (2 * kk), col = q % (2 * kk);
+    for (int q = tid; q < kc * 2 * kc; q += kThreads) {
+      const int r = q / (2 * kc), col = q % (2 * kc);
       if (r != k) G[r][col] = zfms(G[r][col], sh.tz[r], G[k][col]);
     }
     __syncthreads();
   }
-  // tau00(L, L') = [M^{-1}]_{00}(L, L') t0_{l(L')} = S_A^{-1}(L', L) t0_{l(L')}
+  // [M^{-1}]_{00}(a, b) = S_A^{-1}(b, a) = G[b][kc + a].  tau00 = [M^{-1}]_{00} t0:
+  // without spin tau00(L, L') = G[L'][kk + L] t0_{l(L')}; with spin (a = kk s + L,
+  // b' = kk s' + L') tau00(a, b') = sum_s'' G[kk s'' + L'][kc + a] t0(L')_{s'' s'}.
   const int e = p.e_idx[inst];
   const zd kap = zsqrt(reinterpret_cast<const zd*>(p.energy)[e]);
-  const int s0 = min(max(p.species[p.liz_off[inst]], 0), p.n_species - 1);
-  const zd* dl = reinterpret_cast<const zd*>(p.delta) + ((int64_t)s0 * p.n_energy + e) * (p.lmax + 1);
+  const int64_t r0 = p.liz_off[inst];
+  const int s0 = min(max(p.species[r0], 0), p.n_species - 1);
+  const int64_t doff = ((int64_t)s0 * p.n_energy + e) * (p.lmax + 1);
+  const zd* dl = reinterpret_cast<const zd*>(p.delta) + doff;
   const int info0 = sh.info;
-  for (int q = tid; q < kk * kk; q += kThreads) {
-    const int L = q % kk, Lp = q / kk;
-    zd v = zmul(G[Lp][kk + L], tmat_from_delta(dl[l_of(Lp)], kap));
+  for (int q = tid; q < kc * kc; q += kThreads) {
+    const int a = q % kc, bp = q / kc;
+    zd v;
+    if (p.nspin == 2) {
+      const int sp = bp / kk, Lp = bp - sp * kk;
+      const zd* dd = reinterpret_cast<const zd*>(p.delta_dn) + doff;
+      const double* m0 = p.moment + 3 * r0;
+      zd t2[4];
+      spin_t(tmat_from_delta(dl[l_of(Lp)], kap), tmat_from_delta(dd[l_of(Lp)], kap), m0[0], m0[1], m0[2], t2);
+      v = zadd(zmul(G[Lp][kc + a], t2[sp]), zmul(G[kk + Lp][kc + a], t2[2 + sp]));
+    } else {
+      v = zmul(G[bp][kk + a], tmat_from_delta(dl[l_of(bp)], kap));
+    }
     if (info0 != 0) v = zmake((double)NAN, (double)NAN);
     if (!zfinite(v)) sh.bad = 1;
     tout[q] = v;
@@ -364,12 +384,12 @@ template <int kR>
 __device__ __forceinline__ bool instance_invalid(const lsms_prob_dev& p, int inst) {
   const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
   const int e = p.e_idx[inst];
-  return nliz < 1 || nliz > p.max_liz || e < 0 || e >= p.n_energy || p.kk * nliz > kThreads * kR;
+  return nliz < 1 || nliz > p.max_liz || e < 0 || e >= p.n_energy || p.kc * nliz > kThreads * kR;
 }
 
 __device__ __forceinline__ void fill_nan(const lsms_prob_dev& p, int inst, double* tau00) {
-  zd* tout = reinterpret_cast<zd*>(tau00) + (int64_t)inst * p.kk * p.kk;
-  for (int q = threadIdx.x; q < p.kk * p.kk; q += kThreads) tout[q] = zmake((double)NAN, (double)NAN);
+  zd* tout = reinterpret_cast<zd*>(tau00) + (int64_t)inst * p.kc * p.kc;
+  for (int q = threadIdx.x; q < p.kc * p.kc; q += kThreads) tout[q] = zmake((double)NAN, (double)NAN);
 }
 
 template <int kR, int kWL>
@@ -426,7 +446,7 @@ __global__ __launch_bounds__(kThreads) void tau_row_fp64_kernel(
     return;
   }
   unsigned char* ws = work + (int64_t)(inst - i0) * wslot;
-  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  const int64_t nmax = (int64_t)p.kc * p.max_liz;
   RowOut ro;
   ro.z = reinterpret_cast<zd*>(ws + row_z_off());
   ro.ipiv = reinterpret_cast<int32_t*>(ws + row_ipiv_off(nmax, p.kk));
@@ -1089,7 +1109,7 @@ __global__ __launch_bounds__(kThreads) void tau00_mixed_kernel(lsms_prob_dev p, 
     return;
   }
   const int kp = p.kk > 16 ? 32 : 16;
-  const MixedBufs b = mixed_bufs(extra + (int64_t)blockIdx.x * xslot, (int64_t)p.kk * p.max_liz, kp);
+  const MixedBufs b = mixed_bufs(extra + (int64_t)blockIdx.x * xslot, (int64_t)p.kc * p.max_liz, kp);
   mixed_instance<kR, kWL>(p, inst, reinterpret_cast<zd*>(Mb) + (int64_t)blockIdx.x * slot, b, tau00, info, nb,
                           tol, max_refine, false, smem_raw);
 }
@@ -1107,7 +1127,7 @@ __global__ __launch_bounds__(kThreads) void tau00_mixed_persistent_kernel(
   unsigned char* base = work + (int64_t)blockIdx.x * slot_bytes;
   zd* M = reinterpret_cast<zd*>(base);
   const int kp = p.kk > 16 ? 32 : 16;
-  const MixedBufs b = mixed_bufs(base + m_bytes, (int64_t)p.kk * p.max_liz, kp);
+  const MixedBufs b = mixed_bufs(base + m_bytes, (int64_t)p.kc * p.max_liz, kp);
   __syncthreads();
   int k = pop_instance(counter, &next);
   while (k < n) {
@@ -1578,7 +1598,7 @@ __global__ __launch_bounds__(kThreads) void tau00_gmres_persistent_kernel(
   unsigned char* base = work + (int64_t)blockIdx.x * slot_bytes;
   zd* M = reinterpret_cast<zd*>(base);
   zd* xg = reinterpret_cast<zd*>(base + m_bytes);
-  const GmresBufs bufs = gmres_bufs(base + m_bytes, (int64_t)p.kk * p.max_liz, m);
+  const GmresBufs bufs = gmres_bufs(base + m_bytes, (int64_t)p.kc * p.max_liz, m);
   __syncthreads();
   int k = pop_instance(counter, &next);
   while (k < n) {
@@ -1714,25 +1734,28 @@ __global__ __launch_bounds__(1024) void lpt_order_kernel(const int64_t* __restri
 
 }  // namespace
 
-// Leaf rows per thread kR bounds N <= 512 kR: kR = 5 covers N <= 2560 and
-// kR = 8 covers N <= 4096; leaves are 4 columns wide.
+// Leaf rows per thread kR bounds N <= 512 kR: kR = 5 covers N <= 2560 (leaves
+// 8 columns wide), kR = 8 covers N <= 4096 (4 wide) and, for the FP64 path
+// only, kR = 16 covers N <= 8192 (2 wide: the spin-canted ranks 4320 and 6750).
 hipError_t lsms_launch_lu_fp64(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, const int64_t* m_off,
                                int64_t slot, double* xgb, int64_t xstride, double* tau00, int32_t* info,
                                int keep_info, int32_t nb, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  const int64_t nmax = (int64_t)p.kc * p.max_liz;
   if (nmax <= kThreads * 5)
     return launch<5, 8>(p, i0, n, M, m_off, slot, xgb, xstride, tau00, info, keep_info, nb, s);
-  return launch<8, 4>(p, i0, n, M, m_off, slot, xgb, xstride, tau00, info, keep_info, nb, s);
+  if (nmax <= kThreads * 8)
+    return launch<8, 4>(p, i0, n, M, m_off, slot, xgb, xstride, tau00, info, keep_info, nb, s);
+  return launch<16, 2>(p, i0, n, M, m_off, slot, xgb, xstride, tau00, info, keep_info, nb, s);
 }
 
-int64_t lsms_row_slot_bytes(const lsms_prob_dev& p) { return row_slot_bytes((int64_t)p.kk * p.max_liz, p.kk); }
+int64_t lsms_row_slot_bytes(const lsms_prob_dev& p) { return row_slot_bytes((int64_t)p.kc * p.max_liz, p.kk); }
 
 hipError_t lsms_launch_tau_row(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, const int64_t* m_off,
                                unsigned char* work, const int64_t* row_off, double* row, double* logdet,
                                double* tau00, int32_t* info, int32_t nb, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  const int64_t nmax = (int64_t)p.kc * p.max_liz;
   const int64_t wslot = row_slot_bytes(nmax, p.kk);
   const size_t smem = sizeof(LuSmemD);
   if (nmax <= kThreads * 5)
@@ -1759,11 +1782,13 @@ hipError_t lsms_persistent_grid(const lsms_prob_dev& p, int device, int* grid) {
   if (e != hipSuccess) return e;
   const size_t smem = sizeof(LuSmemD) > sizeof(BuildSmem) ? sizeof(LuSmemD) : sizeof(BuildSmem);
   int per_cu = 0;
-  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  const int64_t nmax = (int64_t)p.kc * p.max_liz;
   if (nmax <= kThreads * 5)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_persistent_kernel<5, 8>, kThreads, smem);
-  else
+  else if (nmax <= kThreads * 8)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_persistent_kernel<8, 4>, kThreads, smem);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_persistent_kernel<16, 2>, kThreads, smem);
   if (e != hipSuccess) return e;
   *grid = cus * (per_cu > 0 ? per_cu : 1);
   return hipSuccess;
@@ -1773,10 +1798,12 @@ hipError_t lsms_launch_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev& 
                                   int32_t* counter, double* work, int64_t slot, int64_t xoff, int grid,
                                   double* tau00, int32_t* info, int32_t nb, hipStream_t s) {
   if (p.n_inst <= 0) return hipSuccess;
-  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  const int64_t nmax = (int64_t)p.kc * p.max_liz;
   if (nmax <= kThreads * 5)
     return launch_persistent<5, 8>(p, g, order, p.n_inst, counter, work, slot, xoff, grid, tau00, info, nb, s);
-  return launch_persistent<8, 4>(p, g, order, p.n_inst, counter, work, slot, xoff, grid, tau00, info, nb, s);
+  if (nmax <= kThreads * 8)
+    return launch_persistent<8, 4>(p, g, order, p.n_inst, counter, work, slot, xoff, grid, tau00, info, nb, s);
+  return launch_persistent<16, 2>(p, g, order, p.n_inst, counter, work, slot, xoff, grid, tau00, info, nb, s);
 }
 
 // Dynamic LDS limits of every elimination kernel; called once per device
@@ -1802,19 +1829,21 @@ hipError_t lsms_prepare_kernels() {
   if ((e = hipFuncSetAttribute((const void*)lu_schur_fp64_kernel<8, 4>, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)tau_row_fp64_kernel<5, 8>, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)tau_row_fp64_kernel<8, 4>, attr, a)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)lu_schur_fp64_kernel<16, 2>, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)tau00_persistent_kernel<5, 8>, attr, b)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)tau00_persistent_kernel<16, 2>, attr, b)) != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)tau00_persistent_kernel<8, 4>, attr, b);
 }
 
 int64_t lsms_mixed_extra_bytes(const lsms_prob_dev& p) {
-  return mixed_extra_bytes((int64_t)p.kk * p.max_liz, p.kk > 16 ? 32 : 16);
+  return mixed_extra_bytes((int64_t)p.kc * p.max_liz, p.kk > 16 ? 32 : 16);
 }
 
 hipError_t lsms_launch_mixed(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, int64_t slot,
                              unsigned char* extra, int64_t xslot, double* tau00, int32_t* info, int32_t nb, double tol,
                              int32_t max_refine, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  const int64_t nmax = (int64_t)p.kc * p.max_liz;
   if (nmax <= kThreads * 5)
     return launch_mixed<5, 8>(p, i0, n, M, slot, extra, xslot, tau00, info, nb, tol, max_refine, s);
   return launch_mixed<8, 4>(p, i0, n, M, slot, extra, xslot, tau00, info, nb, tol, max_refine, s);
@@ -1825,7 +1854,7 @@ hipError_t lsms_mixed_persistent_grid(const lsms_prob_dev& p, int device, int* g
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  const int64_t nmax = (int64_t)p.kc * p.max_liz;
   if (nmax <= kThreads * 5)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_mixed_persistent_kernel<5, 8>, kThreads,
                                                      mixed_smem_bytes());
@@ -1842,7 +1871,7 @@ hipError_t lsms_launch_mixed_persistent(const lsms_prob_dev& p, const lsms_gaunt
                                         int grid, double* tau00, int32_t* info, int32_t nb, double tol,
                                         int32_t max_refine, hipStream_t s) {
   if (p.n_inst <= 0) return hipSuccess;
-  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  const int64_t nmax = (int64_t)p.kc * p.max_liz;
   if (nmax <= kThreads * 5)
     return launch_mixed_persistent<5, 8>(p, g, order, counter, work, slot_bytes, m_bytes, grid, tau00, info, nb, tol,
                                          max_refine, s);
@@ -1850,7 +1879,7 @@ hipError_t lsms_launch_mixed_persistent(const lsms_prob_dev& p, const lsms_gaunt
                                        max_refine, s);
 }
 
-int64_t lsms_gmres_extra_bytes(const lsms_prob_dev& p, int m) { return gmres_extra_bytes((int64_t)p.kk * p.max_liz, m); }
+int64_t lsms_gmres_extra_bytes(const lsms_prob_dev& p, int m) { return gmres_extra_bytes((int64_t)p.kc * p.max_liz, m); }
 
 int lsms_gmres_max_restart() { return kGmMaxM; }
 
@@ -1859,7 +1888,7 @@ hipError_t lsms_gmres_grid(const lsms_prob_dev& p, int device, int* grid) {
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  const int64_t nmax = (int64_t)p.kc * p.max_liz;
   if (nmax <= kThreads * 5)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tau00_gmres_persistent_kernel<5, 8>, kThreads,
                                                      gmres_smem_bytes());
@@ -1876,7 +1905,7 @@ hipError_t lsms_launch_gmres(const lsms_prob_dev& p, const lsms_gaunt_dev& g, co
                              double* tau00, int32_t* info, int32_t* steps, int32_t nb, double tol, int max_cycles,
                              int m, hipStream_t s) {
   if (p.n_inst <= 0) return hipSuccess;
-  const int64_t nmax = (int64_t)p.kk * p.max_liz;
+  const int64_t nmax = (int64_t)p.kc * p.max_liz;
   if (nmax <= kThreads * 5)
     return launch_gmres<5, 8>(p, g, order, counter, work, slot_bytes, m_bytes, grid, seed, tau00, info, steps, nb,
                               tol, max_cycles, m, s);

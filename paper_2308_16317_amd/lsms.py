@@ -38,6 +38,10 @@ class _Problem(ctypes.Structure):
     ]
 
 
+class _Spin(ctypes.Structure):
+    _fields_ = [("moment", _P), ("delta_dn", _P)]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [
         ("precision", ctypes.c_int32),
@@ -64,7 +68,8 @@ SYMBOLS = ("lsms_create", "lsms_destroy", "lsms_build_liz", "build_kkr", "tau00_
            "lsms_mlp_features", "lsms_mlp_cast", "lsms_mlp_forward", "lsms_mlp_backward", "lsms_mlp_mse",
            "lsms_mlp_adamw", "lsms_mlp_seed", "lsms_mlp_targets", "lsms_mlp_norm_stats",
            "lsms_gmres_workspace_size", "tau00_gmres", "lsms_row_workspace_size", "tau_row_batched",
-           "lsms_contour_sum", "lsms_lloyd_idos")
+           "lsms_contour_sum", "lsms_lloyd_idos", "lsms_liz_moments", "build_kkr_spin", "tau00_spin_batched",
+           "lsms_spin_workspace_size", "tau00_spin_solve")
 
 BATCHED_WORK_PER_INST = 2 * 64 * 64 * 16
 MLP_PARAMS = 399616
@@ -89,6 +94,14 @@ def lib():
         L.lsms_row_workspace_size.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(ctypes.c_size_t)]
         L.tau_row_batched.argtypes = [_P, ctypes.POINTER(_Problem), _P, _P, ctypes.POINTER(Opts), _P, _P, _P, _P, _P,
                                       _P, ctypes.c_size_t, _P]
+        PP = ctypes.POINTER(_Problem)
+        SP = ctypes.POINTER(_Spin)
+        L.lsms_liz_moments.argtypes = [_P, ctypes.c_int64, _P, _P, _I32, _P, _P]
+        L.build_kkr_spin.argtypes = [_P, PP, SP, _P, _P, _P, _P]
+        L.tau00_spin_batched.argtypes = [_P, PP, SP, _P, _P, ctypes.POINTER(Opts), _P, _P, _P, ctypes.c_size_t, _P]
+        L.lsms_spin_workspace_size.argtypes = [_P, PP, SP, ctypes.POINTER(Opts), _I32,
+                                               ctypes.POINTER(ctypes.c_size_t)]
+        L.tau00_spin_solve.argtypes = [_P, PP, SP, ctypes.POINTER(Opts), _P, _P, _P, ctypes.c_size_t, _P]
         L.lsms_contour_sum.argtypes = [_P, _I32, _I32, _I32, _P, _P, _P, _P]
         L.lsms_lloyd_idos.argtypes = [_P, _I32, _I32, _P, _P, _P]
         L.lsms_workspace_size.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(Opts), _I32,
@@ -186,10 +199,39 @@ class Problem:
     def kk(self):
         return (self.lmax + 1) ** 2
 
+    @property
+    def kc(self):
+        """Rows per LIZ site: kk, or 2 kk with spin canting."""
+        return self.kk * (2 if self.spin is not None else 1)
+
+    spin = None  # SpinData of a spin-canted problem
+
     def struct(self) -> _Problem:
         return _Problem(self.lmax, self.n_inst, int(self.delta.shape[0]), int(self.delta.shape[1]), self.max_liz, 0,
                         _ptr(self.liz_off), _ptr(self.pos), _ptr(self.species), _ptr(self.energy), _ptr(self.e_idx),
                         _ptr(self.delta))
+
+
+class SpinData:
+    """Device-resident lsms_spin: per-LIZ-row moment directions and the
+    phase shifts of the spin antiparallel to the moment."""
+
+    def __init__(self, moment, delta_dn):
+        self.moment = _dev(moment, torch.float64)
+        self.delta_dn = _dev(delta_dn, torch.complex128)
+
+    def struct(self) -> _Spin:
+        return _Spin(_ptr(self.moment), _ptr(self.delta_dn))
+
+
+def liz_moments(h: Handle, liz_atom: torch.Tensor, atom_moment) -> torch.Tensor:
+    """lsms_liz_moments: the moment of each LIZ row from the supercell's."""
+    am = _dev(atom_moment, torch.float64)
+    n = int(liz_atom.shape[0])
+    out = torch.empty((max(n, 1), 3), dtype=torch.float64, device="cuda")
+    _check(lib().lsms_liz_moments(h.ptr, n, _ptr(liz_atom), _ptr(am), int(am.shape[0]), _ptr(out), _stream()),
+           "lsms_liz_moments")
+    return out[:n]
 
 
 def build_liz(h: Handle, atom_pos, atom_species, box, centre, rc, max_liz: int, with_atoms: bool = False,
@@ -351,13 +393,67 @@ def tau00_solve(h: Handle, prob: Problem, work: torch.Tensor, opts: Opts | None 
 def problem_for_workload(h: Handle, w, max_liz: int = 1024) -> Problem:
     """Upload a workload's inputs (supercell, centres, cutoffs, energies, phase
     shifts) and extract every instance's LIZ with lsms_build_liz.  The
-    problem's max_liz is the largest LIZ found (one device-to-host read)."""
-    liz = build_liz(h, w.atom_pos, w.atom_species, w.box, w.centre, w.rc, max_liz)
+    problem's max_liz is the largest LIZ found (one device-to-host read).  A
+    spin-canted workload also gets its per-row moments (lsms_liz_moments) and
+    down-spin phase shifts in prob.spin."""
+    spin = getattr(w, "atom_moment", None) is not None
+    liz = build_liz(h, w.atom_pos, w.atom_species, w.box, w.centre, w.rc, max_liz, with_atoms=spin)
     n_max = int(liz["liz_n"].max().item()) if w.centre.shape[0] else 1
     if n_max > max_liz:
         raise RuntimeError(f"a LIZ has {n_max} sites, above max_liz={max_liz}")
-    return Problem(w.lmax, liz["liz_off"], liz["pos"], liz["species"], w.energies, w.e_idx, w.delta,
+    prob = Problem(w.lmax, liz["liz_off"], liz["pos"], liz["species"], w.energies, w.e_idx, w.delta,
                    max_liz=n_max)
+    if spin:
+        rows = int(liz["liz_off"][-1].item()) if w.centre.shape[0] else 0
+        prob.spin = SpinData(liz_moments(h, liz["atom"][:rows], w.atom_moment), w.delta_dn)
+    return prob
+
+
+def build_kkr_spin(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tensor) -> torch.Tensor:
+    """build_kkr_spin into M at offsets m_off; returns info (device)."""
+    info = torch.empty(max(prob.n_inst, 1), dtype=torch.int32, device="cuda")
+    ps, sp = prob.struct(), prob.spin.struct()
+    _check(lib().build_kkr_spin(h.ptr, ctypes.byref(ps), ctypes.byref(sp), _ptr(M), _ptr(m_off), _ptr(info),
+                                _stream()), "build_kkr_spin")
+    return info[:prob.n_inst]
+
+
+def tau00_spin_batched(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tensor, opts: Opts | None = None,
+                       work=None):
+    """tau00_spin_batched on caller-built M (overwritten): (tau00 [n, kc, kc], info)."""
+    kc = prob.kc
+    tau = torch.empty(max(prob.n_inst, 1) * kc * kc, dtype=torch.complex128, device="cuda")
+    info = torch.empty(max(prob.n_inst, 1), dtype=torch.int32, device="cuda")
+    ps, sp = prob.struct(), prob.spin.struct()
+    o = opts if opts is not None else Opts()
+    wb = 0 if work is None else work.numel() * work.element_size()
+    _check(lib().tau00_spin_batched(h.ptr, ctypes.byref(ps), ctypes.byref(sp), _ptr(M), _ptr(m_off),
+                                    ctypes.byref(o), _ptr(tau), _ptr(info), _ptr(work), wb, _stream()),
+           "tau00_spin_batched")
+    return _tau_view(tau, kc)[:prob.n_inst], info[:prob.n_inst]
+
+
+def spin_workspace_size(h: Handle, prob: Problem, chunk: int, opts: Opts | None = None) -> int:
+    b = ctypes.c_size_t()
+    ps, sp = prob.struct(), prob.spin.struct()
+    o = opts if opts is not None else Opts()
+    _check(lib().lsms_spin_workspace_size(h.ptr, ctypes.byref(ps), ctypes.byref(sp), ctypes.byref(o), int(chunk),
+                                          ctypes.byref(b)), "lsms_spin_workspace_size")
+    return int(b.value)
+
+
+def tau00_spin_solve(h: Handle, prob: Problem, work: torch.Tensor, opts: Opts | None = None, tau=None, info=None):
+    """Fused spin-canted build + solve in `work`: (tau00 [n, kc, kc], info)."""
+    kc = prob.kc
+    if tau is None:
+        tau = torch.empty(max(prob.n_inst, 1) * kc * kc, dtype=torch.complex128, device="cuda")
+    if info is None:
+        info = torch.empty(max(prob.n_inst, 1), dtype=torch.int32, device="cuda")
+    ps, sp = prob.struct(), prob.spin.struct()
+    o = opts if opts is not None else Opts()
+    _check(lib().tau00_spin_solve(h.ptr, ctypes.byref(ps), ctypes.byref(sp), ctypes.byref(o), _ptr(tau), _ptr(info),
+                                  _ptr(work), work.numel() * work.element_size(), _stream()), "tau00_spin_solve")
+    return _tau_view(tau, kc)[:prob.n_inst], info[:prob.n_inst]
 
 
 def autotune(h: Handle, prob: Problem, work: torch.Tensor, opts: Opts | None = None):
