@@ -24,6 +24,7 @@ from .workloads import (  # noqa: F401
     config3,
     config4,
     config_canted,
+    config_large,
     contour_energies,
     contour_ends,
     contour_weights,

@@ -222,6 +222,22 @@ def config_canted(seed: int = 0, lmax: int = 3) -> Workload:
                                atom_moment=canted_moments(w.atom_pos.shape[0], seed))
 
 
+def config_large(seed: int = 0, lmax: int = 4) -> Workload:
+    """One matrix per instance at the paper's non-canted NiAu rank: 6x6x6 fcc
+    cells (864 atoms, box 6a, so that the cutoff stays below half the box),
+    exact 50/50 species, cutoff 2.46a (the shell closure of 249 atoms: N =
+    25 * 249 = 6225 at lmax = 4), 32 energies; 864 x 32 instances, site-major."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(8)[7])
+    pos, box = fcc_supercell(6)
+    species = rng.permutation(np.repeat(np.array([0, 1], np.int32), pos.shape[0] // 2))
+    e = contour_energies(32)
+    sites = np.repeat(np.arange(pos.shape[0]), e.size)
+    eidx = np.tile(np.arange(e.size), pos.shape[0])
+    return Workload(f"fcc-NiAu-249atomLIZ-lmax{lmax}", lmax, box, pos, species.astype(np.int32), e,
+                    phase_shift_table(e, lmax), sites.astype(np.int32), np.full(sites.size, 2.46 * A_LAT),
+                    eidx.astype(np.int32))
+
+
 def config4(seed: int = 0, n_inst: int = 1024) -> Workload:
     """Ragged case: 10x10x10 cells (4000 sites), 3% vacancies, Gaussian noise
     sigma = 0.02a per component, exact 50/50 species over occupied sites,
