@@ -279,6 +279,30 @@ int lsms_spin_workspace_size(lsms_handle_t h, const lsms_problem *p, const lsms_
 int tau00_spin_solve(lsms_handle_t h, const lsms_problem *p, const lsms_spin *spin, const lsms_opts *opts,
                      double *tau00, int32_t *info, void *work, size_t work_bytes, void *stream);
 
+/* One instance across the whole GPU (paper Sec. 5: offloading the inverse of
+ * the whole KKR matrix; Sec. 4.1: ranks 6225 to 12450).  tau00 of a single
+ * caller-built matrix with every compute unit taking part: per panel of 64
+ * columns one workgroup factorises the panel (partial pivoting among the
+ * non-central rows, as tau00_batched), then one workgroup per 64-column
+ * strip applies the interchanges and forms U12, and one per (strip, 512
+ * rows) applies the MFMA update; the next panel is factorised while the rest
+ * of the update runs (one panel of look-ahead, on a second stream of the
+ * handle, joined back to `stream` before the call's last kernel).
+ *   p        n_inst = 1, the instance's LIZ exactly max_liz sites (info -3
+ *            otherwise); N = kk * max_liz (2 kk * max_liz with spin) <= 8192
+ *   spin     NULL, or spin canting as tau00_spin_batched
+ *   M        device complex N x N column-major (build_kkr / build_kkr_spin with
+ *            m_off = 0); overwritten
+ *   opts     FP64 only, nb 0 or 64, no flags (-5 otherwise)
+ *   tau00, info  device, one instance (as tau00_batched / tau00_spin_batched)
+ *   work     device, lsms_large_workspace_size bytes (pivots, two 64 x 64
+ *            blocks; -8 when NULL, -9 when too small)
+ * Calls on one handle must not overlap in time (they share the second stream
+ * and its events). */
+int lsms_large_workspace_size(lsms_handle_t h, const lsms_problem *p, const lsms_spin *spin, size_t *bytes);
+int tau00_large(lsms_handle_t h, const lsms_problem *p, const lsms_spin *spin, double *M, const lsms_opts *opts,
+                double *tau00, int32_t *info, void *work, size_t work_bytes, void *stream);
+
 /* Energy integration along the contour (paper Sec. 2.1, eq. Density: the
  * density of states and the charge are energy integrals, taken by quadrature
  * on a complex contour).  A batch is laid out [site][energy], instance

@@ -162,6 +162,10 @@ struct lsms_handle_s {
   int32_t tuned_nb[kPrecisions][kBuckets];
   GraphEntry graphs[kGraphCache];
   uint64_t clock;
+  // tau00_large: the second stream of its look-ahead and its events (made on
+  // the first call)
+  hipStream_t aux = nullptr;
+  std::vector<hipEvent_t> big_ev;
 };
 
 #define HIP_TRY(x)                          \
@@ -287,7 +291,8 @@ extern "C" int lsms_create(lsms_handle_t* out, int device) {
     h->g[lmax].lmax = lmax;
     h->g[lmax].nnz = (int32_t)coef.size();
   }
-  if (lsms_prepare_kernels() != hipSuccess || scratch_setup(device) != 0 || hipDeviceSynchronize() != hipSuccess) {
+  if (lsms_prepare_kernels() != hipSuccess || lsms_prepare_big_kernels() != hipSuccess ||
+      scratch_setup(device) != 0 || hipDeviceSynchronize() != hipSuccess) {
     for (int q = 0; q <= kMaxLmax; ++q) (void)hipFree(h->mem[q]);
     delete h;
     return LSMS_EHIP;
@@ -303,6 +308,8 @@ extern "C" int lsms_destroy(lsms_handle_t h) {
   for (int q = 0; q < kGraphCache; ++q)
     if (h->graphs[q].used) (void)hipGraphExecDestroy(h->graphs[q].exec);
   for (int q = 0; q <= kMaxLmax; ++q) (void)hipFree(h->mem[q]);
+  for (hipEvent_t e : h->big_ev) (void)hipEventDestroy(e);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
   delete h;
   return 0;
 }
@@ -524,6 +531,56 @@ extern "C" int tau00_spin_solve(lsms_handle_t h, const lsms_problem* p, const ls
   (void)hipSetDevice(h->device);
   const int er = enqueue_solve(h, p, opts, tau00, info, work, work_bytes, (hipStream_t)stream, spin);
   return er == -7 ? -8 : er;
+}
+
+// ------------------------------------------------ one instance, whole GPU
+int check_large(const lsms_problem* p, const lsms_spin* spin, const lsms_opts* opts) {
+  int r = check_problem(p, spin ? 2 : 1);
+  if (r) return r;
+  if (p->n_inst != 1) return -2;
+  if (spin && (r = check_spin(p, spin))) return r;
+  if (check_opts(opts) || mixed(opts) || (opts && opts->nb != 0 && opts->nb != 64) || (opts && opts->flags))
+    return -5;
+  return 0;
+}
+
+extern "C" int lsms_large_workspace_size(lsms_handle_t h, const lsms_problem* p, const lsms_spin* spin,
+                                         size_t* bytes) {
+  if (!h) return -1;
+  const int r = check_large(p, spin, nullptr);
+  if (r) return r;
+  if (!bytes) return -4;
+  *bytes = (size_t)lsms_big_work_bytes(to_dev(p, spin));
+  return 0;
+}
+
+extern "C" int tau00_large(lsms_handle_t h, const lsms_problem* p, const lsms_spin* spin, double* M,
+                           const lsms_opts* opts, double* tau00, int32_t* info, void* work, size_t work_bytes,
+                           void* stream) {
+  if (!h) return -1;
+  const int r = check_large(p, spin, opts);
+  if (r) return r;
+  if (!M) return -4;
+  if (!tau00) return -6;
+  if (!info) return -7;
+  if (!work) return -8;
+  const lsms_prob_dev d = to_dev(p, spin);
+  if (work_bytes < (size_t)lsms_big_work_bytes(d)) return -9;
+  (void)hipSetDevice(h->device);
+  if (!h->aux && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) {
+    h->aux = nullptr;
+    return LSMS_EHIP;
+  }
+  const size_t nev = (size_t)lsms_big_events(d);
+  while (h->big_ev.size() < nev) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return LSMS_EHIP;
+    h->big_ev.push_back(e);
+  }
+  return lsms_launch_big(d, M, (unsigned char*)work, tau00, info, 64, (hipStream_t)stream, h->aux,
+                         h->big_ev.data()) == hipSuccess
+             ? 0
+             : LSMS_EHIP;
 }
 
 // The allocation-free variant of tau00_batched: the same kernels, the

@@ -162,6 +162,15 @@ hipError_t lsms_launch_tau_row(const lsms_prob_dev& p, int32_t i0, int32_t n, do
                                double* tau00, int32_t* info, int32_t nb, hipStream_t s);
 hipError_t lsms_launch_lpt_order(const lsms_prob_dev& p, int32_t* order, hipStream_t s);
 
+// One instance (n_inst = 1, exactly max_liz sites) across the whole GPU:
+// workspace bytes, events needed (2 per panel), the launch sequence on the
+// streams s0 (the caller's) and s1, and the kernels' LDS attributes.
+int64_t lsms_big_work_bytes(const lsms_prob_dev& p);
+int lsms_big_events(const lsms_prob_dev& p);
+hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* work, double* tau00, int32_t* info,
+                           int32_t nb, hipStream_t s0, hipStream_t s1, hipEvent_t* ev);
+hipError_t lsms_prepare_big_kernels();
+
 // out[r][0..2] = src[idx[r]][0..2] (liz.hip): per-row moments of the LIZs.
 hipError_t lsms_launch_gather3(int64_t n, const int32_t* idx, const double* src, int32_t n_src, double* out,
                                hipStream_t s);

@@ -753,14 +753,16 @@ constexpr int kUpdChunk = sizeof(R) == 4 ? 32 : 16;
 // U[k] are zero for k >= s.
 template <typename R, int NCS>
 __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, int r0, int s, int s0, int sw,
-                                            const typename Prec<R>::C (*Ub)[kSWp<R>]) {
+                                            const typename Prec<R>::C (*Ub)[kSWp<R>], int vlo = 0,
+                                            int vhi = 0x7fffffff) {
   typedef typename Prec<R>::C C;
   typedef typename Prec<R>::V4 V4;
   constexpr int KJ = kUpdChunk<R> / 4;  // MFMA steps per chunk
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
-  const int N = (int)A.N;
-  const int rstart = r0 + s;
+  // rows [max(r0 + s, vlo), min(N, vhi)) (all rows below the block by default)
+  const int N = min((int)A.N, vhi);
+  const int rstart = max(r0 + s, vlo);
   int64_t ccol[NCS];
   bool cok[NCS];
 #pragma unroll

@@ -250,41 +250,18 @@ __device__ __noinline__ void row_output(const lsms_prob_dev& p, int inst, const 
   __syncthreads();
 }
 
-// Eliminates one instance whose matrix is at `base` and writes its tau00 and
-// info (and, with ro, its block row of tau and ln det M).  All threads of the
-// workgroup call it; it ends after a barrier.
-template <int kR, int kWL>
-__device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, double* __restrict__ tau00,
-                            int32_t* __restrict__ info, int nb, LuSmemD& sh, const RowOut ro = RowOut{}) {
+// The end of one instance after its elimination (sh.info holds the first
+// zero-pivot step or 0): Gauss-Jordan inverse of the Schur block S_A,
+// tau00, and with ro the block row and ln det M (ld_*: the sums over the U
+// diagonal).  All threads call it; it ends after a barrier.
+__device__ __noinline__ void finish_instance(const lsms_prob_dev& p, int inst, const Mat<zd>& A, const RowOut& ro,
+                                             double ld_re, double ld_im, int ld_sw, double* __restrict__ tau00,
+                                             int32_t* __restrict__ info, LuSmemD& sh) {
   const int tid = threadIdx.x;
-  const int kk = p.kk, kc = p.kc;  // kc = kk, or 2 kk with spin canting
-  const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
-  const int N = kc * nliz, Nd = N - kc;
+  const int kk = p.kk, kc = p.kc;
+  const int N = (int)A.N, Nd = A.Nd;
   zd* tout = reinterpret_cast<zd*>(tau00) + (int64_t)inst * kc * kc;
-  Mat<zd> A;
-  A.base = glb(base);
-  A.N = N;
-  A.Nd = Nd;
-  A.kk = kc;
-  if (tid == 0) {
-    sh.info = 0;
-    sh.bad = 0;
-  }
-  __syncthreads();
   const bool want_row = ro.row != nullptr, want_ld = ro.logdet != nullptr;
-  eliminate<double, kR, kWL>(A, 0, Nd, Nd, nb, want_row, want_ld ? ro.ipiv : nullptr, xg, sh);
-  double ld_re = 0.0, ld_im = 0.0;
-  int ld_sw = 0;
-  if (want_ld) {
-    for (int v = tid; v < Nd; v += kThreads) {
-      const zd u = *A.ptr(v, v);
-      ld_re += log(hypot(u.x, u.y));
-      ld_im += atan2(u.y, u.x);
-      ld_sw += ro.ipiv[v] != v;
-    }
-    block_sum(ld_re, ld_im, ld_sw, sh);
-  }
-
   // Gauss-Jordan inverse of S_A (kc x kc, physical rows/cols 0..kc-1)
   GjRow* G = gj_view(sh);
   for (int q = tid; q < kc * 2 * kc; q += kThreads) {
@@ -376,6 +353,43 @@ __device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, 
   __syncthreads();
   if (tid == 0) info[inst] = info0 != 0 ? info0 : (sh.bad ? -1 : 0);
   __syncthreads();
+}
+
+// Eliminates one instance whose matrix is at `base` and writes its tau00 and
+// info (and, with ro, its block row of tau and ln det M).  All threads of the
+// workgroup call it; it ends after a barrier.
+template <int kR, int kWL>
+__device__ void lu_instance(const lsms_prob_dev& p, int inst, zd* base, zd* xg, double* __restrict__ tau00,
+                            int32_t* __restrict__ info, int nb, LuSmemD& sh, const RowOut ro = RowOut{}) {
+  const int tid = threadIdx.x;
+  const int kc = p.kc;  // kk, or 2 kk with spin canting
+  const int nliz = (int)(p.liz_off[inst + 1] - p.liz_off[inst]);
+  const int N = kc * nliz, Nd = N - kc;
+  Mat<zd> A;
+  A.base = glb(base);
+  A.N = N;
+  A.Nd = Nd;
+  A.kk = kc;
+  if (tid == 0) {
+    sh.info = 0;
+    sh.bad = 0;
+  }
+  __syncthreads();
+  const bool want_ld = ro.logdet != nullptr;
+  eliminate<double, kR, kWL>(A, 0, Nd, Nd, nb, ro.row != nullptr, want_ld ? ro.ipiv : nullptr, xg, sh);
+  double ld_re = 0.0, ld_im = 0.0;
+  int ld_sw = 0;
+  if (want_ld) {
+    for (int v = tid; v < Nd; v += kThreads) {
+      const zd u = *A.ptr(v, v);
+      ld_re += log(hypot(u.x, u.y));
+      ld_im += atan2(u.y, u.x);
+      ld_sw += ro.ipiv[v] != v;
+    }
+    block_sum(ld_re, ld_im, ld_sw, sh);
+  }
+
+  finish_instance(p, inst, A, ro, ld_re, ld_im, ld_sw, tau00, info, sh);
 }
 
 // True when the instance cannot be processed (empty LIZ, LIZ above max_liz,
@@ -1656,6 +1670,141 @@ __global__ __launch_bounds__(kThreads) void tau00_gmres_persistent_kernel(
   }
 }
 
+// ======================================================================
+// One instance across the whole GPU (paper Sec. 5: offloading the whole KKR
+// inverse, whose ranks, 6225 to 12450 in Sec. 4.1, are too large for one
+// compute unit to factorise quickly).  The same elimination as lu_instance
+// (A = M^T, pivots among the non-central rows, the central block last, then
+// Gauss-Jordan on the Schur block), split over many workgroups: per panel
+// of 64 columns
+//   big_panel_kernel: one workgroup factorises the panel (the recursive
+//     register-leaf panel_factor over all rows), writes its pivots and the
+//     inverse of its unit lower diagonal block;
+//   big_u12_kernel: one workgroup per 64-column strip of the trailing
+//     columns applies the panel's interchanges to the strip and forms
+//     U12 = L11^{-1} A12 (stored in A);
+//   big_gemm_kernel: one workgroup per (strip, 512 rows) updates
+//     A22 -= L21 U12 on MFMA.
+// The host issues the launches on two streams with one panel of
+// look-ahead: the next strip's update and the next panel run on the
+// caller's stream while the rest of the trailing update runs on the second.
+// ======================================================================
+constexpr int kBigRows = 512;  // trailing-update rows per workgroup
+
+struct BigView {
+  Mat<zd> A;
+  int N, Nd;
+};
+
+__device__ __forceinline__ BigView big_view(const lsms_prob_dev& p, double* Mb) {
+  BigView v;
+  v.N = p.kc * p.max_liz;
+  v.Nd = v.N - p.kc;
+  v.A.base = glb(reinterpret_cast<zd*>(Mb));
+  v.A.N = v.N;
+  v.A.Nd = v.Nd;
+  v.A.kk = p.kc;
+  return v;
+}
+
+// state[0] := 0, or -3 when the instance is not one of max_liz sites with a
+// valid energy index (its rank would differ from the planned N).
+__global__ void big_init_kernel(lsms_prob_dev p, int32_t* state) {
+  if (threadIdx.x != 0) return;
+  const int64_t nliz = p.liz_off[1] - p.liz_off[0];
+  const int e = p.e_idx[0];
+  state[0] = (nliz != p.max_liz || e < 0 || e >= p.n_energy) ? -3 : 0;
+}
+
+template <int kR, int kWL>
+__global__ __launch_bounds__(kThreads) void big_panel_kernel(lsms_prob_dev p, double* Mb, int c, int w,
+                                                             int32_t* __restrict__ ipiv, double* __restrict__ xg,
+                                                             int32_t* __restrict__ state) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
+  const BigView v = big_view(p, Mb);
+  if (threadIdx.x == 0) sh.info = 0;
+  __syncthreads();
+  panel_factor<double, kR, kWL>(v.A, c, w, v.Nd, false, sh);
+  if (threadIdx.x < w) ipiv[c + threadIdx.x] = sh.ipiv[threadIdx.x];
+  if (threadIdx.x == 0 && sh.info != 0 && state[0] == 0) state[0] = sh.info;
+  if (c + w < v.N) {
+    invert_unit_lower<double>(v.A, c, w, sh);
+    save_x<double>(sh, reinterpret_cast<zd*>(xg));
+  }
+}
+
+// Strips [s_begin + 64 b, ...) of the trailing columns, b = blockIdx.x.
+__global__ __launch_bounds__(kThreads) void big_u12_kernel(lsms_prob_dev p, double* Mb, int c, int w,
+                                                           const int32_t* __restrict__ ipiv,
+                                                           const double* __restrict__ xg, int s_begin,
+                                                           int s_end) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
+  const BigView v = big_view(p, Mb);
+  const int s0 = s_begin + kNB * blockIdx.x, sw = min(kNB, s_end - s0);
+  if (threadIdx.x < w) sh.ipiv[threadIdx.x] = ipiv[c + threadIdx.x];
+  const zd* x = reinterpret_cast<const zd*>(xg);
+  for (int q = threadIdx.x; q < kNB * kNB; q += kThreads) sh.X[q / kNB][q % kNB] = x[q];
+  __syncthreads();
+  apply_swaps<double>(v.A, c, w, s0, s0 + sw, sh);
+  __syncthreads();
+  trsm_strip<double>(v.A, c, w, s0, sw, true, sh);
+}
+
+// A22 -= L21 U12 for the strip s_begin + 64 blockIdx.x and the rows
+// [c + w + rows blockIdx.y, + rows) (U12 read back from A into LDS).
+// Panels wider than 32 columns take the MFMA row-block update with row
+// bounds; narrower ones (only a ragged last panel) one workgroup per strip
+// over all rows (launched with one row block).
+__global__ __launch_bounds__(kThreads) void big_gemm_kernel(lsms_prob_dev p, double* Mb, int c, int w,
+                                                            int s_begin, int s_end, int rows) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
+  const BigView v = big_view(p, Mb);
+  const int s0 = s_begin + kNB * blockIdx.x, sw = min(kNB, s_end - s0);
+  const int vlo = c + w + rows * blockIdx.y, vhi = min(v.N, vlo + rows);
+  if (vlo >= v.N) return;
+  for (int q = threadIdx.x; q < kNB * kNB; q += kThreads) {
+    const int k = q / kNB, j = q % kNB;
+    sh.U[k][j] = (k < w && j < sw) ? *v.A.ptr(c + k, s0 + j) : zmake(0.0, 0.0);
+  }
+  __syncthreads();
+  if (w <= 32) {
+    update_strip<double>(v.A, c, w, s0, sw, sh.U);
+  } else if (sw > 48) {
+    update_rows<double, 4>(v.A, c, w, s0, sw, sh.U, vlo, vhi);
+  } else if (sw > 32) {
+    update_rows<double, 3>(v.A, c, w, s0, sw, sh.U, vlo, vhi);
+  } else if (sw > 16) {
+    update_rows<double, 2>(v.A, c, w, s0, sw, sh.U, vlo, vhi);
+  } else {
+    update_rows<double, 1>(v.A, c, w, s0, sw, sh.U, vlo, vhi);
+  }
+}
+
+// Gauss-Jordan on the Schur block and tau00 (instance 0).
+__global__ __launch_bounds__(kThreads) void big_finish_kernel(lsms_prob_dev p, double* Mb,
+                                                              double* __restrict__ tau00,
+                                                              int32_t* __restrict__ info,
+                                                              const int32_t* __restrict__ state) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
+  const int st = state[0];
+  if (st < 0) {
+    fill_nan(p, 0, tau00);
+    if (threadIdx.x == 0) info[0] = st;
+    return;
+  }
+  const BigView v = big_view(p, Mb);
+  if (threadIdx.x == 0) {
+    sh.info = st;
+    sh.bad = 0;
+  }
+  __syncthreads();
+  finish_instance(p, 0, v.A, RowOut{}, 0.0, 0.0, 0, tau00, info, sh);
+}
+
 template <int kR, int kWL>
 hipError_t launch(const lsms_prob_dev& p, int32_t i0, int32_t n, double* M, const int64_t* m_off, int64_t slot,
                   double* xgb, int64_t xstride, double* tau00, int32_t* info, int keep_info, int32_t nb,
@@ -1911,4 +2060,79 @@ hipError_t lsms_launch_gmres(const lsms_prob_dev& p, const lsms_gaunt_dev& g, co
                               tol, max_cycles, m, s);
   return launch_gmres<8, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, seed, tau00, info, steps, nb, tol,
                             max_cycles, m, s);
+}
+
+// One instance across the whole GPU: workspace layout [state | ipiv | two
+// 64 x 64 blocks], see lsms_big_work_bytes.
+int64_t lsms_big_work_bytes(const lsms_prob_dev& p) {
+  const int64_t N = (int64_t)p.kc * p.max_liz;
+  return 256 + ((N * 4 + 255) & ~(int64_t)255) + 2 * kNB * kNB * 16;
+}
+
+int lsms_big_events(const lsms_prob_dev& p) {
+  const int Nd = p.kc * p.max_liz - p.kc;
+  return 2 * ((Nd + kNB - 1) / kNB);
+}
+
+hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* work, double* tau00, int32_t* info,
+                           int32_t nb, hipStream_t s0, hipStream_t s1, hipEvent_t* ev) {
+  (void)nb;  // panels are 64 wide
+  const int N = p.kc * p.max_liz, Nd = N - p.kc;
+  const int np = (Nd + kNB - 1) / kNB;
+  int32_t* state = reinterpret_cast<int32_t*>(work);
+  int32_t* ipiv = reinterpret_cast<int32_t*>(work + 256);
+  double* xg = reinterpret_cast<double*>(work + 256 + (((int64_t)N * 4 + 255) & ~(int64_t)255));
+  const size_t smem = sizeof(LuSmemD);
+  auto xgk = [&](int k) { return xg + (size_t)(k & 1) * kNB * kNB * 2; };
+  auto panel = [&](int k, hipStream_t s) {
+    const int c = kNB * k, w = min(kNB, Nd - c);
+    if (N <= kThreads * 5)
+      hipLaunchKernelGGL((big_panel_kernel<5, 8>), dim3(1), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k), state);
+    else if (N <= kThreads * 8)
+      hipLaunchKernelGGL((big_panel_kernel<8, 4>), dim3(1), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k), state);
+    else
+      hipLaunchKernelGGL((big_panel_kernel<16, 2>), dim3(1), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k),
+                         state);
+  };
+  // the update by panel k of the columns [a, b)
+  auto update = [&](int k, int a, int b, hipStream_t s) {
+    if (a >= b) return;
+    const int c = kNB * k, w = min(kNB, Nd - c);
+    const unsigned ns = (unsigned)((b - a + kNB - 1) / kNB);
+    hipLaunchKernelGGL(big_u12_kernel, dim3(ns), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k), a, b);
+    const int below = N - (c + w);
+    const unsigned nr = w <= 32 ? 1u : (unsigned)((below + kBigRows - 1) / kBigRows);
+    if (below > 0)
+      hipLaunchKernelGGL(big_gemm_kernel, dim3(ns, nr), dim3(kThreads), smem, s, p, M, c, w, a, b, kBigRows);
+  };
+  hipLaunchKernelGGL(big_init_kernel, dim3(1), dim3(64), 0, s0, p, state);
+  panel(0, s0);
+  for (int k = 0; k < np; ++k) {
+    const int next = kNB * (k + 1);  // first column of panel k + 1 (Nd after the last)
+    const int rest = k + 1 < np ? min(next + kNB, Nd) : Nd;
+    hipError_t e = hipEventRecord(ev[2 * k], s0);
+    if (e != hipSuccess) return e;
+    if (k + 1 < np) {
+      update(k, next, rest, s0);  // the next panel's columns first
+      panel(k + 1, s0);
+    }
+    if ((e = hipStreamWaitEvent(s1, ev[2 * k], 0)) != hipSuccess) return e;
+    update(k, rest, N, s1);  // every other trailing column, beside the next panel
+    if ((e = hipEventRecord(ev[2 * k + 1], s1)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s0, ev[2 * k + 1], 0)) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(big_finish_kernel, dim3(1), dim3(kThreads), smem, s0, p, M, tau00, info, state);
+  return hipGetLastError();
+}
+
+hipError_t lsms_prepare_big_kernels() {
+  const int a = (int)sizeof(LuSmemD);
+  const hipFuncAttribute attr = hipFuncAttributeMaxDynamicSharedMemorySize;
+  hipError_t e;
+  if ((e = hipFuncSetAttribute((const void*)big_panel_kernel<5, 8>, attr, a)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)big_panel_kernel<8, 4>, attr, a)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)big_panel_kernel<16, 2>, attr, a)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)big_u12_kernel, attr, a)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)big_gemm_kernel, attr, a)) != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)big_finish_kernel, attr, a);
 }

@@ -69,7 +69,7 @@ SYMBOLS = ("lsms_create", "lsms_destroy", "lsms_build_liz", "build_kkr", "tau00_
            "lsms_mlp_adamw", "lsms_mlp_seed", "lsms_mlp_targets", "lsms_mlp_norm_stats",
            "lsms_gmres_workspace_size", "tau00_gmres", "lsms_row_workspace_size", "tau_row_batched",
            "lsms_contour_sum", "lsms_lloyd_idos", "lsms_liz_moments", "build_kkr_spin", "tau00_spin_batched",
-           "lsms_spin_workspace_size", "tau00_spin_solve")
+           "lsms_spin_workspace_size", "tau00_spin_solve", "lsms_large_workspace_size", "tau00_large")
 
 BATCHED_WORK_PER_INST = 2 * 64 * 64 * 16
 MLP_PARAMS = 399616
@@ -102,6 +102,8 @@ def lib():
         L.lsms_spin_workspace_size.argtypes = [_P, PP, SP, ctypes.POINTER(Opts), _I32,
                                                ctypes.POINTER(ctypes.c_size_t)]
         L.tau00_spin_solve.argtypes = [_P, PP, SP, ctypes.POINTER(Opts), _P, _P, _P, ctypes.c_size_t, _P]
+        L.lsms_large_workspace_size.argtypes = [_P, PP, SP, ctypes.POINTER(ctypes.c_size_t)]
+        L.tau00_large.argtypes = [_P, PP, SP, _P, ctypes.POINTER(Opts), _P, _P, _P, ctypes.c_size_t, _P]
         L.lsms_contour_sum.argtypes = [_P, _I32, _I32, _I32, _P, _P, _P, _P]
         L.lsms_lloyd_idos.argtypes = [_P, _I32, _I32, _P, _P, _P]
         L.lsms_workspace_size.argtypes = [_P, ctypes.POINTER(_Problem), ctypes.POINTER(Opts), _I32,
@@ -328,6 +330,26 @@ def tau_row_batched(h: Handle, prob: Problem, M: torch.Tensor, m_off: torch.Tens
                                  _ptr(rows), _ptr(ld), _ptr(tau), _ptr(info), _ptr(work),
                                  work.numel() * work.element_size(), _stream()), "tau_row_batched")
     return rows, row_off[:n], (ld[:n] if ld is not None else None), _tau_view(tau, kk)[:n], info[:n]
+
+
+def tau00_large(h: Handle, prob: Problem, M: torch.Tensor, opts: Opts | None = None, work=None):
+    """tau00_large: one instance (prob.n_inst == 1) across the whole GPU on caller-built M
+    (overwritten); returns (tau00 [1, kc, kc], info [1])."""
+    kc = prob.kc
+    sp = prob.spin.struct() if prob.spin is not None else None
+    ps = prob.struct()
+    if work is None:
+        b = ctypes.c_size_t()
+        _check(lib().lsms_large_workspace_size(h.ptr, ctypes.byref(ps), ctypes.byref(sp) if sp else None,
+                                               ctypes.byref(b)), "lsms_large_workspace_size")
+        work = torch.empty(int(b.value), dtype=torch.uint8, device="cuda")
+    tau = torch.empty(kc * kc, dtype=torch.complex128, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    o = opts if opts is not None else Opts()
+    _check(lib().tau00_large(h.ptr, ctypes.byref(ps), ctypes.byref(sp) if sp else None, _ptr(M), ctypes.byref(o),
+                             _ptr(tau), _ptr(info), _ptr(work), work.numel() * work.element_size(), _stream()),
+           "tau00_large")
+    return _tau_view(tau, kc), info
 
 
 def contour_sum(h: Handle, weights, values: torch.Tensor, n_sites: int, n_energy: int) -> torch.Tensor:
