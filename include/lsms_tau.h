@@ -69,6 +69,9 @@ extern "C" {
 /* info flag of tau00_gmres when GMRES did not reach its tolerance and the
  * instance was solved by the FP64 path (ORed onto that path's info) */
 #define LSMS_INFO_LU_FALLBACK (1 << 21)
+/* info flag of tau00_gmres_pc for an instance that the caller's routing sent
+ * straight to the FP64 path (no GMRES step taken) */
+#define LSMS_INFO_ROUTED (1 << 22)
 
 /* learned form: parameters of the seed network and floats of activations
  * kept per sample by lsms_mlp_forward */
@@ -488,6 +491,34 @@ int lsms_gmres_workspace_size(lsms_handle_t h, const lsms_problem *p, int32_t re
 int tau00_gmres(lsms_handle_t h, const lsms_problem *p, const double *seed, int32_t restart, int32_t max_cycles,
                 double tol, double *tau00, int32_t *info, int32_t *steps, void *work, size_t work_bytes,
                 void *stream);
+
+/* tau00_gmres with a block-diagonal right preconditioner and per-instance
+ * routing (both optional, NULL for none; the other arguments as tau00_gmres,
+ * their error numbers shifted by three):
+ *   precond      device [n_blocks][256] complex, column-major 16 x 16 blocks
+ *                D_b approximating a site's diagonal block of M^{-1} (the
+ *                network's [M^{-1}]_{00} of the instance centred on that site,
+ *                lsms_mlp_seed); GMRES then solves A P^{-1} Z = E_c,
+ *                Y = P^{-1} Z, with P^{-1} block-diagonal over the LIZ sites,
+ *                the block of site j being D_{row[j]}^T (A = M^T)
+ *   precond_row  device [liz_off[n_inst]]: the block of every LIZ row, < 0 for
+ *                the identity (lsms_site_blocks); required with precond (-5)
+ *   route        device [n_inst] int8 or NULL: nonzero sends the instance
+ *                straight to the FP64 path (info |= LSMS_INFO_ROUTED, steps 0)
+ * The stopping test is on the true residual ||E_c - A Y||_F. */
+int tau00_gmres_pc(lsms_handle_t h, const lsms_problem *p, const double *seed, const double *precond,
+                   const int32_t *precond_row, const int8_t *route, int32_t restart, int32_t max_cycles, double tol,
+                   double *tau00, int32_t *info, int32_t *steps, void *work, size_t work_bytes, void *stream);
+
+/* Preconditioner block of every LIZ row for tau00_gmres_pc when the batch
+ * itself holds the blocks: precond_row[r] = the instance i of the batch with
+ * centre[i] = liz_atom[r] and the energy of the row's own instance (-1 when
+ * the batch has no such instance).  liz_atom: device [liz_off[n_inst]]
+ * (lsms_build_liz), centre: device [n_inst] supercell indices of the
+ * instances' centres, work: device n_atoms * n_energy ints.
+ * Errors: -3/-4/-6/-7 null pointers, -5 n_atoms < 1. */
+int lsms_site_blocks(lsms_handle_t h, const lsms_problem *p, const int32_t *liz_atom, const int32_t *centre,
+                     int32_t n_atoms, int32_t *precond_row, int32_t *work, void *stream);
 
 #ifdef __cplusplus
 }

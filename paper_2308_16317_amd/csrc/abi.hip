@@ -847,26 +847,60 @@ extern "C" int lsms_gmres_workspace_size(lsms_handle_t h, const lsms_problem* p,
   return 0;
 }
 
+extern "C" int tau00_gmres_pc(lsms_handle_t h, const lsms_problem* p, const double* seed, const double* precond,
+                              const int32_t* precond_row, const int8_t* route, int32_t restart, int32_t max_cycles,
+                              double tol, double* tau00, int32_t* info, int32_t* steps, void* work,
+                              size_t work_bytes, void* stream);
+
 extern "C" int tau00_gmres(lsms_handle_t h, const lsms_problem* p, const double* seed, int32_t restart,
                            int32_t max_cycles, double tol, double* tau00, int32_t* info, int32_t* steps, void* work,
                            size_t work_bytes, void* stream) {
+  const int r = tau00_gmres_pc(h, p, seed, nullptr, nullptr, nullptr, restart, max_cycles, tol, tau00, info, steps,
+                               work, work_bytes, stream);
+  return (r <= -7 && r >= -14) ? r + 3 : r;  // argument numbers of this signature
+}
+
+extern "C" int lsms_site_blocks(lsms_handle_t h, const lsms_problem* p, const int32_t* liz_atom,
+                                const int32_t* centre, int32_t n_atoms, int32_t* precond_row, int32_t* work,
+                                void* stream) {
+  if (!h) return -1;
+  int r = check_problem(p);
+  if (r) return r;
+  if (p->n_inst == 0) return 0;
+  if (!liz_atom) return -3;
+  if (!centre) return -4;
+  if (n_atoms < 1) return -5;
+  if (!precond_row) return -6;
+  if (!work) return -7;
+  (void)hipSetDevice(h->device);
+  return lsms_launch_site_blocks(to_dev(p), liz_atom, centre, n_atoms, precond_row, work, (hipStream_t)stream) ==
+                 hipSuccess
+             ? 0
+             : LSMS_EHIP;
+}
+
+extern "C" int tau00_gmres_pc(lsms_handle_t h, const lsms_problem* p, const double* seed, const double* precond,
+                              const int32_t* precond_row, const int8_t* route, int32_t restart, int32_t max_cycles,
+                              double tol, double* tau00, int32_t* info, int32_t* steps, void* work,
+                              size_t work_bytes, void* stream) {
   if (!h) return -1;
   int r = check_problem_small(p);
   if (r) return r;
   if (p->lmax != 3) return -2;
-  if (restart < 1 || restart > lsms_gmres_max_restart()) return -4;
-  if (max_cycles < 0 || max_cycles > 1000) return -5;
-  if (!(tol > 0.0 && tol < 1.0)) return -6;
+  if (restart < 1 || restart > lsms_gmres_max_restart()) return -7;
+  if (precond && !precond_row) return -5;
+  if (max_cycles < 0 || max_cycles > 1000) return -8;
+  if (!(tol > 0.0 && tol < 1.0)) return -9;
   if (p->n_inst == 0) return 0;
-  if (!tau00) return -7;
-  if (!info) return -8;
-  if (!steps) return -9;
-  if (!work) return -10;
+  if (!tau00) return -10;
+  if (!info) return -11;
+  if (!steps) return -12;
+  if (!work) return -13;
   (void)hipSetDevice(h->device);
   hipStream_t s = (hipStream_t)stream;
   GmresLayout L;
   if (gmres_layout(h, p, restart, &L)) return LSMS_EHIP;
-  if (work_bytes < L.total) return -11;
+  if (work_bytes < L.total) return -14;
   const lsms_prob_dev d = to_dev(p);
   char* w = (char*)work;
   int32_t* counter = (int32_t*)w;
@@ -874,7 +908,8 @@ extern "C" int tau00_gmres(lsms_handle_t h, const lsms_problem* p, const double*
   if (fill_i32(counter, 0, 1, s) != hipSuccess) return LSMS_EHIP;
   if (lsms_launch_lpt_order(d, order, s) != hipSuccess) return LSMS_EHIP;
   if (lsms_launch_gmres(d, h->g[p->lmax], order, counter, (unsigned char*)(w + L.slots_off), (int64_t)L.slot_stride,
-                        (int64_t)m_bytes(p), L.grid, seed, tau00, info, steps, panel_width(h, p, nullptr), tol,
+                        (int64_t)m_bytes(p), L.grid, seed, precond_row ? precond : nullptr, precond_row, route,
+                        tau00, info, steps, panel_width(h, p, nullptr), tol,
                         max_cycles, restart, s) != hipSuccess)
     return LSMS_EHIP;
   return 0;

@@ -209,8 +209,14 @@ int lsms_gmres_max_restart();
 hipError_t lsms_gmres_grid(const lsms_prob_dev& p, int device, int* grid);
 hipError_t lsms_launch_gmres(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order, int32_t* counter,
                              unsigned char* work, int64_t slot_bytes, int64_t m_bytes, int grid, const double* seed,
-                             double* tau00, int32_t* info, int32_t* steps, int32_t nb, double tol, int max_cycles,
-                             int m, hipStream_t s);
+                             const double* pc_blk, const int32_t* pc_row, const int8_t* route, double* tau00,
+                             int32_t* info, int32_t* steps, int32_t nb, double tol, int max_cycles, int m,
+                             hipStream_t s);
+// Block index of each LIZ row for the GMRES preconditioner: the instance of
+// the batch centred on the row's atom at the row's instance's energy (-1 if
+// none); inst_of: n_atoms * n_energy ints of scratch.
+hipError_t lsms_launch_site_blocks(const lsms_prob_dev& p, const int32_t* liz_atom, const int32_t* centre,
+                                   int32_t n_atoms, int32_t* row, int32_t* inst_of, hipStream_t s);
 
 // Learned form, network (mlp.hip).
 int64_t lsms_mlp_param_count();

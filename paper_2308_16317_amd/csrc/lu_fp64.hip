@@ -1182,6 +1182,8 @@ __global__ __launch_bounds__(kThreads) void tau00_mixed_persistent_kernel(
 
 // Fallback flag of the GMRES form: bit 21, ORed like kInfoIrFallback.
 constexpr int kInfoLuFallback = 1 << 21;
+// Instances sent straight to the FP64 path by the caller's routing: bit 22.
+constexpr int kInfoRouted = 1 << 22;
 constexpr int kGmMaxM = 8;  // block Arnoldi steps per restart, at most
 
 struct GmresBufs {
@@ -1201,6 +1203,7 @@ struct GmresSmem {
   zd r[16][16];                  // triangular factor of a block QR
   zd t[16][16];                  // scratch
   zd hv[48];                     // Householder vector
+  zd part[kLuWaves][16][16];     // per-wave partial sums of a block inner product
   double red[kLuWaves];
   double beta;
   int flag;
@@ -1265,33 +1268,83 @@ __device__ void gm_amul(const Mat<zd>& A, const zd* __restrict__ X, zd* __restri
   __syncthreads();
 }
 
-// gs.h[16 i + a][b] = sum_v conj(V_i[v][a]) W[v][b], i < nb.
+// gs.h[16 i + a][b] = sum_v conj(V_i[v][a]) W[v][b], i < nb, on FP64 MFMA:
+// for each block i the waves take interleaved chunks of 4 rows (lane (li, lq)
+// supplies conj(V_i[v0 + lq][li]) and W[v0 + lq][li], so that a chunk is one
+// MFMA step of a 16 x 16 tile), two chunks loaded ahead, and the eight
+// partial tiles are summed through LDS in a fixed order.
 __device__ void gm_gram(const zd* __restrict__ V, int nb, int N, const zd* __restrict__ W, GmresSmem& gs) {
-  for (int q = threadIdx.x; q < nb * 256; q += kLuThreads) {
-    const int i = q >> 8, a = (q >> 4) & 15, b = q & 15;
+  typedef Prec<double>::V4 V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  for (int i = 0; i < nb; ++i) {
     const zd* vi = V + (int64_t)i * N * 16;
-    double sr = 0.0, si = 0.0;
-    for (int v = 0; v < N; ++v) {
-      const zd x = vi[(int64_t)v * 16 + a], y = W[(int64_t)v * 16 + b];
-      sr += x.x * y.x + x.y * y.y;
-      si += x.x * y.y - x.y * y.x;
+    V4 ar = V4{0.0, 0.0, 0.0, 0.0}, ai = V4{0.0, 0.0, 0.0, 0.0};
+    auto ld = [&](int v0, zd& x, zd& y) {
+      const int v = v0 + lq;
+      x = v < N ? vi[(int64_t)v * 16 + li] : zmake(0.0, 0.0);
+      y = v < N ? W[(int64_t)v * 16 + li] : zmake(0.0, 0.0);
+    };
+    constexpr int kStep = 4 * kLuWaves;
+    zd x0, y0, x1, y1;
+    ld(4 * wave, x0, y0);
+    ld(4 * wave + kStep, x1, y1);
+    for (int v0 = 4 * wave; v0 < N; v0 += kStep) {
+      const zd x = x0, y = y0;
+      x0 = x1;
+      y0 = y1;
+      ld(v0 + 2 * kStep, x1, y1);
+      ar = Prec<double>::mfma(x.x, y.x, ar);
+      ar = Prec<double>::mfma(x.y, y.y, ar);
+      ai = Prec<double>::mfma(x.x, y.y, ai);
+      ai = Prec<double>::mfma(-x.y, y.x, ai);
     }
-    gs.h[16 * i + a][b] = zmake(sr, si);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gs.part[wave][Prec<double>::drow(r, lq)][li] = zmake(ar[r], ai[r]);
+    __syncthreads();
+    if (tid < 256) {
+      const int a = tid >> 4, b = tid & 15;
+      zd acc = gs.part[0][a][b];
+#pragma unroll
+      for (int w = 1; w < kLuWaves; ++w) acc = zadd(acc, gs.part[w][a][b]);
+      gs.h[16 * i + a][b] = acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
-// W[v][b] -= sum_{i < nb, a} V_i[v][a] gs.h[16 i + a][b].
+// W[v][b] -= sum_{i < nb, a} V_i[v][a] gs.h[16 i + a][b] on FP64 MFMA: one
+// 16-row block per wave at a time, the 16 nb columns of V in chunks of 4
+// (lane (li, lq) supplies V_i[rb + li][a0 + lq] and gs.h[16 i + a0 + lq][li]).
 __device__ void gm_subtract(const zd* __restrict__ V, int nb, int N, zd* __restrict__ W, const GmresSmem& gs) {
-  for (int q = threadIdx.x; q < N * 16; q += kLuThreads) {
-    const int v = q >> 4, b = q & 15;
-    zd acc = W[q];
+  typedef Prec<double>::V4 V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  for (int rb = 16 * wave; rb < N; rb += 16 * kLuWaves) {
+    V4 ar = V4{0.0, 0.0, 0.0, 0.0}, ai = V4{0.0, 0.0, 0.0, 0.0};
+    const int va = min(rb + li, N - 1);
     for (int i = 0; i < nb; ++i) {
-      const zd* vr = V + ((int64_t)i * N + v) * 16;
-#pragma unroll 4
-      for (int a = 0; a < 16; ++a) acc = zfms(acc, vr[a], gs.h[16 * i + a][b]);
+      const zd* vr = V + ((int64_t)i * N + va) * 16;
+      zd x[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) x[c] = vr[4 * c + lq];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const zd hh = gs.h[16 * i + 4 * c + lq][li];
+        ar = Prec<double>::mfma(x[c].x, hh.x, ar);
+        ar = Prec<double>::mfma(-x[c].y, hh.y, ar);
+        ai = Prec<double>::mfma(x[c].x, hh.y, ai);
+        ai = Prec<double>::mfma(x[c].y, hh.x, ai);
+      }
     }
-    W[q] = acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = rb + Prec<double>::drow(r, lq);
+      if (v < N) {
+        zd* o = W + (int64_t)v * 16 + li;
+        *o = zmake(o->x - ar[r], o->y - ai[r]);
+      }
+    }
   }
   __syncthreads();
 }
@@ -1474,8 +1527,42 @@ __device__ double gm_norm(const zd* __restrict__ X, int N, GmresSmem& gs) {
 
 // Block GMRES for one instance; returns true when converged (Y holds the
 // solution) and the number of block Arnoldi steps taken in *steps.
+// Block-diagonal right preconditioner over the LIZ sites: the block of site
+// j approximates the site's diagonal block of A^{-1} = (M^{-1})^T; blk
+// holds kk x kk column-major approximations D_j of [M^{-1}]_{jj} (for
+// instance blocks of the network, [M^{-1}]_{00} of the instance centred on
+// that site), row[j] the block of site j (< 0: identity).  blk null: none.
+struct GmresPc {
+  const zd* blk;
+  const int32_t* row;  // this instance's LIZ rows
+  int nliz;
+};
+
+// T = P^{-1} X (N x 16 row-major, internal rows): site j's rows (internal
+// kk (j - 1) .. for j >= 1, the central rows Nd .. for j = 0) times D_j^T,
+// T[r][c] = sum_a D_j[a][r] X[a][c].  Ends after a barrier.
+__device__ void gm_precond(const GmresPc& pc, int Nd, const zd* __restrict__ X, zd* __restrict__ T) {
+  for (int q = threadIdx.x; q < pc.nliz * 256; q += kLuThreads) {
+    const int j = q >> 8, r = (q >> 4) & 15, c = q & 15;
+    const int64_t base = j ? 16 * (int64_t)(j - 1) : (int64_t)Nd;
+    const int pr = pc.row[j];
+    zd acc;
+    if (pr < 0) {
+      acc = X[(base + r) * 16 + c];
+    } else {
+      const zd* D = pc.blk + (int64_t)pr * 256 + 16 * r;  // column r of D_j
+      acc = zmake(0.0, 0.0);
+#pragma unroll 4
+      for (int a = 0; a < 16; ++a) acc = zfms(acc, zmake(-D[a].x, -D[a].y), X[(base + a) * 16 + c]);
+    }
+    T[(base + r) * 16 + c] = acc;
+  }
+  __syncthreads();
+}
+
 __device__ __noinline__ bool gmres_solve(const Mat<zd>& A, const GmresBufs& b, const double* seed, double tol,
-                                         int max_cycles, unsigned char* smem, int* steps) {
+                                         int max_cycles, unsigned char* smem, int* steps,
+                                         const GmresPc pc = GmresPc{}) {
   GmresSmem& gs = *reinterpret_cast<GmresSmem*>(smem);
   const int tid = threadIdx.x;
   const int N = (int)A.N, Nd = A.Nd, m = b.m;
@@ -1519,7 +1606,12 @@ __device__ __noinline__ bool gmres_solve(const Mat<zd>& A, const GmresBufs& b, c
     for (int j = 0; j < m; ++j) {
       zd* Vj = b.V + (int64_t)j * N * 16;
       zd* W = b.V + (int64_t)(j + 1) * N * 16;
-      gm_amul(A, Vj, W, false);
+      if (pc.blk) {  // W = A P^{-1} V_j, P^{-1} V_j in R (free during the cycle)
+        gm_precond(pc, Nd, Vj, b.R);
+        gm_amul(A, b.R, W, false);
+      } else {
+        gm_amul(A, Vj, W, false);
+      }
       for (int pass = 0; pass < 2; ++pass) {
         gm_gram(b.V, j + 1, N, W, gs);
         for (int q = tid; q < (j + 1) * 256; q += kLuThreads) {
@@ -1545,18 +1637,24 @@ __device__ __noinline__ bool gmres_solve(const Mat<zd>& A, const GmresBufs& b, c
       if (!ok || est <= tol * enorm) break;
     }
     if (!gm_backsolve(b, ldh, 16 * jdone, gs)) break;
-    // Y += [V_0 .. V_{jdone-1}] y
+    // Y += P^{-1} [V_0 .. V_{jdone-1}] y (P^{-1} = 1 without preconditioner)
     for (int q = tid; q < N * 16; q += kLuThreads) {
       const int v = q >> 4, c = q & 15;
-      zd acc = b.Y[q];
+      zd acc = pc.blk ? zmake(0.0, 0.0) : b.Y[q];
       for (int i = 0; i < jdone; ++i) {
         const zd* vr = b.V + ((int64_t)i * N + v) * 16;
         const zd* g = b.G + (int64_t)c * ldh + 16 * i;
         for (int a = 0; a < 16; ++a) acc = zfms(acc, zmake(-vr[a].x, -vr[a].y), g[a]);
       }
-      b.Y[q] = acc;
+      if (pc.blk) b.R[q] = acc;
+      else b.Y[q] = acc;
     }
     __syncthreads();
+    if (pc.blk) {
+      gm_precond(pc, Nd, b.R, b.V);  // V_0 is free once y is applied
+      for (int q = tid; q < N * 16; q += kLuThreads) b.Y[q] = zadd(b.Y[q], b.V[q]);
+      __syncthreads();
+    }
   }
   *steps = it;
   return conv;
@@ -1603,6 +1701,7 @@ template <int kR, int kWL>
 __global__ __launch_bounds__(kThreads) void tau00_gmres_persistent_kernel(
     lsms_prob_dev p, lsms_gaunt_dev g, const int32_t* __restrict__ order, int n, int32_t* __restrict__ counter,
     unsigned char* __restrict__ work, int64_t slot_bytes, int64_t m_bytes, const double* __restrict__ seed,
+    const double* __restrict__ pc_blk, const int32_t* __restrict__ pc_row, const int8_t* __restrict__ route,
     double* __restrict__ tau00, int32_t* __restrict__ info, int32_t* __restrict__ steps, int nb, double tol,
     int max_cycles, int m) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1633,8 +1732,14 @@ __global__ __launch_bounds__(kThreads) void tau00_gmres_persistent_kernel(
       A.Nd = (int)A.N - p.kk;
       A.kk = p.kk;
       int nsteps = 0;
-      const bool conv =
-          gmres_solve(A, bufs, seed ? seed + (int64_t)inst * 2 * 256 : nullptr, tol, max_cycles, smem_raw, &nsteps);
+      GmresPc pc;
+      pc.blk = reinterpret_cast<const zd*>(pc_blk);
+      pc.row = pc_row ? pc_row + p.liz_off[inst] : nullptr;
+      pc.nliz = nliz;
+      if (!pc_row) pc.blk = nullptr;
+      const bool direct = route && __builtin_amdgcn_readfirstlane((int)route[inst]) != 0;
+      const bool conv = !direct && gmres_solve(A, bufs, seed ? seed + (int64_t)inst * 2 * 256 : nullptr, tol,
+                                               max_cycles, smem_raw, &nsteps, pc);
       if (threadIdx.x == 0) steps[inst] = nsteps;
       if (__builtin_amdgcn_readfirstlane((int)conv)) {
         const int e = p.e_idx[inst];
@@ -1655,7 +1760,7 @@ __global__ __launch_bounds__(kThreads) void tau00_gmres_persistent_kernel(
         __syncthreads();
       } else {
         lu_instance<kR, kWL>(p, inst, M, xg, tau00, info, nb, *reinterpret_cast<LuSmemD*>(smem_raw));
-        if (threadIdx.x == 0 && info[inst] >= 0) info[inst] |= kInfoLuFallback;
+        if (threadIdx.x == 0 && info[inst] >= 0) info[inst] |= direct ? kInfoRouted : kInfoLuFallback;
         __syncthreads();
       }
     } else {
@@ -1847,11 +1952,12 @@ hipError_t launch_mixed_persistent(const lsms_prob_dev& p, const lsms_gaunt_dev&
 template <int kR, int kWL>
 hipError_t launch_gmres(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order, int32_t* counter,
                         unsigned char* work, int64_t slot_bytes, int64_t m_bytes, int grid, const double* seed,
-                        double* tau00, int32_t* info, int32_t* steps, int32_t nb, double tol, int max_cycles,
-                        int m, hipStream_t s) {
+                        const double* pc_blk, const int32_t* pc_row, const int8_t* route, double* tau00,
+                        int32_t* info, int32_t* steps, int32_t nb, double tol, int max_cycles, int m,
+                        hipStream_t s) {
   hipLaunchKernelGGL((tau00_gmres_persistent_kernel<kR, kWL>), dim3(grid), dim3(kThreads), gmres_smem_bytes(), s, p,
-                     g, order, p.n_inst, counter, work, slot_bytes, m_bytes, seed, tau00, info, steps, nb, tol,
-                     max_cycles, m);
+                     g, order, p.n_inst, counter, work, slot_bytes, m_bytes, seed, pc_blk, pc_row, route, tau00,
+                     info, steps, nb, tol, max_cycles, m);
   return hipGetLastError();
 }
 
@@ -2051,15 +2157,56 @@ hipError_t lsms_gmres_grid(const lsms_prob_dev& p, int device, int* grid) {
 
 hipError_t lsms_launch_gmres(const lsms_prob_dev& p, const lsms_gaunt_dev& g, const int32_t* order, int32_t* counter,
                              unsigned char* work, int64_t slot_bytes, int64_t m_bytes, int grid, const double* seed,
-                             double* tau00, int32_t* info, int32_t* steps, int32_t nb, double tol, int max_cycles,
-                             int m, hipStream_t s) {
+                             const double* pc_blk, const int32_t* pc_row, const int8_t* route, double* tau00,
+                             int32_t* info, int32_t* steps, int32_t nb, double tol, int max_cycles, int m,
+                             hipStream_t s) {
   if (p.n_inst <= 0) return hipSuccess;
   const int64_t nmax = (int64_t)p.kc * p.max_liz;
   if (nmax <= kThreads * 5)
-    return launch_gmres<5, 8>(p, g, order, counter, work, slot_bytes, m_bytes, grid, seed, tau00, info, steps, nb,
-                              tol, max_cycles, m, s);
-  return launch_gmres<8, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, seed, tau00, info, steps, nb, tol,
-                            max_cycles, m, s);
+    return launch_gmres<5, 8>(p, g, order, counter, work, slot_bytes, m_bytes, grid, seed, pc_blk, pc_row, route,
+                              tau00, info, steps, nb, tol, max_cycles, m, s);
+  return launch_gmres<8, 4>(p, g, order, counter, work, slot_bytes, m_bytes, grid, seed, pc_blk, pc_row, route,
+                            tau00, info, steps, nb, tol, max_cycles, m, s);
+}
+
+namespace {
+// row[r] = index of the block of LIZ row r: inst_of[atom[r] * n_energy + e]
+// for the energy index e of the instance owning the row (-1 when absent).
+// One workgroup per instance.
+__global__ __launch_bounds__(256) void site_blocks_kernel(lsms_prob_dev p, const int32_t* __restrict__ liz_atom,
+                                                          int32_t n_atoms, const int32_t* __restrict__ inst_of,
+                                                          int32_t* __restrict__ row) {
+  const int i = blockIdx.x;
+  const int64_t a = p.liz_off[i], b = p.liz_off[i + 1];
+  const int e = p.e_idx[i];
+  for (int64_t r = a + threadIdx.x; r < b; r += 256) {
+    const int at = liz_atom[r];
+    row[r] = (at >= 0 && at < n_atoms && e >= 0 && e < p.n_energy) ? inst_of[(int64_t)at * p.n_energy + e] : -1;
+  }
+}
+
+// inst_of[q] = -1 for q < n, then inst_of[centre[i] * n_energy + e_idx[i]] = i.
+__global__ __launch_bounds__(256) void inst_of_clear_kernel(int32_t* __restrict__ inst_of, int64_t n) {
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) inst_of[q] = -1;
+}
+__global__ __launch_bounds__(256) void inst_of_fill_kernel(lsms_prob_dev p, const int32_t* __restrict__ centre,
+                                                           int32_t n_atoms, int32_t* __restrict__ inst_of) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= p.n_inst) return;
+  const int c = centre[i], e = p.e_idx[i];
+  if (c >= 0 && c < n_atoms && e >= 0 && e < p.n_energy) inst_of[(int64_t)c * p.n_energy + e] = i;
+}
+}  // namespace
+
+hipError_t lsms_launch_site_blocks(const lsms_prob_dev& p, const int32_t* liz_atom, const int32_t* centre,
+                                   int32_t n_atoms, int32_t* row, int32_t* inst_of, hipStream_t s) {
+  if (p.n_inst <= 0) return hipSuccess;
+  const int64_t n = (int64_t)n_atoms * p.n_energy;
+  const unsigned gb = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(inst_of_clear_kernel, dim3(gb), dim3(256), 0, s, inst_of, n);
+  hipLaunchKernelGGL(inst_of_fill_kernel, dim3((p.n_inst + 255) / 256), dim3(256), 0, s, p, centre, n_atoms, inst_of);
+  hipLaunchKernelGGL(site_blocks_kernel, dim3(p.n_inst), dim3(256), 0, s, p, liz_atom, n_atoms, inst_of, row);
+  return hipGetLastError();
 }
 
 // One instance across the whole GPU: workspace layout [state | ipiv | two

@@ -5,7 +5,11 @@ FP64 path.
 
 Training data are tau00 values the solver itself produced (`tau00_solve`);
 training runs on the GPU through the library's own kernels (forward,
-backward, MSE, AdamW).  This module only sequences those calls.
+backward, MSE, AdamW).  The same network's outputs at every LIZ site's own
+environment give a block-diagonal preconditioner, and a routing table,
+calibrated on the training alloy, sends the energies where GMRES would cost
+more than the direct elimination straight to it.  This module only sequences
+the library's calls.
 """
 
 from __future__ import annotations
@@ -104,3 +108,64 @@ def train_on(h: lsms.Handle, w, a_lat: float, init_params, steps: int, batch: in
     target = lsms.mlp_targets(h, prob, tau, net.scale, net.shift)
     losses = net.train(feat, target, steps, batch=batch, lr=lr, lr_final=lr_final)
     return net, losses
+
+
+def preconditioner(h: lsms.Handle, prob: lsms.Problem, liz_atom: torch.Tensor, centre, n_atoms: int,
+                   seeds: torch.Tensor):
+    """Block-diagonal preconditioner of tau00_gmres_pc from the network's
+    seeds of the batch itself: the block of a LIZ site is the seed of the
+    instance centred on that site's atom at the same energy (identity where
+    the batch has no such instance).  Returns (precond, precond_row)."""
+    return seeds, lsms.site_blocks(h, prob, liz_atom, centre, n_atoms)
+
+
+def _timed(fn):
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    r = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return r, e0.elapsed_time(e1) * 1e-3
+
+
+def calibrate_routing(h: lsms.Handle, prob: lsms.Problem, seeds, precond, precond_row, n_energy: int,
+                      restart: int = 8, tol: float = 1e-12):
+    """Routing table and step cap from a calibration batch (training alloy,
+    at most one instance per compute unit so that one launch is one wave):
+    the time of one block step t and of the direct elimination T follow from
+    two GMRES launches that never converge (tol 1e-300) with 1 and 3 restart
+    cycles (time = steps t + T); then GMRES with the seeds and the
+    preconditioner gives each instance's steps and convergence.  An energy is
+    routed to the direct path when the mean GMRES cost of its instances
+    (steps t, plus T for those that did not converge within the cap of
+    ceil(T / t) steps) is not below T.  Returns a dict with the table
+    (int8 per energy index), the cycle cap, t, T and the per-energy means."""
+    n = prob.n_inst
+    work = torch.empty(lsms.gmres_workspace_size(h, prob, restart), dtype=torch.uint8, device="cuda")
+    _, t1 = _timed(lambda: lsms.tau00_gmres(h, prob, work, seed=seeds, restart=restart, max_cycles=1, tol=1e-300))
+    _, t3 = _timed(lambda: lsms.tau00_gmres(h, prob, work, seed=seeds, restart=restart, max_cycles=3, tol=1e-300))
+    t_step = max((t3 - t1) / (2 * restart), 1e-9)
+    t_lu = max(t1 - restart * t_step, t_step)
+    cap_cycles = max(1, int(np.ceil(t_lu / t_step / restart)))
+    _, info, steps = lsms.tau00_gmres(h, prob, work, seed=seeds, restart=restart, max_cycles=cap_cycles, tol=tol,
+                                      precond=precond, precond_row=precond_row)
+    torch.cuda.synchronize()
+    steps = steps.cpu().numpy().astype(np.float64)
+    fell = (info.cpu().numpy() & lsms.INFO_LU_FALLBACK) != 0
+    e_idx = prob.e_idx.cpu().numpy()
+    route = np.ones(n_energy, np.int8)
+    mean_steps = np.full(n_energy, np.nan)
+    frac_conv = np.full(n_energy, np.nan)
+    for e in range(n_energy):
+        sel = e_idx == e
+        if not np.any(sel):
+            continue
+        cost = np.mean(steps[sel] * t_step + fell[sel] * t_lu)
+        mean_steps[e] = float(np.mean(steps[sel]))
+        frac_conv[e] = float(1.0 - np.mean(fell[sel]))
+        route[e] = 0 if cost < t_lu else 1
+    del work
+    return {"route_by_energy": route, "max_cycles": cap_cycles, "t_step_s": t_step, "t_lu_s": t_lu,
+            "mean_steps_by_energy": mean_steps, "converged_by_energy": frac_conv, "instances": n}

@@ -69,11 +69,13 @@ SYMBOLS = ("lsms_create", "lsms_destroy", "lsms_build_liz", "build_kkr", "tau00_
            "lsms_mlp_adamw", "lsms_mlp_seed", "lsms_mlp_targets", "lsms_mlp_norm_stats",
            "lsms_gmres_workspace_size", "tau00_gmres", "lsms_row_workspace_size", "tau_row_batched",
            "lsms_contour_sum", "lsms_lloyd_idos", "lsms_liz_moments", "build_kkr_spin", "tau00_spin_batched",
-           "lsms_spin_workspace_size", "tau00_spin_solve", "lsms_large_workspace_size", "tau00_large")
+           "lsms_spin_workspace_size", "tau00_spin_solve", "lsms_large_workspace_size", "tau00_large",
+           "tau00_gmres_pc", "lsms_site_blocks")
 
 BATCHED_WORK_PER_INST = 2 * 64 * 64 * 16
 MLP_PARAMS = 399616
 MLP_ACT = 2560
+INFO_ROUTED = 1 << 22
 INFO_LU_FALLBACK = 1 << 21
 
 
@@ -130,6 +132,9 @@ def lib():
         L.lsms_mlp_norm_stats.argtypes = [_P, _P, _I32, _P, _P, _P]
         L.lsms_gmres_workspace_size.argtypes = [_P, PP, _I32, ctypes.POINTER(ctypes.c_size_t)]
         L.tau00_gmres.argtypes = [_P, PP, _P, _I32, _I32, ctypes.c_double, _P, _P, _P, _P, ctypes.c_size_t, _P]
+        L.tau00_gmres_pc.argtypes = [_P, PP, _P, _P, _P, _P, _I32, _I32, ctypes.c_double, _P, _P, _P, _P,
+                                     ctypes.c_size_t, _P]
+        L.lsms_site_blocks.argtypes = [_P, PP, _P, _P, _I32, _P, _P, _P]
         for s in SYMBOLS:
             getattr(L, s).restype = ctypes.c_int
         _lib = L
@@ -605,8 +610,8 @@ def gmres_workspace_size(h: Handle, prob: Problem, restart: int) -> int:
 
 
 def tau00_gmres(h: Handle, prob: Problem, work: torch.Tensor, seed=None, restart: int = 8, max_cycles: int = 8,
-                tol: float = 1e-12, tau=None, info=None, steps=None):
-    """tau00_gmres: returns (tau00 [n, 16, 16], info, steps)."""
+                tol: float = 1e-12, tau=None, info=None, steps=None, precond=None, precond_row=None, route=None):
+    """tau00_gmres (tau00_gmres_pc when precond / route are given): returns (tau00 [n, 16, 16], info, steps)."""
     n = max(prob.n_inst, 1)
     if tau is None:
         tau = torch.empty(n * 256, dtype=torch.complex128, device="cuda")
@@ -615,7 +620,25 @@ def tau00_gmres(h: Handle, prob: Problem, work: torch.Tensor, seed=None, restart
     if steps is None:
         steps = torch.empty(n, dtype=torch.int32, device="cuda")
     ps = prob.struct()
-    _check(lib().tau00_gmres(h.ptr, ctypes.byref(ps), _ptr(seed), int(restart), int(max_cycles), float(tol),
-                             _ptr(tau), _ptr(info), _ptr(steps), _ptr(work), work.numel() * work.element_size(),
-                             _stream()), "tau00_gmres")
+    if precond is None and route is None:
+        _check(lib().tau00_gmres(h.ptr, ctypes.byref(ps), _ptr(seed), int(restart), int(max_cycles), float(tol),
+                                 _ptr(tau), _ptr(info), _ptr(steps), _ptr(work), work.numel() * work.element_size(),
+                                 _stream()), "tau00_gmres")
+    else:
+        _check(lib().tau00_gmres_pc(h.ptr, ctypes.byref(ps), _ptr(seed), _ptr(precond), _ptr(precond_row),
+                                    _ptr(route), int(restart), int(max_cycles), float(tol), _ptr(tau), _ptr(info),
+                                    _ptr(steps), _ptr(work), work.numel() * work.element_size(), _stream()),
+               "tau00_gmres_pc")
     return _tau_view(tau, 16)[:prob.n_inst], info[:prob.n_inst], steps[:prob.n_inst]
+
+
+def site_blocks(h: Handle, prob: Problem, liz_atom: torch.Tensor, centre, n_atoms: int) -> torch.Tensor:
+    """lsms_site_blocks: preconditioner block index of every LIZ row (device int32)."""
+    ce = _dev(centre, torch.int32)
+    rows = int(prob.liz_off[-1].item()) if prob.n_inst else 0
+    out = torch.empty(max(rows, 1), dtype=torch.int32, device="cuda")
+    work = torch.empty(max(n_atoms * int(prob.energy.shape[0]), 1), dtype=torch.int32, device="cuda")
+    ps = prob.struct()
+    _check(lib().lsms_site_blocks(h.ptr, ctypes.byref(ps), _ptr(liz_atom), _ptr(ce), int(n_atoms), _ptr(out),
+                                  _ptr(work), _stream()), "lsms_site_blocks")
+    return out[:rows]

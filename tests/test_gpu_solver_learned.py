@@ -161,34 +161,134 @@ def test_gmres_full_size_sample(P, h):
     assert err[info != 0].max(initial=0.0) <= 1e-12
 
 
+def _all_centre_batch(w, energies):
+    """Every atom of the supercell as a centre at each of `energies`: the
+    batch holds a block for every LIZ site of every instance."""
+    import dataclasses
+
+    n_at = w.atom_pos.shape[0]
+    centre = np.repeat(np.arange(n_at), len(energies)).astype(np.int32)
+    e_idx = np.tile(np.asarray(energies), n_at).astype(np.int32)
+    return dataclasses.replace(w, centre=centre, rc=np.full(centre.size, float(w.rc[0])), e_idx=e_idx)
+
+
+def test_gmres_preconditioner_and_routing(P, h):
+    # blocks from the direct solution of the batch itself ([M^-1]_00 of the
+    # instance centred on each site): GMRES with them converges to the oracle
+    # (on these 13-site LIZs the centred block is a poor stand-in for an edge
+    # site's own diagonal block, and the steps are printed, not compared);
+    # routed instances take the FP64 path
+    torch = _torch()
+    from paper_2308_16317_amd import learned
+
+    w = _all_centre_batch(inputs.config1(), [0, 5, 10, 15])  # 32 atoms x 4 energies
+    ref, rinfo = oracle.tau00_workload(w)
+    prob = P.problem_for_workload(h, w)
+    tau_d = learned.solve_direct(h, prob).cpu().numpy().reshape(-1, 16, 16).transpose(0, 2, 1)
+    lv = np.floor(np.sqrt(np.arange(16)) + 1e-9).astype(int)
+    t0 = np.stack([oracle.tmat(3, w.energies[w.e_idx[i]], w.delta[w.atom_species[w.centre[i]], w.e_idx[i]])[lv]
+                   for i in range(w.n_inst)])
+    D = tau_d / t0[:, None, :]  # [M^-1]_00, natural indexing
+    blocks = torch.as_tensor(np.ascontiguousarray(D.transpose(0, 2, 1)).reshape(-1)).to("cuda")
+    liz = P.build_liz(h, w.atom_pos, w.atom_species, w.box, w.centre, w.rc, 1024, with_atoms=True)
+    rows = int(prob.liz_off[-1].item())
+    prow = P.site_blocks(h, prob, liz["atom"][:rows], w.centre, w.atom_pos.shape[0])
+    assert int((prow < 0).sum().item()) == 0
+    work = torch.empty(P.gmres_workspace_size(h, prob, 8), dtype=torch.uint8, device="cuda")
+    out = {}
+    for name, kw in (("none", {}), ("blocks", dict(precond=blocks, precond_row=prow))):
+        tau, info, steps = P.tau00_gmres(h, prob, work, restart=8, max_cycles=20, tol=1e-12, **kw)
+        torch.cuda.synchronize()
+        tau, info, steps = tau.cpu().numpy(), info.cpu().numpy(), steps.cpu().numpy()
+        err = _err(tau, ref, w)
+        print(f"preconditioner {name}: mean steps {steps.mean():.2f}, converged {(info == 0).mean():.2f}, "
+              f"max rel_F {err.max():.2e}")
+        assert np.all((info == 0) | (info == P.INFO_LU_FALLBACK))
+        assert err[info == 0].max(initial=0.0) <= 1e-10 and err[info != 0].max(initial=0.0) <= 1e-12
+        out[name] = steps
+    # routing: every other instance straight to the FP64 path
+    route = torch.as_tensor((np.arange(w.n_inst) % 2).astype(np.int8)).to("cuda")
+    tau, info, steps = P.tau00_gmres(h, prob, work, restart=8, max_cycles=20, tol=1e-12, route=route)
+    torch.cuda.synchronize()
+    tau, info, steps = tau.cpu().numpy(), info.cpu().numpy(), steps.cpu().numpy()
+    r = np.arange(w.n_inst) % 2 == 1
+    assert np.all(info[r] == P.INFO_ROUTED) and np.all(steps[r] == 0)
+    assert np.all(info[~r] != P.INFO_ROUTED)
+    err = _err(tau, ref, w)
+    assert err[r].max() <= 1e-12 and err[~r][info[~r] == 0].max(initial=0.0) <= 1e-10
+
+
 def test_trained_seed_reduces_gmres_steps(P, h):
     """Train the network on tau00 the direct solver produced for a different
-    random alloy (seed 1), then solve instances of the evaluation alloy
-    (seed 0) by GMRES with the trained seed, with the untrained network's
-    seed and with no seed; the direct FP64 path is the reference."""
+    random alloy (seed 1), then solve the evaluation alloy (seed 0, every site
+    at five energies across the contour, so that every LIZ site has its own
+    block) by GMRES: no seed, the untrained network (its output is the
+    training-set mean after the normalisation), the trained network, each
+    with and without the block-diagonal preconditioner built from the same
+    network's outputs.  The direct FP64 path is the reference."""
     torch = _torch()
     from paper_2308_16317_amd import learned
 
     net, losses = learned.train_on(h, inputs.config2(seed=1), inputs.A_LAT, inputs.mlp_init(seed=0), steps=3000)
     print("training loss: first", losses[0], "last 50 mean", np.mean(losses[-50:]))
     assert np.mean(losses[-50:]) < 0.6 * losses[0]
-    w = inputs.subset(inputs.config2(seed=0), np.arange(5, 8192, 131))  # 63 instances, all energies
+    w = _all_centre_batch(inputs.config2(seed=0), [4, 8, 12, 16, 20])
     prob = P.problem_for_workload(h, w)
     ref = learned.solve_direct(h, prob).cpu().numpy().reshape(-1, 16, 16).transpose(0, 2, 1)
     feat = P.mlp_features(h, prob, inputs.A_LAT)
-    seeds = {"trained": net.seeds(feat), "none": None}
     net0 = learned.SeedNet(h, inputs.mlp_init(seed=0))
     net0.scale, net0.shift = net.scale, net.shift
-    seeds["untrained"] = net0.seeds(feat)
+    sd = {"trained": net.seeds(feat), "mean": net0.seeds(feat)}
+    liz = P.build_liz(h, w.atom_pos, w.atom_species, w.box, w.centre, w.rc, 1024, with_atoms=True)
+    prow = P.site_blocks(h, prob, liz["atom"][:int(prob.liz_off[-1].item())], w.centre, w.atom_pos.shape[0])
+    work = torch.empty(P.gmres_workspace_size(h, prob, 8), dtype=torch.uint8, device="cuda")
+    variants = {"none": {}, "mean": dict(seed=sd["mean"]), "trained": dict(seed=sd["trained"]),
+                "mean+pc": dict(seed=sd["mean"], precond=sd["mean"], precond_row=prow),
+                "trained+pc": dict(seed=sd["trained"], precond=sd["trained"], precond_row=prow)}
     res = {}
-    for k, sd in seeds.items():
-        tau, info, steps = _gmres(P, h, w, seed=sd)
+    for k, kw in variants.items():
+        tau, info, steps = P.tau00_gmres(h, prob, work, restart=8, max_cycles=20, tol=1e-12, **kw)
+        torch.cuda.synchronize()
+        tau, info, steps = tau.cpu().numpy(), info.cpu().numpy(), steps.cpu().numpy()
         err = _err(tau, ref, w)
         res[k] = (steps, info)
-        print(f"seed={k}: mean steps {steps.mean():.2f}, fallbacks {int((info != 0).sum())}, max rel_F {err.max():.2e}")
+        print(f"{k}: mean steps {steps.mean():.2f}, fallbacks {int((info != 0).sum())}, max rel_F {err.max():.2e}")
         assert np.all((info == 0) | (info == P.INFO_LU_FALLBACK))
         assert err[info == 0].max(initial=0.0) <= 1e-10
-    conv = (res["trained"][1] == 0) & (res["none"][1] == 0)
-    print("jointly converged", int(conv.sum()), "mean steps trained / untrained / none:",
-          res["trained"][0][conv].mean(), res["untrained"][0][conv].mean(), res["none"][0][conv].mean())
-    assert res["trained"][0][conv].mean() < res["none"][0][conv].mean()
+    conv = np.logical_and.reduce([v[1] == 0 for v in res.values()])
+    means = {k: float(v[0][conv].mean()) for k, v in res.items()}
+    print("jointly converged", int(conv.sum()), "mean steps:", means)
+    assert conv.sum() >= 0.5 * w.n_inst
+    # what the network gains: its seed and its per-site preconditioner cut
+    # the block steps below the unseeded, unpreconditioned solve, and the
+    # trained network's per-site blocks beat the untrained network's (the
+    # training-set mean) by at least one block step on average (measured:
+    # 38.8 against 42.3)
+    assert means["trained"] < means["none"]
+    assert means["trained+pc"] < means["trained"]
+    assert means["trained+pc"] <= means["mean+pc"] - 1.0
+
+
+@pytest.mark.xfail(strict=False, reason="negative result: as a seed alone the trained network is no better than "
+                                        "the training-set mean (31.4 against 31.2 block steps measured); its gain "
+                                        "shows through the preconditioner (test above)")
+def test_training_beats_mean_seed(P, h):
+    """Training against the untrained network (the training-set mean), seed
+    only: the trained seed would save at least one block step on average."""
+    torch = _torch()
+    from paper_2308_16317_amd import learned
+
+    net, _ = learned.train_on(h, inputs.config2(seed=1), inputs.A_LAT, inputs.mlp_init(seed=0), steps=3000)
+    w = _all_centre_batch(inputs.config2(seed=0), [8, 16])
+    prob = P.problem_for_workload(h, w)
+    feat = P.mlp_features(h, prob, inputs.A_LAT)
+    net0 = learned.SeedNet(h, inputs.mlp_init(seed=0))
+    net0.scale, net0.shift = net.scale, net.shift
+    work = torch.empty(P.gmres_workspace_size(h, prob, 8), dtype=torch.uint8, device="cuda")
+    st = {}
+    for k, n_ in (("trained", net), ("mean", net0)):
+        _, info, steps = P.tau00_gmres(h, prob, work, seed=n_.seeds(feat), restart=8, max_cycles=20, tol=1e-12)
+        torch.cuda.synchronize()
+        st[k] = steps.cpu().numpy().astype(float)
+    print("mean block steps: trained", st["trained"].mean(), "mean seed", st["mean"].mean())
+    assert st["trained"].mean() <= st["mean"].mean() - 1.0
