@@ -2237,6 +2237,9 @@ hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* wor
       hipLaunchKernelGGL((big_panel_kernel<5, 8>), dim3(1), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k), state);
     else if (N <= kThreads * 8)
       hipLaunchKernelGGL((big_panel_kernel<8, 4>), dim3(1), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k), state);
+    else if (N <= kThreads * 13)
+      hipLaunchKernelGGL((big_panel_kernel<13, 4>), dim3(1), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k),
+                         state);
     else
       hipLaunchKernelGGL((big_panel_kernel<16, 2>), dim3(1), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k),
                          state);
@@ -2278,6 +2281,7 @@ hipError_t lsms_prepare_big_kernels() {
   hipError_t e;
   if ((e = hipFuncSetAttribute((const void*)big_panel_kernel<5, 8>, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)big_panel_kernel<8, 4>, attr, a)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)big_panel_kernel<13, 4>, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)big_panel_kernel<16, 2>, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)big_u12_kernel, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)big_gemm_kernel, attr, a)) != hipSuccess) return e;
