@@ -288,7 +288,11 @@ int tau00_spin_solve(lsms_handle_t h, const lsms_problem *p, const lsms_spin *sp
  * columns one workgroup factorises the panel (partial pivoting among the
  * non-central rows, as tau00_batched), then one workgroup per 64-column
  * strip applies the interchanges and forms U12, and one per (strip, 512
- * rows) applies the MFMA update; the next panel is factorised while the rest
+ * rows) applies the MFMA update; the panel itself is factorised by
+ * ceil(rows / 128) workgroups together (each holding 128 of its rows in LDS,
+ * one grid barrier per column for the pivot choice; the workgroups of a
+ * panel are at most 64, one per compute unit, and every barrier wait gives up
+ * after a bounded number of polls); the next panel is factorised while the rest
  * of the update runs (one panel of look-ahead, on a second stream of the
  * handle, joined back to `stream` before the call's last kernel).
  *   p        n_inst = 1, the instance's LIZ exactly max_liz sites (info -3
@@ -297,12 +301,19 @@ int tau00_spin_solve(lsms_handle_t h, const lsms_problem *p, const lsms_spin *sp
  *   M        device complex N x N column-major (build_kkr / build_kkr_spin with
  *            m_off = 0); overwritten
  *   opts     FP64 only, nb 0 or 64, no flags (-5 otherwise)
- *   tau00, info  device, one instance (as tau00_batched / tau00_spin_batched)
+ *   tau00, info  device, one instance (as tau00_batched / tau00_spin_batched);
+ *            info -4 when a barrier wait gave up (lsms_large_set_spin_limit)
  *   work     device, lsms_large_workspace_size bytes (pivots, two 64 x 64
  *            blocks; -8 when NULL, -9 when too small)
  * Calls on one handle must not overlap in time (they share the second stream
  * and its events). */
 int lsms_large_workspace_size(lsms_handle_t h, const lsms_problem *p, const lsms_spin *spin, size_t *bytes);
+/* Polls of one grid-barrier wait of tau00_large's panel kernel before it
+ * gives up (0: the default, several seconds).  A wait that gives up makes
+ * every workgroup of that panel and every later panel leave at once, and the
+ * instance reports info -4 with tau00 NaN; all kernels still end normally.
+ * Errors: -2 polls < 0. */
+int lsms_large_set_spin_limit(lsms_handle_t h, int64_t polls);
 int tau00_large(lsms_handle_t h, const lsms_problem *p, const lsms_spin *spin, double *M, const lsms_opts *opts,
                 double *tau00, int32_t *info, void *work, size_t work_bytes, void *stream);
 

@@ -166,6 +166,7 @@ struct lsms_handle_s {
   // the first call)
   hipStream_t aux = nullptr;
   std::vector<hipEvent_t> big_ev;
+  int64_t big_spin = 0;  // polls of a grid-barrier wait, 0 = default
 };
 
 #define HIP_TRY(x)                          \
@@ -534,6 +535,7 @@ extern "C" int tau00_spin_solve(lsms_handle_t h, const lsms_problem* p, const ls
 }
 
 // ------------------------------------------------ one instance, whole GPU
+constexpr int64_t kBigSpinDefault = int64_t(1) << 22;  // polls (each with a short sleep): seconds
 int check_large(const lsms_problem* p, const lsms_spin* spin, const lsms_opts* opts) {
   int r = check_problem(p, spin ? 2 : 1);
   if (r) return r;
@@ -577,10 +579,18 @@ extern "C" int tau00_large(lsms_handle_t h, const lsms_problem* p, const lsms_sp
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return LSMS_EHIP;
     h->big_ev.push_back(e);
   }
-  return lsms_launch_big(d, M, (unsigned char*)work, tau00, info, 64, (hipStream_t)stream, h->aux,
+  const int64_t polls = h->big_spin > 0 ? h->big_spin : kBigSpinDefault;
+  return lsms_launch_big(d, M, (unsigned char*)work, tau00, info, 64, polls, (hipStream_t)stream, h->aux,
                          h->big_ev.data()) == hipSuccess
              ? 0
              : LSMS_EHIP;
+}
+
+extern "C" int lsms_large_set_spin_limit(lsms_handle_t h, int64_t polls) {
+  if (!h) return -1;
+  if (polls < 0) return -2;
+  h->big_spin = polls;
+  return 0;
 }
 
 // The allocation-free variant of tau00_batched: the same kernels, the

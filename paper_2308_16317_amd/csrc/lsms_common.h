@@ -167,8 +167,9 @@ hipError_t lsms_launch_lpt_order(const lsms_prob_dev& p, int32_t* order, hipStre
 // streams s0 (the caller's) and s1, and the kernels' LDS attributes.
 int64_t lsms_big_work_bytes(const lsms_prob_dev& p);
 int lsms_big_events(const lsms_prob_dev& p);
+// spin: polls of a grid-barrier wait before it gives up (info -4).
 hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* work, double* tau00, int32_t* info,
-                           int32_t nb, hipStream_t s0, hipStream_t s1, hipEvent_t* ev);
+                           int32_t nb, int64_t spin, hipStream_t s0, hipStream_t s1, hipEvent_t* ev);
 hipError_t lsms_prepare_big_kernels();
 
 // out[r][0..2] = src[idx[r]][0..2] (liz.hip): per-row moments of the LIZs.

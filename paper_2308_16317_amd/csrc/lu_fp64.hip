@@ -1782,9 +1782,10 @@ __global__ __launch_bounds__(kThreads) void tau00_gmres_persistent_kernel(
 // (A = M^T, pivots among the non-central rows, the central block last, then
 // Gauss-Jordan on the Schur block), split over many workgroups: per panel
 // of 64 columns
-//   big_panel_kernel: one workgroup factorises the panel (the recursive
-//     register-leaf panel_factor over all rows), writes its pivots and the
-//     inverse of its unit lower diagonal block;
+//   big_panel_coop_kernel: ceil(rows / 128) workgroups factorise the panel
+//     together, each holding 128 of its rows in LDS, with one grid barrier
+//     per column for the pivot choice; it writes the pivots and the inverse
+//     of the unit lower diagonal block;
 //   big_u12_kernel: one workgroup per 64-column strip of the trailing
 //     columns applies the panel's interchanges to the strip and forms
 //     U12 = L11^{-1} A12 (stored in A);
@@ -1813,27 +1814,192 @@ __device__ __forceinline__ BigView big_view(const lsms_prob_dev& p, double* Mb) 
 }
 
 // state[0] := 0, or -3 when the instance is not one of max_liz sites with a
-// valid energy index (its rank would differ from the planned N).
-__global__ void big_init_kernel(lsms_prob_dev p, int32_t* state) {
+// valid energy index (its rank would differ from the planned N); state[1]
+// (a barrier wait gave up) := 0; the panels' arrival counters := 0; the
+// pivots := the identity (a panel that gave up leaves them so).
+__global__ void big_init_kernel(lsms_prob_dev p, int32_t* state, int32_t* counters, int np, int32_t* ipiv, int N) {
+  for (int q = threadIdx.x; q < np; q += blockDim.x) counters[q] = 0;
+  for (int q = threadIdx.x; q < N; q += blockDim.x) ipiv[q] = q;  // no interchange until a panel writes one
   if (threadIdx.x != 0) return;
   const int64_t nliz = p.liz_off[1] - p.liz_off[0];
   const int e = p.e_idx[0];
   state[0] = (nliz != p.max_liz || e < 0 || e >= p.n_energy) ? -3 : 0;
+  state[1] = 0;
 }
 
-template <int kR, int kWL>
-__global__ __launch_bounds__(kThreads) void big_panel_kernel(lsms_prob_dev p, double* Mb, int c, int w,
-                                                             int32_t* __restrict__ ipiv, double* __restrict__ xg,
-                                                             int32_t* __restrict__ state) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
-  const BigView v = big_view(p, Mb);
-  if (threadIdx.x == 0) sh.info = 0;
+// Cooperative panel factorisation: P workgroups, workgroup b owning the panel
+// rows [c + 128 b, c + 128 b + 128) (all panel columns) in LDS.  Per column:
+// each workgroup finds its best pivot candidate (|Re| + |Im| among its rows
+// in [c + j, plim), lowest row on ties) and publishes it with the
+// candidate's row and, if it owns row c + j, that row; one grid barrier;
+// every workgroup takes the same winner, swaps the two rows where it owns
+// them and eliminates the column in its own rows.  The barrier counts
+// arrivals on this panel's own counter (zeroed by big_init_kernel); a wait
+// gives up after `spin` polls, setting state[1], and every workgroup then
+// leaves (a later panel kernel leaves at once when state[1] is set).  After
+// the last column the rows are written back and workgroup 0, which owns the
+// diagonal block, inverts its unit lower part into xg.
+constexpr int kCoopRows = 128;  // panel rows per workgroup
+constexpr int kCoopMaxP = 64;   // workgroups of a panel (N <= 8192)
+
+struct CoopSmem {
+  zd blk[kCoopRows][kNB];  // this workgroup's rows of the panel
+  zd prow[kNB];            // the pivot row
+  zd rowj[kNB];            // the row that the pivot row replaces
+  double candv[kLuWaves];
+  int candi[kLuWaves];
+  int win, stop;
+  double winv;
+};
+
+struct CoopBufs {
+  int32_t* counter;  // this panel's arrival counter
+  double* candv;     // [2][kCoopMaxP]
+  int32_t* candi;    // [2][kCoopMaxP]
+  zd* candrow;       // [2][kCoopMaxP][kNB]
+  zd* rowj;          // [2][kNB]
+};
+
+// Arrival of this workgroup at barrier `target` (all threads call it) and the
+// wait for every workgroup; false (uniform) when the wait gave up.
+__device__ bool coop_barrier(int32_t* counter, int target, int64_t spin, int* stop) {
+  __threadfence();
   __syncthreads();
-  panel_factor<double, kR, kWL>(v.A, c, w, v.Nd, false, sh);
-  if (threadIdx.x < w) ipiv[c + threadIdx.x] = sh.ipiv[threadIdx.x];
-  if (threadIdx.x == 0 && sh.info != 0 && state[0] == 0) state[0] = sh.info;
-  if (c + w < v.N) {
+  if (threadIdx.x == 0) {
+    atomicAdd(counter, 1);
+    int ok = 1;
+    int64_t it = 0;
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++it >= spin) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    *stop = !ok;
+  }
+  __syncthreads();
+  __threadfence();
+  return !__builtin_amdgcn_readfirstlane(*stop);
+}
+
+__global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev p, double* Mb, int c, int w,
+                                                                  int32_t* __restrict__ ipiv,
+                                                                  double* __restrict__ xg,
+                                                                  int32_t* __restrict__ state, CoopBufs cb,
+                                                                  int64_t spin) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  CoopSmem& cs = *reinterpret_cast<CoopSmem*>(smem_raw);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) cs.stop = state[1];  // an earlier wait gave up: leave at once
+  __syncthreads();
+  if (__builtin_amdgcn_readfirstlane(cs.stop) != 0) return;
+  const BigView v = big_view(p, Mb);
+  const int N = v.N, plim = v.Nd;
+  const int P = (int)gridDim.x, b = (int)blockIdx.x;
+  const int row0 = c + kCoopRows * b;
+  const int nr = max(0, min(kCoopRows, N - row0));
+  for (int q = tid; q < kCoopRows * kNB; q += kThreads) {
+    const int r = q / kNB, j = q % kNB;
+    cs.blk[r][j] = (r < nr && j < w) ? *v.A.ptr(row0 + r, c + j) : zmake(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    const int cj = c + j, buf = j & 1;
+    // candidate of this workgroup (threads 0..127 take one row each)
+    double best = -1.0;
+    int bi = cj;
+    if (tid < nr) {
+      const int g = row0 + tid;
+      if (g >= cj && g < plim) {
+        best = zcabs1(cs.blk[tid][j]);
+        bi = g;
+      }
+    }
+    wave_argmax(best, bi);
+    if (lane == 0) {
+      cs.candv[wave] = best;
+      cs.candi[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double bb = cs.candv[0];
+      int ii = cs.candi[0];
+      for (int q = 1; q < kLuWaves; ++q)
+        if (better(cs.candv[q], cs.candi[q], bb, ii)) {
+          bb = cs.candv[q];
+          ii = cs.candi[q];
+        }
+      cb.candv[buf * kCoopMaxP + b] = bb;
+      cb.candi[buf * kCoopMaxP + b] = ii;
+      cs.win = ii;
+    }
+    __syncthreads();
+    {
+      const int wr = cs.win - row0;  // local row of the candidate (its values; any if none)
+      if (tid < w) {
+        cb.candrow[((int64_t)buf * kCoopMaxP + b) * kNB + tid] = cs.blk[min(max(wr, 0), kCoopRows - 1)][tid];
+        if (cj >= row0 && cj < row0 + nr) cb.rowj[buf * kNB + tid] = cs.blk[cj - row0][tid];
+      }
+    }
+    if (!coop_barrier(cb.counter, P * (j + 1), spin, &cs.stop)) {
+      if (tid == 0) state[1] = 1;
+      return;
+    }
+    // the winner, the same in every workgroup
+    if (tid == 0) {
+      double bb = cb.candv[buf * kCoopMaxP];
+      int ii = cb.candi[buf * kCoopMaxP], wb = 0;
+      for (int q = 1; q < P; ++q) {
+        const double ob = cb.candv[buf * kCoopMaxP + q];
+        const int oi = cb.candi[buf * kCoopMaxP + q];
+        if (better(ob, oi, bb, ii)) {
+          bb = ob;
+          ii = oi;
+          wb = q;
+        }
+      }
+      const bool zero = !(bb > 0.0);
+      cs.win = zero ? cj : ii;
+      cs.winv = zero ? 0.0 : bb;
+      if (zero && bb == 0.0 && b == 0 && state[0] == 0) state[0] = cj + 1;
+      if (b == 0) ipiv[cj] = cs.win;
+      cs.candi[0] = wb;
+    }
+    __syncthreads();
+    const int pr = cs.win;
+    if (tid < w) {
+      cs.prow[tid] = cb.candrow[((int64_t)buf * kCoopMaxP + cs.candi[0]) * kNB + tid];
+      cs.rowj[tid] = cb.rowj[buf * kNB + tid];
+    }
+    __syncthreads();
+    if (pr != cj && tid < w) {
+      if (pr >= row0 && pr < row0 + nr) cs.blk[pr - row0][tid] = cs.rowj[tid];
+      if (cj >= row0 && cj < row0 + nr) cs.blk[cj - row0][tid] = cs.prow[tid];
+    }
+    __syncthreads();
+    if (cs.winv > 0.0) {
+      // rows below the pivot: l = a_rj / pivot, a_r(j+1..) -= l prow(j+1..);
+      // four threads per row, each a quarter of the columns
+      const zd inv = zinv(cs.prow[j]);
+      const int r = tid >> 2, part = tid & 3;
+      if (r < nr && row0 + r > cj) {
+        const zd l = zmul(cs.blk[r][j], inv);
+        for (int jj = j + 1 + part; jj < w; jj += 4) cs.blk[r][jj] = zfms(cs.blk[r][jj], l, cs.prow[jj]);
+      }
+      __syncthreads();
+      if (tid < nr && row0 + tid > cj) cs.blk[tid][j] = zmul(cs.blk[tid][j], inv);
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < nr * kNB; q += kThreads) {
+    const int r = q / kNB, j = q % kNB;
+    if (j < w) *v.A.ptr(row0 + r, c + j) = cs.blk[r][j];
+  }
+  __syncthreads();
+  // the diagonal block (rows c .. c+w-1) is workgroup 0's own
+  if (b == 0 && c + w < N) {
+    LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
     invert_unit_lower<double>(v.A, c, w, sh);
     save_x<double>(sh, reinterpret_cast<zd*>(xg));
   }
@@ -1848,7 +2014,12 @@ __global__ __launch_bounds__(kThreads) void big_u12_kernel(lsms_prob_dev p, doub
   LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
   const BigView v = big_view(p, Mb);
   const int s0 = s_begin + kNB * blockIdx.x, sw = min(kNB, s_end - s0);
-  if (threadIdx.x < w) sh.ipiv[threadIdx.x] = ipiv[c + threadIdx.x];
+  if (threadIdx.x < w) {
+    // a pivot row below the column and inside the matrix (anything else,
+    // which only a panel that gave up could leave, means no interchange)
+    const int r = c + threadIdx.x, pv = ipiv[r];
+    sh.ipiv[threadIdx.x] = (pv >= r && pv < v.N) ? pv : r;
+  }
   const zd* x = reinterpret_cast<const zd*>(xg);
   for (int q = threadIdx.x; q < kNB * kNB; q += kThreads) sh.X[q / kNB][q % kNB] = x[q];
   __syncthreads();
@@ -1895,7 +2066,7 @@ __global__ __launch_bounds__(kThreads) void big_finish_kernel(lsms_prob_dev p, d
                                                               const int32_t* __restrict__ state) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   LuSmemD& sh = *reinterpret_cast<LuSmemD*>(smem_raw);
-  const int st = state[0];
+  const int st = state[1] ? -4 : state[0];
   if (st < 0) {
     fill_nan(p, 0, tau00);
     if (threadIdx.x == 0) info[0] = st;
@@ -2210,11 +2381,31 @@ hipError_t lsms_launch_site_blocks(const lsms_prob_dev& p, const int32_t* liz_at
 }
 
 // One instance across the whole GPU: workspace layout [state | ipiv | two
-// 64 x 64 blocks], see lsms_big_work_bytes.
-int64_t lsms_big_work_bytes(const lsms_prob_dev& p) {
+// 64 x 64 blocks | panel counters | pivot candidates, their rows, row j],
+// each part 256-byte aligned; see lsms_big_work_bytes.
+namespace {
+struct BigLayout {
+  int64_t ipiv, xg, counters, candv, candi, candrow, rowj, total;
+};
+BigLayout big_layout(const lsms_prob_dev& p) {
   const int64_t N = (int64_t)p.kc * p.max_liz;
-  return 256 + ((N * 4 + 255) & ~(int64_t)255) + 2 * kNB * kNB * 16;
+  const int64_t np = (N - p.kc + kNB - 1) / kNB;
+  auto al = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
+  BigLayout L;
+  L.ipiv = 256;
+  L.xg = L.ipiv + al(N * 4);
+  L.counters = L.xg + 2 * kNB * kNB * 16;
+  L.candv = L.counters + al(np * 4);
+  L.candi = L.candv + al(2 * kCoopMaxP * 8);
+  L.candrow = L.candi + al(2 * kCoopMaxP * 4);
+  L.rowj = L.candrow + al(2 * (int64_t)kCoopMaxP * kNB * 16);
+  L.total = L.rowj + al(2 * kNB * 16);
+  return L;
 }
+size_t coop_smem() { return sizeof(CoopSmem) > sizeof(LuSmemD) ? sizeof(CoopSmem) : sizeof(LuSmemD); }
+}  // namespace
+
+int64_t lsms_big_work_bytes(const lsms_prob_dev& p) { return big_layout(p).total; }
 
 int lsms_big_events(const lsms_prob_dev& p) {
   const int Nd = p.kc * p.max_liz - p.kc;
@@ -2222,27 +2413,28 @@ int lsms_big_events(const lsms_prob_dev& p) {
 }
 
 hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* work, double* tau00, int32_t* info,
-                           int32_t nb, hipStream_t s0, hipStream_t s1, hipEvent_t* ev) {
+                           int32_t nb, int64_t spin, hipStream_t s0, hipStream_t s1, hipEvent_t* ev) {
   (void)nb;  // panels are 64 wide
   const int N = p.kc * p.max_liz, Nd = N - p.kc;
   const int np = (Nd + kNB - 1) / kNB;
+  const BigLayout L = big_layout(p);
   int32_t* state = reinterpret_cast<int32_t*>(work);
-  int32_t* ipiv = reinterpret_cast<int32_t*>(work + 256);
-  double* xg = reinterpret_cast<double*>(work + 256 + (((int64_t)N * 4 + 255) & ~(int64_t)255));
+  int32_t* ipiv = reinterpret_cast<int32_t*>(work + L.ipiv);
+  double* xg = reinterpret_cast<double*>(work + L.xg);
+  int32_t* counters = reinterpret_cast<int32_t*>(work + L.counters);
   const size_t smem = sizeof(LuSmemD);
   auto xgk = [&](int k) { return xg + (size_t)(k & 1) * kNB * kNB * 2; };
   auto panel = [&](int k, hipStream_t s) {
     const int c = kNB * k, w = min(kNB, Nd - c);
-    if (N <= kThreads * 5)
-      hipLaunchKernelGGL((big_panel_kernel<5, 8>), dim3(1), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k), state);
-    else if (N <= kThreads * 8)
-      hipLaunchKernelGGL((big_panel_kernel<8, 4>), dim3(1), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k), state);
-    else if (N <= kThreads * 13)
-      hipLaunchKernelGGL((big_panel_kernel<13, 4>), dim3(1), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k),
-                         state);
-    else
-      hipLaunchKernelGGL((big_panel_kernel<16, 2>), dim3(1), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k),
-                         state);
+    CoopBufs cb;
+    cb.counter = counters + k;
+    cb.candv = reinterpret_cast<double*>(work + L.candv);
+    cb.candi = reinterpret_cast<int32_t*>(work + L.candi);
+    cb.candrow = reinterpret_cast<zd*>(work + L.candrow);
+    cb.rowj = reinterpret_cast<zd*>(work + L.rowj);
+    const unsigned P = (unsigned)((N - c + kCoopRows - 1) / kCoopRows);
+    hipLaunchKernelGGL(big_panel_coop_kernel, dim3(P), dim3(kThreads), coop_smem(), s, p, M, c, w, ipiv, xgk(k),
+                       state, cb, spin);
   };
   // the update by panel k of the columns [a, b)
   auto update = [&](int k, int a, int b, hipStream_t s) {
@@ -2255,7 +2447,7 @@ hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* wor
     if (below > 0)
       hipLaunchKernelGGL(big_gemm_kernel, dim3(ns, nr), dim3(kThreads), smem, s, p, M, c, w, a, b, kBigRows);
   };
-  hipLaunchKernelGGL(big_init_kernel, dim3(1), dim3(64), 0, s0, p, state);
+  hipLaunchKernelGGL(big_init_kernel, dim3(1), dim3(256), 0, s0, p, state, counters, np, ipiv, N);
   panel(0, s0);
   for (int k = 0; k < np; ++k) {
     const int next = kNB * (k + 1);  // first column of panel k + 1 (Nd after the last)
@@ -2279,10 +2471,7 @@ hipError_t lsms_prepare_big_kernels() {
   const int a = (int)sizeof(LuSmemD);
   const hipFuncAttribute attr = hipFuncAttributeMaxDynamicSharedMemorySize;
   hipError_t e;
-  if ((e = hipFuncSetAttribute((const void*)big_panel_kernel<5, 8>, attr, a)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)big_panel_kernel<8, 4>, attr, a)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)big_panel_kernel<13, 4>, attr, a)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)big_panel_kernel<16, 2>, attr, a)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)big_panel_coop_kernel, attr, (int)coop_smem())) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)big_u12_kernel, attr, a)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute((const void*)big_gemm_kernel, attr, a)) != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)big_finish_kernel, attr, a);

@@ -70,7 +70,7 @@ SYMBOLS = ("lsms_create", "lsms_destroy", "lsms_build_liz", "build_kkr", "tau00_
            "lsms_gmres_workspace_size", "tau00_gmres", "lsms_row_workspace_size", "tau_row_batched",
            "lsms_contour_sum", "lsms_lloyd_idos", "lsms_liz_moments", "build_kkr_spin", "tau00_spin_batched",
            "lsms_spin_workspace_size", "tau00_spin_solve", "lsms_large_workspace_size", "tau00_large",
-           "tau00_gmres_pc", "lsms_site_blocks")
+           "tau00_gmres_pc", "lsms_site_blocks", "lsms_large_set_spin_limit")
 
 BATCHED_WORK_PER_INST = 2 * 64 * 64 * 16
 MLP_PARAMS = 399616
@@ -105,6 +105,7 @@ def lib():
                                                ctypes.POINTER(ctypes.c_size_t)]
         L.tau00_spin_solve.argtypes = [_P, PP, SP, ctypes.POINTER(Opts), _P, _P, _P, ctypes.c_size_t, _P]
         L.lsms_large_workspace_size.argtypes = [_P, PP, SP, ctypes.POINTER(ctypes.c_size_t)]
+        L.lsms_large_set_spin_limit.argtypes = [_P, ctypes.c_int64]
         L.tau00_large.argtypes = [_P, PP, SP, _P, ctypes.POINTER(Opts), _P, _P, _P, ctypes.c_size_t, _P]
         L.lsms_contour_sum.argtypes = [_P, _I32, _I32, _I32, _P, _P, _P, _P]
         L.lsms_lloyd_idos.argtypes = [_P, _I32, _I32, _P, _P, _P]
@@ -355,6 +356,11 @@ def tau00_large(h: Handle, prob: Problem, M: torch.Tensor, opts: Opts | None = N
                              _ptr(tau), _ptr(info), _ptr(work), work.numel() * work.element_size(), _stream()),
            "tau00_large")
     return _tau_view(tau, kc), info
+
+
+def large_set_spin_limit(h: Handle, polls: int):
+    """lsms_large_set_spin_limit (0 = default)."""
+    _check(lib().lsms_large_set_spin_limit(h.ptr, int(polls)), "lsms_large_set_spin_limit")
 
 
 def contour_sum(h: Handle, weights, values: torch.Tensor, n_sites: int, n_energy: int) -> torch.Tensor:

@@ -80,7 +80,8 @@ def test_large_config1_against_oracle_and_batched(P, h):
     idx = [0, 15, 37, 64, 127]
     got = _run(P, h, w, idx)
     check_tau(got, ref[idx], inputs.subset(w, idx), TOL, "tau00_large config1")
-    # the batched path with 64-column panels takes the same arithmetic
+    # the batched path with 64-column panels (same pivot rule, its own panel
+    # arithmetic)
     ws = inputs.subset(w, idx)
     prob = P.problem_for_workload(h, ws)
     N = prob.kk * np.diff(prob.liz_off.cpu().numpy())
@@ -92,7 +93,7 @@ def test_large_config1_against_oracle_and_batched(P, h):
     tb = tb.cpu().numpy()
     d = np.abs(got - tb).max() / np.abs(tb).max()
     print(f"tau00_large vs tau00_batched (64-wide panels): max rel diff {d:.2e}")
-    assert d <= 1e-13
+    assert d <= 1e-12
 
 
 @pytest.mark.parametrize("lmax", [0, 1, 2, 4])
@@ -181,3 +182,32 @@ def test_large_errors(P, h):
         torch.cuda.synchronize()
         assert int(info.cpu().numpy()[0]) == step, (step, int(info.cpu().numpy()[0]))
         assert np.all(np.isnan(tau.cpu().numpy()))
+
+
+def test_large_spin_limit_gives_up(P, h):
+    # a barrier wait allowed a single poll gives up (the first workgroup to
+    # arrive never finds the others there): every kernel still ends, the
+    # instance reports info -4 with tau00 NaN; with the default limit the next
+    # call on the same handle and workspace is exact again
+    torch = _torch()
+    w = inputs.subset(inputs.config2(), [0])
+    prob = P.problem_for_workload(h, w)
+    N = prob.kk * prob.max_liz
+    M = torch.zeros(N * N, dtype=torch.complex128, device="cuda")
+    moff = torch.zeros(1, dtype=torch.int64, device="cuda")
+    P.build_kkr(h, prob, M, moff)
+    P.large_set_spin_limit(h, 1)
+    try:
+        tau, info = P.tau00_large(h, prob, M)
+        torch.cuda.synchronize()
+        print("spin limit 1: info", int(info.cpu().numpy()[0]), flush=True)
+        assert int(info.cpu().numpy()[0]) == -4
+        assert np.all(np.isnan(tau.cpu().numpy()))
+    finally:
+        P.large_set_spin_limit(h, 0)
+    P.build_kkr(h, prob, M, moff)
+    tau, info = P.tau00_large(h, prob, M)
+    torch.cuda.synchronize()
+    assert int(info.cpu().numpy()[0]) == 0
+    ref, _ = oracle.tau00_workload(w)
+    check_tau(tau.cpu().numpy(), ref, w, TOL, "tau00_large after a give-up")
