@@ -1860,13 +1860,39 @@ struct CoopBufs {
   zd* rowj;          // [2][kNB]
 };
 
+// Exchange between the workgroups of one panel: relaxed device-scope atomic
+// loads and stores, which reach the level where all XCDs meet without a
+// write-back or invalidation of this XCD's whole L2 (a device-scope fence
+// costs both, twice per column).
+__device__ __forceinline__ void st_dev(double* a, double x) {
+  __hip_atomic_store(a, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(int32_t* a, int32_t x) {
+  __hip_atomic_store(a, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(double* a) {
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_dev(int32_t* a) {
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(zd* a, zd x) {
+  st_dev(reinterpret_cast<double*>(a), x.x);
+  st_dev(reinterpret_cast<double*>(a) + 1, x.y);
+}
+__device__ __forceinline__ zd ld_dev(zd* a) {
+  return zmake(ld_dev(reinterpret_cast<double*>(a)), ld_dev(reinterpret_cast<double*>(a) + 1));
+}
+
 // Arrival of this workgroup at barrier `target` (all threads call it) and the
-// wait for every workgroup; false (uniform) when the wait gave up.
+// wait for every workgroup; false (uniform) when the wait gave up.  Every
+// thread's exchange stores are acknowledged (all memory counters drained)
+// before thread 0 adds the arrival.
 __device__ bool coop_barrier(int32_t* counter, int target, int64_t spin, int* stop) {
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    atomicAdd(counter, 1);
+    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     int64_t it = 0;
     while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -1879,7 +1905,6 @@ __device__ bool coop_barrier(int32_t* counter, int target, int64_t spin, int* st
     *stop = !ok;
   }
   __syncthreads();
-  __threadfence();
   return !__builtin_amdgcn_readfirstlane(*stop);
 }
 
@@ -1930,48 +1955,48 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
           bb = cs.candv[q];
           ii = cs.candi[q];
         }
-      cb.candv[buf * kCoopMaxP + b] = bb;
-      cb.candi[buf * kCoopMaxP + b] = ii;
+      st_dev(cb.candv + buf * kCoopMaxP + b, bb);
+      st_dev(cb.candi + buf * kCoopMaxP + b, ii);
       cs.win = ii;
     }
     __syncthreads();
     {
       const int wr = cs.win - row0;  // local row of the candidate (its values; any if none)
       if (tid < w) {
-        cb.candrow[((int64_t)buf * kCoopMaxP + b) * kNB + tid] = cs.blk[min(max(wr, 0), kCoopRows - 1)][tid];
-        if (cj >= row0 && cj < row0 + nr) cb.rowj[buf * kNB + tid] = cs.blk[cj - row0][tid];
+        st_dev(cb.candrow + ((int64_t)buf * kCoopMaxP + b) * kNB + tid, cs.blk[min(max(wr, 0), kCoopRows - 1)][tid]);
+        if (cj >= row0 && cj < row0 + nr) st_dev(cb.rowj + buf * kNB + tid, cs.blk[cj - row0][tid]);
       }
     }
     if (!coop_barrier(cb.counter, P * (j + 1), spin, &cs.stop)) {
       if (tid == 0) state[1] = 1;
       return;
     }
-    // the winner, the same in every workgroup
-    if (tid == 0) {
-      double bb = cb.candv[buf * kCoopMaxP];
-      int ii = cb.candi[buf * kCoopMaxP], wb = 0;
-      for (int q = 1; q < P; ++q) {
-        const double ob = cb.candv[buf * kCoopMaxP + q];
-        const int oi = cb.candi[buf * kCoopMaxP + q];
-        if (better(ob, oi, bb, ii)) {
-          bb = ob;
-          ii = oi;
-          wb = q;
-        }
+    // the winner, the same in every workgroup: wave 0 reads the P candidates
+    // at once (lane q that of workgroup q) and reduces them; wave 1 reads row
+    // cj meanwhile
+    if (wave == 0) {
+      double bb = -1.0;
+      int ii = 0x7fffffff;
+      if (lane < P) {
+        bb = ld_dev(cb.candv + buf * kCoopMaxP + lane);
+        ii = ld_dev(cb.candi + buf * kCoopMaxP + lane);
       }
-      const bool zero = !(bb > 0.0);
-      cs.win = zero ? cj : ii;
-      cs.winv = zero ? 0.0 : bb;
-      if (zero && bb == 0.0 && b == 0 && state[0] == 0) state[0] = cj + 1;
-      if (b == 0) ipiv[cj] = cs.win;
-      cs.candi[0] = wb;
+      wave_argmax(bb, ii);
+      if (lane == 0) {
+        const bool zero = !(bb > 0.0);
+        cs.win = zero ? cj : ii;
+        cs.winv = zero ? 0.0 : bb;
+        if (zero && bb == 0.0 && b == 0 && state[0] == 0) state[0] = cj + 1;
+        if (b == 0) ipiv[cj] = cs.win;
+      }
+    } else if (wave == 1 && lane < w) {
+      cs.rowj[lane] = ld_dev(cb.rowj + buf * kNB + lane);
     }
     __syncthreads();
     const int pr = cs.win;
-    if (tid < w) {
-      cs.prow[tid] = cb.candrow[((int64_t)buf * kCoopMaxP + cs.candi[0]) * kNB + tid];
-      cs.rowj[tid] = cb.rowj[buf * kNB + tid];
-    }
+    // the winning row, published by its owner (workgroup 0 owns row cj)
+    const int wb = min(max((pr - c) / kCoopRows, 0), P - 1);
+    if (tid < w) cs.prow[tid] = ld_dev(cb.candrow + ((int64_t)buf * kCoopMaxP + wb) * kNB + tid);
     __syncthreads();
     if (pr != cj && tid < w) {
       if (pr >= row0 && pr < row0 + nr) cs.blk[pr - row0][tid] = cs.rowj[tid];
