@@ -364,19 +364,22 @@ def time_row(args, P, h, w, liz, energy, e_idx, delta, max_liz, n: int = 256):
     return res
 
 
-def bench_large(args):
+def bench_large(args, canted: bool = False):
     """One matrix across the whole GPU (tau00_large) at the paper's
-    non-canted NiAu rank N = 6225 (lmax = 4, 249-atom LIZ): the instances are
-    solved one after another (build_kkr, then tau00_large), HIP events
-    around each tau00_large; the golden oracle instances are checked."""
+    non-canted NiAu rank N = 6225 (lmax = 4, 249-atom LIZ), or with `canted`
+    at its spin-canted NiAu rank 12450 (canted moments, spin-split wells):
+    the instances are solved one after another (build, then tau00_large),
+    HIP events around each tau00_large; the golden oracle instances are
+    checked."""
     import torch
 
     import inputs
     import paper_2308_16317_amd as P
 
-    w_all = inputs.config_large()
-    g = np.load(os.path.join(ROOT, "tests", "golden", "large_tau00.npz"), allow_pickle=False)
-    idx = list(g["idx"]) + list(range(1, 1 + max(0, (args.n_inst or 6) - 2)))
+    w_all = inputs.config_large_canted() if canted else inputs.config_large()
+    gname = "large_canted_tau00.npz" if canted else "large_tau00.npz"
+    g = np.load(os.path.join(ROOT, "tests", "golden", gname), allow_pickle=False)
+    idx = list(g["idx"]) + list(range(1, 1 + max(0, (args.n_inst or (4 if canted else 6)) - 2)))
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     h = P.Handle()
@@ -384,11 +387,12 @@ def bench_large(args):
     N = probs[0].kc * probs[0].max_liz
     M = torch.empty(N * N, dtype=torch.complex128, device=dev)
     m_off = torch.zeros(1, dtype=torch.int64, device=dev)
+    build = P.build_kkr_spin if canted else P.build_kkr
     work = None
     ms, taus = [], []
     for it in range(args.warmup + args.steps):
         for q, prob in enumerate(probs):
-            P.build_kkr(h, prob, M, m_off)
+            build(h, prob, M, m_off)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -404,18 +408,20 @@ def bench_large(args):
     flops = 8.0 / 3.0 * float(N) ** 3
     med = float(np.median(ms))
     rf = [float(np.linalg.norm(t - r) / np.linalg.norm(r)) for t, r in zip(taus, g["tau"])]
-    out = {"metric": f"single-instance τ00 solves/s at N={N} (whole GPU)", "value": 1e3 / med,
+    kind = ("spin-canted (cone 60 deg, spin-split wells), rank 2 kk 249" if canted else "non-canted")
+    out = {"metric": f"single-instance {'spin-canted ' if canted else ''}τ00 solves/s at N={N} (whole GPU)",
+           "value": 1e3 / med,
            "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": med,
            "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{w_all.name}: one (site, E) instance at a time, 6x6x6 fcc NiAu 50/50, 249-atom "
-                                  f"LIZ, N={N}, lmax=4, complex FP64 LU/Schur over all compute units",
+                                  f"LIZ, {kind}, N={N}, lmax=4, complex FP64 LU/Schur over all compute units",
                       "instances": len(idx), "N": N},
            "roofline": {"bound": "mfma", "achieved": flops / (med * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": flops / (med * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                         "traffic": None, "kernel": "tau00_large (panel, U12 and MFMA update kernels, look-ahead)",
                         "ms_per_launch": med, "ms_min": float(np.min(ms))},
            "oracle_check": {"instances": [int(i) for i in g["idx"]], "max_rel_F_vs_oracle": max(rf), "bar": 1e-12,
-                            "pass": bool(max(rf) <= 1e-12), "source": "tests/golden/large_tau00.npz (oracle)"}}
+                            "pass": bool(max(rf) <= 1e-12), "source": f"tests/golden/{gname} (oracle)"}}
     print(json.dumps(out), flush=True)
     if not out["oracle_check"]["pass"]:
         sys.exit(1)
@@ -522,13 +528,14 @@ def main():
     ap.add_argument("--chunk", type=int, default=1024, help="instances per build/LU launch (chunked)")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--n-inst", type=int, default=0, help="limit the batch (0 = all 8192)")
-    ap.add_argument("--workload", choices=["benchmark", "ragged", "lmax4", "canted", "canted4", "large"],
+    ap.add_argument("--workload", choices=["benchmark", "ragged", "lmax4", "canted", "canted4", "large", "large_canted"],
                     default="benchmark",
                     help="benchmark: 8192 instances at N = 2160 (the metric's workload); ragged: 1024 instances of "
                          "the vacancy/noise supercell with cutoffs 1.7a-2.1a (N = 1200-2400); lmax4: the benchmark "
                          "systems at lmax = 4 (N = 3375); canted / canted4: the spin-canted path at rank 4320 / "
                          "6750 (first 1024 / 256 instances unless --n-inst); large: one N = 6225 matrix at a "
-                         "time across the whole GPU (tau00_large)")
+                         "time across the whole GPU (tau00_large); large_canted: the same at the spin-canted "
+                         "rank 12450")
     ap.add_argument("--forms", choices=["none", "fp32ir", "all"], default="all",
                     help="also time the other forms on the same instances (persistent launch) and report them "
                          "with their speedup over the FP64 path and their deviation from it")
@@ -559,8 +566,8 @@ def main():
         print(json.dumps({"error": "--precision fp32ir runs through tau00_solve: use --mode persistent or graph"}))
         sys.exit(2)
 
-    if args.workload == "large":
-        bench_large(args)
+    if args.workload in ("large", "large_canted"):
+        bench_large(args, canted=args.workload == "large_canted")
         return
     if args.workload in ("canted", "canted4"):
         bench_canted(args, 3 if args.workload == "canted" else 4)

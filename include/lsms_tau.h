@@ -102,8 +102,9 @@ typedef struct {
     int32_t n_energy;    /* number of energies in energy/delta (>= 1)                  */
     int32_t max_liz;     /* upper bound on every LIZ size (1..1024); sizes workspace slots.
                             The matrix bound N = kk * max_liz (2 kk * max_liz with spin
-                            canting) is at most 8192 for the FP64 paths and at most 4096
-                            for LSMS_PREC_FP32_IR, tau00_gmres and tau_row_batched (-2
+                            canting) is at most 8192 for the batched FP64 paths, 16384
+                            for build_kkr, build_kkr_spin and tau00_large, and 4096 for
+                            LSMS_PREC_FP32_IR, tau00_gmres and tau_row_batched (-2
                             above)                                                      */
     int32_t reserved;
     const int64_t *liz_off;  /* device [n_inst+1]: instance i owns LIZ rows liz_off[i] ..
@@ -132,8 +133,10 @@ typedef struct {
     double tol;          /* LSMS_PREC_FP32_IR: stop once the last correction of the central
                             block is at most tol times the block (Frobenius norms), or
                             once the contraction of the last two steps (at most 1/2)
-                            predicts that the next one would be; 0 = 1e-12; otherwise
-                            1e-15 .. 1e-3                                               */
+                            predicts that the next one would be (the first FP32 solve
+                            counts as the step from zero, so one refinement step can
+                            suffice when it predicts at most tol / 4); 0 = 1e-12;
+                            otherwise 1e-15 .. 1e-3                                     */
 } lsms_opts;
 
 /* Create a handle bound to HIP device `device`: uploads the real Gaunt
@@ -259,7 +262,7 @@ int lsms_liz_moments(lsms_handle_t h, int64_t n_rows, const int32_t *liz_atom, c
                      int32_t n_atoms, double *liz_moment, void *stream);
 
 /* build_kkr with spin canting: instance i is a kc N_LIZ square at M + 2*m_off[i]
- * doubles (N_i = 2 kk N_LIZ,i <= 8192).  Arguments as build_kkr, spin third
+ * doubles (N_i = 2 kk N_LIZ,i <= 16384).  Arguments as build_kkr, spin third
  * (-3 when NULL or, for a nonempty batch, with a NULL member). */
 int build_kkr_spin(lsms_handle_t h, const lsms_problem *p, const lsms_spin *spin, double *M, const int64_t *m_off,
                    int32_t *info, void *stream);
@@ -291,12 +294,12 @@ int tau00_spin_solve(lsms_handle_t h, const lsms_problem *p, const lsms_spin *sp
  * rows) applies the MFMA update; the panel itself is factorised by
  * ceil(rows / 128) workgroups together (each holding 128 of its rows in LDS,
  * one grid barrier per column for the pivot choice; the workgroups of a
- * panel are at most 64, one per compute unit, and every barrier wait gives up
+ * panel are at most 128, one per compute unit, and every barrier wait gives up
  * after a bounded number of polls); the next panel is factorised while the rest
  * of the update runs (one panel of look-ahead, on a second stream of the
  * handle, joined back to `stream` before the call's last kernel).
  *   p        n_inst = 1, the instance's LIZ exactly max_liz sites (info -3
- *            otherwise); N = kk * max_liz (2 kk * max_liz with spin) <= 8192
+ *            otherwise); N = kk * max_liz (2 kk * max_liz with spin) <= 16384
  *   spin     NULL, or spin canting as tau00_spin_batched
  *   M        device complex N x N column-major (build_kkr / build_kkr_spin with
  *            m_off = 0); overwritten

@@ -25,6 +25,7 @@ from .workloads import (  # noqa: F401
     config4,
     config_canted,
     config_large,
+    config_large_canted,
     contour_energies,
     contour_ends,
     contour_weights,

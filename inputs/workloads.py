@@ -281,3 +281,13 @@ def mlp_init(seed: int = 0) -> np.ndarray:
         parts.append(rng.standard_normal(o * i) * scale)
         parts.append(np.zeros(o))
     return np.concatenate(parts)
+
+
+def config_large_canted(seed: int = 0, lmax: int = 4) -> Workload:
+    """The large-instance systems (249-atom LIZ) with a canted moment on every
+    atom and spin-split square wells: rank 2 kk 249 = 12450 at lmax = 4, the
+    paper's spin-canted NiAu rank.  864 x 32 instances, site-major."""
+    w = config_large(seed, lmax)
+    up, dn = spin_phase_shift_tables(w.energies, lmax)
+    return dataclasses.replace(w, name=f"fcc-NiAu-canted-249atomLIZ-lmax{lmax}", delta=up, delta_dn=dn,
+                               atom_moment=canted_moments(w.atom_pos.shape[0], seed))

@@ -35,19 +35,20 @@ hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
 
 // Largest matrix of the FP64 elimination (leaf registers, kR = 16) and of the
 // precision form, the learned form and the block-row solve (kR = 8).
-constexpr int64_t kMaxN = 8192;
-constexpr int64_t kMaxNSmall = 4096;
+constexpr int64_t kMaxN = 8192;        // batched FP64 kernels (register leaves)
+constexpr int64_t kMaxNSmall = 4096;   // precision form, GMRES, block row
+constexpr int64_t kMaxNLarge = 16384;  // the build and tau00_large
 
 int64_t n_max(const lsms_problem* p, int nspin = 1) {
   return (int64_t)nspin * (p->lmax + 1) * (p->lmax + 1) * p->max_liz;
 }
 
-int check_problem(const lsms_problem* p, int nspin = 1) {
+int check_problem(const lsms_problem* p, int nspin = 1, int64_t nmax = kMaxN) {
   if (!p) return -2;
   if (p->lmax < 0 || p->lmax > kMaxLmax) return -2;
   if (p->n_inst < 0 || p->n_species < 1 || p->n_species > kMaxSpeciesAbi || p->n_energy < 1) return -2;
   if (p->max_liz < 1 || p->max_liz > 1024) return -2;
-  if (n_max(p, nspin) > kMaxN) return -2;
+  if (n_max(p, nspin) > nmax) return -2;
   if (p->n_inst > 0 && (!p->liz_off || !p->pos || !p->species || !p->energy || !p->e_idx || !p->delta))
     return -2;
   return 0;
@@ -340,7 +341,7 @@ extern "C" int lsms_build_liz(lsms_handle_t h, const double* atom_pos, const int
 extern "C" int build_kkr(lsms_handle_t h, const lsms_problem* p, double* M, const int64_t* m_off, int32_t* info,
                          void* stream) {
   if (!h) return -1;
-  int r = check_problem(p);
+  int r = check_problem(p, 1, kMaxNLarge);
   if (r) return r;
   if (p->n_inst == 0) return 0;
   if (!M) return -3;
@@ -460,7 +461,7 @@ extern "C" int lsms_liz_moments(lsms_handle_t h, int64_t n_rows, const int32_t* 
 extern "C" int build_kkr_spin(lsms_handle_t h, const lsms_problem* p, const lsms_spin* spin, double* M,
                               const int64_t* m_off, int32_t* info, void* stream) {
   if (!h) return -1;
-  int r = check_problem(p, 2);
+  int r = check_problem(p, 2, kMaxNLarge);
   if (r) return r;
   if ((r = check_spin(p, spin))) return r;
   if (p->n_inst == 0) return 0;
@@ -537,7 +538,7 @@ extern "C" int tau00_spin_solve(lsms_handle_t h, const lsms_problem* p, const ls
 // ------------------------------------------------ one instance, whole GPU
 constexpr int64_t kBigSpinDefault = int64_t(1) << 22;  // polls (each with a short sleep): seconds
 int check_large(const lsms_problem* p, const lsms_spin* spin, const lsms_opts* opts) {
-  int r = check_problem(p, spin ? 2 : 1);
+  int r = check_problem(p, spin ? 2 : 1, kMaxNLarge);
   if (r) return r;
   if (p->n_inst != 1) return -2;
   if (spin && (r = check_spin(p, spin))) return r;

@@ -1030,9 +1030,15 @@ __device__ __noinline__ void mixed_instance(const lsms_prob_dev& p, int inst, zd
       }
       // converged when the correction is below tol, or when the contraction
       // seen over the last two steps (at most 1/2) predicts that the next
-      // correction is: |d_k|^2 / |d_{k-1}| <= tol |Y|
+      // correction is: |d_k|^2 / |d_{k-1}| <= tol |Y|.  The first FP32 solve
+      // is the step from a zero start (its correction is Y itself, |Y| taken
+      // after this step), so one refinement step can already show it; that
+      // first estimate of the contraction is asked for a margin of 4
+      // (predicted correction at most tol / 4).
+      const double dp = it > 0 ? dprev : yn;
+      const double margin = it > 0 ? 1.0 : 1.0 / 16.0;
       const bool small = dn <= tol * tol * yn;
-      const bool predicted = it > 0 && dn <= 0.25 * dprev && dn * dn <= tol * tol * yn * dprev;
+      const bool predicted = dn <= 0.25 * dp && dn * dn <= margin * tol * tol * yn * dp;
       conv = __builtin_amdgcn_readfirstlane((int)(small || predicted)) != 0;
       dprev = dn;
       __syncthreads();
@@ -1840,7 +1846,7 @@ __global__ void big_init_kernel(lsms_prob_dev p, int32_t* state, int32_t* counte
 // the last column the rows are written back and workgroup 0, which owns the
 // diagonal block, inverts its unit lower part into xg.
 constexpr int kCoopRows = 128;  // panel rows per workgroup
-constexpr int kCoopMaxP = 64;   // workgroups of a panel (N <= 8192)
+constexpr int kCoopMaxP = 128;  // workgroups of a panel (N <= 16384)
 
 struct CoopSmem {
   zd blk[kCoopRows][kNB];  // this workgroup's rows of the panel
@@ -1972,14 +1978,22 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
       return;
     }
     // the winner, the same in every workgroup: wave 0 reads the P candidates
-    // at once (lane q that of workgroup q) and reduces them; wave 1 reads row
-    // cj meanwhile
+    // at once (lane q those of workgroups q and q + 64) and reduces them;
+    // wave 1 reads row cj meanwhile
     if (wave == 0) {
       double bb = -1.0;
       int ii = 0x7fffffff;
       if (lane < P) {
         bb = ld_dev(cb.candv + buf * kCoopMaxP + lane);
         ii = ld_dev(cb.candi + buf * kCoopMaxP + lane);
+      }
+      if (lane + 64 < P) {
+        const double ob = ld_dev(cb.candv + buf * kCoopMaxP + lane + 64);
+        const int oi = ld_dev(cb.candi + buf * kCoopMaxP + lane + 64);
+        if (better(ob, oi, bb, ii)) {
+          bb = ob;
+          ii = oi;
+        }
       }
       wave_argmax(bb, ii);
       if (lane == 0) {
@@ -2441,6 +2455,7 @@ hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* wor
                            int32_t nb, int64_t spin, hipStream_t s0, hipStream_t s1, hipEvent_t* ev) {
   (void)nb;  // panels are 64 wide
   const int N = p.kc * p.max_liz, Nd = N - p.kc;
+  if ((N + kCoopRows - 1) / kCoopRows > kCoopMaxP) return hipErrorInvalidValue;  // more panel rows than workgroups
   const int np = (Nd + kNB - 1) / kNB;
   const BigLayout L = big_layout(p);
   int32_t* state = reinterpret_cast<int32_t*>(work);

@@ -6,7 +6,9 @@ Bar: tau00 rel_F <= 1e-12 and the scale-free [M^{-1}]_00 elementwise within
 1e-12 of its largest entry (the plain FP64 bar).  The paper's non-canted NiAu
 rank N = 6225 (lmax = 4, 249-atom LIZ) is checked against
 tests/golden/large_tau00.npz, written by make_large_golden.py beside it with
-the oracle alone; the spin-canted rank 4320 against canted_tau00.npz.
+the oracle alone; the spin-canted rank 4320 against canted_tau00.npz, and
+the paper's spin-canted NiAu rank 12450 (2 kk 249, lmax = 4) against
+large_canted_tau00.npz (same script, argument `canted`).
 """
 
 import dataclasses
@@ -153,6 +155,21 @@ def test_large_spin(P, h):
         assert d <= TOL
 
 
+def test_large_spin_n12450(P, h):
+    # the paper's spin-canted NiAu rank: 2 kk 249 = 12450 (98 panel
+    # workgroups in the first panels, 195 panels)
+    path = os.path.join(GOLD, "large_canted_tau00.npz")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/large_canted_tau00.npz not written")
+    g = np.load(path, allow_pickle=False)
+    w = inputs.config_large_canted()
+    got = _run(P, h, w, list(g["idx"]))
+    ref = g["tau"]
+    d = np.linalg.norm((got - ref).reshape(len(ref), -1), axis=1) / np.linalg.norm(ref.reshape(len(ref), -1), axis=1)
+    print(f"tau00_large canted rank 12450: rel_F {d.max():.2e}")
+    assert d.max() <= TOL
+
+
 def test_large_errors(P, h):
     torch = _torch()
     w = inputs.subset(inputs.config1(), [0, 1])
@@ -164,6 +181,12 @@ def test_large_errors(P, h):
     p1 = P.problem_for_workload(h, w1)
     with pytest.raises(RuntimeError):  # panel width other than 64
         P.tau00_large(h, p1, M, P.Opts(0, 32, 0, 0))
+    # rank limit: 16384 rows (max_liz 656 at lmax = 4 is 16400)
+    w4 = inputs.subset(inputs.config1().with_lmax(4), [0])
+    p4 = P.problem_for_workload(h, w4)
+    big = P.Problem(4, p4.liz_off, p4.pos, p4.species, w4.energies, w4.e_idx, w4.delta, max_liz=656)
+    with pytest.raises(RuntimeError):
+        P.tau00_large(h, big, M)
     # a LIZ smaller than max_liz: info -3, tau00 NaN
     p2 = P.Problem(3, p1.liz_off, p1.pos, p1.species, w1.energies, w1.e_idx, w1.delta, max_liz=14)
     M2 = torch.zeros((16 * 14) ** 2, dtype=torch.complex128, device="cuda")
