@@ -4,10 +4,11 @@
 // instance's local environment and energy to normalised approximations of
 // tau00 and of [M^{-1}]_{00}; the latter seeds the GMRES solve.
 //
-// Products: Z = bf16(H) bf16(W)^T + b, computed on v_mfma_f32_16x16x4f32 with
-// the operands rounded to bf16 (round to nearest even) as they are loaded, so
-// every product of two bf16 values is exact and accumulates in FP32.
-// Backward products use FP32 operands (the rounding is taken as the identity).
+// Forward products: Z = bf16(H) bf16(W)^T + b on the bf16 matrix cores
+// (v_mfma_f32_16x16x16_bf16: every product of two bf16 values is exact, the
+// sums in FP32), the activations rounded to bf16 (round to nearest even) as
+// they are loaded.  Backward products use FP32 operands on
+// v_mfma_f32_16x16x4f32 (the rounding is taken as the identity).
 #include <cstdint>
 
 #include "lsms_common.h"
@@ -91,6 +92,63 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const TA
           if (accumulate) v += *c;
           *c = v;
         }
+      }
+}
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+// C[i][j] (ldc) = sum_k bf16(A[i lda + k]) Wb[j ldw + k] + bias[j]: both
+// operands run along k, so lane (li, lq) of a 16 x 16 x 16 step supplies k =
+// kb + 4 lq .. + 3 of row i (A) and of column j (W).  A 64x64 tile per
+// 256-thread workgroup, 32x32 (2x2 MFMA tiles) per wave; K ragged (zeros).
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const float* __restrict__ A, int64_t lda,
+                                                        const uint16_t* __restrict__ Wb, int64_t ldw,
+                                                        float* __restrict__ C, int64_t ldc,
+                                                        const float* __restrict__ bias) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int i0 = blockIdx.y * 64 + 32 * (wave >> 1), j0 = blockIdx.x * 64 + 32 * (wave & 1);
+  v4f acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int kb = 0; kb < K; kb += 16) {
+    const int k0 = kb + 4 * lq;
+    v4s av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i = i0 + 16 * a + li;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) av[a][t] = (i < M && k0 + t < K) ? bf16_bits(A[(int64_t)i * lda + k0 + t]) : 0;
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int j = j0 + 16 * b + li;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bv[b][t] = (j < N && k0 + t < K) ? (short)Wb[(int64_t)j * ldw + k0 + t] : 0;
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+  }
+  // register r of lane l holds D[4 (l / 16) + r][l % 16]
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 16 * a + 4 * lq + r, j = j0 + 16 * b + li;
+        if (i < M && j < N) C[(int64_t)i * ldc + j] = acc[a][b][r] + (bias ? bias[j] : 0.f);
       }
 }
 
@@ -314,8 +372,11 @@ hipError_t lsms_launch_mlp_forward(const float* params, const uint16_t* wb, cons
     const float* b = params + off + (int64_t)o * in;
     float* Z = (l + 1 < kLayers) ? act + 512 * l : act + 6 * 256;
     // Z[i][j] = sum_k bf16(hin[i][k]) bf16(W[j][k]) + b[j]
-    if ((e = gemm<float, true, uint16_t, false>(n, o, in, hin, ldin, 1, W, 1, in, Z, ld, b, 0, s)) != hipSuccess)
-      return e;
+    if (n > 0) {
+      hipLaunchKernelGGL(gemm_bf16_kernel, dim3((o + 63) / 64, (n + 63) / 64), dim3(256), 0, s, n, o, in, hin, ldin,
+                         W, (int64_t)in, Z, ld, b);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (l + 1 < kLayers) {
       float* H = Z + 256;
       hipLaunchKernelGGL(silu_kernel, dim3(blocks_for((int64_t)n * 256)), dim3(256), 0, s, n, Z, H, ld);
