@@ -23,7 +23,7 @@ constexpr int kBMaxSpecies = 8;
 constexpr int kBMaxLm = 5;
 
 struct BuildSmem {
-  double Y[kBuildChunk][kBMaxKK2];
+  zd F[kBuildChunk][kBMaxKK2];     // h_l''(kappa R) Y_L''(R^) of each row block of the chunk
   zd h[kBuildChunk][kBMaxL2 + 1];
   double nlm[kBMaxL2 + 1][kBMaxL2 + 1];  // sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!)
   double rcp[kBMaxL2 + 2];               // 1/k
@@ -33,17 +33,17 @@ struct BuildSmem {
   double coef[kBMaxNnz];
   int32_t rp[kBMaxKK * kBMaxKK + 1];
   int16_t lpp[kBMaxNnz];
-  int8_t lof[kBMaxNnz];
   int spec[kBuildChunk];
   int bad, bad_species;
 };
 
-// Y_L''(r) for the l'' = m .. l2 of one order m >= 0 (both signs of m), of a
-// nonzero vector r: cos(m phi) + i sin(m phi) as ((x + i y)/rho)^m,
-// P_m^m = (2m-1)!! sin^m(theta) and upward recurrence in l; normalisation
-// constants and reciprocals from LDS (no divisions in the recurrence).
+// F_L'' = h_l'' Y_L''(r) for the l'' = m .. l2 of one order m >= 0 (both
+// signs of m), of a nonzero vector r, given the Hankel values h_l'':
+// cos(m phi) + i sin(m phi) as ((x + i y)/rho)^m, P_m^m = (2m-1)!!
+// sin^m(theta) and upward recurrence in l; normalisation constants and
+// reciprocals from LDS (no divisions in the recurrence).
 __device__ inline void ylm_order(int l2, int m, double x, double y, double z, const BuildSmem& sb,
-                                 double* __restrict__ Y) {
+                                 const zd* __restrict__ h, zd* __restrict__ F) {
   const double rho2 = x * x + y * y;
   const double r = sqrt(rho2 + z * z);
   const double rho = sqrt(rho2);
@@ -67,12 +67,13 @@ __device__ inline void ylm_order(int l2, int m, double x, double y, double z, co
     p_lm2 = p_lm1;
     p_lm1 = pl;
     const double nlm = sb.nlm[l][m];
+    const zd hl = h[l];
     if (m == 0) {
-      Y[l * l + l] = nlm * pl;
+      F[l * l + l] = zscale(hl, nlm * pl);
     } else {
       const double sc = 1.4142135623730951 * nlm * pl;
-      Y[l * l + l + m] = sc * cm;
-      Y[l * l + l - m] = sc * sm;
+      F[l * l + l + m] = zscale(hl, sc * cm);
+      F[l * l + l - m] = zscale(hl, sc * sm);
     }
   }
 }
@@ -115,7 +116,6 @@ __device__ void build_setup(const lsms_prob_dev& p, const lsms_gaunt_dev& g, int
   for (int q = tid; q < g.nnz; q += kNT) {
     const int lpp = g.lpp[q];
     sb.lpp[q] = (int16_t)lpp;
-    sb.lof[q] = (int8_t)l_of(lpp);
     sb.coef[q] = g.coef[q];
   }
   if (tid <= kBMaxL2 + 1) sb.rcp[tid] = tid > 0 ? 1.0 / (double)tid : 0.0;
@@ -165,13 +165,12 @@ __device__ __forceinline__ void build_spin_phase_b(const lsms_prob_dev& p, int j
       const int e0 = sb.rp[pidx], e1 = sb.rp[pidx + 1];
       for (int k = e0; k < e1; ++k) {
         const double c = sb.coef[k];
-        const int lp = sb.lpp[k], lo = sb.lof[k];
-        const double cy0 = c * sb.Y[i0][lp], cy1 = c * sb.Y[i1][lp];
-        const zd h0 = sb.h[i0][lo], h1 = sb.h[i1][lo];
-        sr0 += cy0 * h0.x;
-        si0 += cy0 * h0.y;
-        sr1 += cy1 * h1.x;
-        si1 += cy1 * h1.y;
+        const int lp = sb.lpp[k];
+        const zd f0 = sb.F[i0][lp], f1 = sb.F[i1][lp];
+        sr0 += c * f0.x;
+        si0 += c * f0.y;
+        sr1 += c * f1.x;
+        si1 += c * f1.y;
       }
       const zd g0 = zmake(sr0, si0), g1 = zmake(sr1, si1);
 #pragma unroll
@@ -192,11 +191,12 @@ __device__ __forceinline__ void build_spin_phase_b(const lsms_prob_dev& p, int j
 }
 
 // Block column j of M, in chunks of kBuildChunk LIZ row blocks.  Phase A:
-// for each row block i of the chunk, 2 lmax + 2 tasks: one per order
-// m = 0 .. 2 lmax of Y_L''(R_ij) and one for the Hankel functions
-// h_l''(kappa R_ij); task (m, i) is thread 64 m + i, so that a wave runs one
-// kind of task.  Phase B: each thread owns one L and two row blocks (which
-// share the Gaunt lists) and sweeps the kk columns L', entry (L, L') of row
+// for each row block i of the chunk the Hankel functions h_l''(kappa R_ij),
+// then 2 lmax + 1 tasks, one per order m = 0 .. 2 lmax, forming
+// F_L'' = h_l'' Y_L''(R_ij) of that order; task (m, i) is thread 64 m + i,
+// so that a wave runs one order.  Phase B: each thread owns one L and two
+// row blocks (which share the Gaunt lists) and sweeps the kk columns L'
+// (sum over the list of (L, L') of coefficient x F), entry (L, L') of row
 // block i at index L + kk (i + nb L'), so consecutive threads write
 // consecutive rows.
 template <int kNT>
@@ -214,34 +214,38 @@ __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int in
   const zd pref = zmake(4.0 * M_PI * kap.y, -4.0 * M_PI * kap.x);  // -4 pi i kappa
   for (int ib = 0; ib < nliz; ib += kBuildChunk) {
     const int nb = min(kBuildChunk, nliz - ib);
-    const int slots = l2 + 2;  // orders m = 0 .. l2, then the Hankel functions
-    for (int t = tid; t < slots * kBuildChunk; t += kNT) {
-      const int m = t >> 6, il = t & 63;  // one kind of task per wave
+    // phase A1: per row block its species (and moment) and the Hankel
+    // functions; A2: per (order m, row block) the F_L'' of that order
+    for (int il = tid; il < kBuildChunk; il += kNT) {
       const int iw = ib + il;
       if (il >= nb) continue;
-      if (m == 0) {
-        const int sp = spec[iw];
-        if (sp < 0 || sp >= p.n_species) sb.bad_species = 1;
-        sb.spec[il] = (sp >= 0 && sp < p.n_species) ? sp : 0;
-        if (p.nspin == 2) {
-          const double* e = p.moment + 3 * (a + iw);
-          sb.mom[il][0] = e[0];
-          sb.mom[il][1] = e[1];
-          sb.mom[il][2] = e[2];
-        }
+      const int sp = spec[iw];
+      if (sp < 0 || sp >= p.n_species) sb.bad_species = 1;
+      sb.spec[il] = (sp >= 0 && sp < p.n_species) ? sp : 0;
+      if (p.nspin == 2) {
+        const double* e = p.moment + 3 * (a + iw);
+        sb.mom[il][0] = e[0];
+        sb.mom[il][1] = e[1];
+        sb.mom[il][2] = e[2];
       }
       if (iw != j) {
         const double Rx = rel[3 * iw] - rjx, Ry = rel[3 * iw + 1] - rjy, Rz = rel[3 * iw + 2] - rjz;
         const double R2 = Rx * Rx + Ry * Ry + Rz * Rz;
         if (R2 < 1e-16) {
-          if (m == 0) sb.bad = 1;
-        } else if (m == l2 + 1) {
+          sb.bad = 1;
+        } else {
           const double R = sqrt(R2);
           hankel_all(l2, zmake(kap.x * R, kap.y * R), sb.h[il]);
-        } else {
-          ylm_order(l2, m, Rx, Ry, Rz, sb, sb.Y[il]);
         }
       }
+    }
+    __syncthreads();
+    for (int t = tid; t < (l2 + 1) * kBuildChunk; t += kNT) {
+      const int m = t >> 6, il = t & 63;  // one order per wave
+      const int iw = ib + il;
+      if (il >= nb || iw == j) continue;
+      const double Rx = rel[3 * iw] - rjx, Ry = rel[3 * iw + 1] - rjy, Rz = rel[3 * iw + 2] - rjz;
+      if (Rx * Rx + Ry * Ry + Rz * Rz >= 1e-16) ylm_order(l2, m, Rx, Ry, Rz, sb, sb.h[il], sb.F[il]);
     }
     __syncthreads();
     if (p.nspin == 2) {
@@ -268,13 +272,12 @@ __device__ __forceinline__ void build_column_body(const lsms_prob_dev& p, int in
         const int e0 = sb.rp[pidx], e1 = sb.rp[pidx + 1];
         for (int k = e0; k < e1; ++k) {
           const double c = sb.coef[k];
-          const int lp = sb.lpp[k], lo = sb.lof[k];
-          const double cy0 = c * sb.Y[i0][lp], cy1 = c * sb.Y[i1][lp];
-          const zd h0 = sb.h[i0][lo], h1 = sb.h[i1][lo];
-          sr0 += cy0 * h0.x;
-          si0 += cy0 * h0.y;
-          sr1 += cy1 * h1.x;
-          si1 += cy1 * h1.y;
+          const int lp = sb.lpp[k];
+          const zd f0 = sb.F[i0][lp], f1 = sb.F[i1][lp];
+          sr0 += c * f0.x;
+          si0 += c * f0.y;
+          sr1 += c * f1.x;
+          si1 += c * f1.y;
         }
         zd v0, v1;
         if (iw0 == j) {
