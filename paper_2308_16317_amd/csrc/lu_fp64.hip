@@ -1849,7 +1849,7 @@ constexpr int kCoopRows = 128;  // panel rows per workgroup
 constexpr int kCoopMaxP = 128;  // workgroups of a panel (N <= 16384)
 
 struct CoopSmem {
-  zd blk[kCoopRows][kNB];  // this workgroup's rows of the panel
+  zd blk[kCoopRows][kNB + 1];  // this workgroup's rows of the panel (row stride padded: rows start on different LDS banks)
   zd prow[kNB];            // the pivot row
   zd rowj[kNB];            // the row that the pivot row replaces
   double candv[kLuWaves];
