@@ -6,7 +6,8 @@ Bar: tau00 rel_F <= 1e-12 and the scale-free [M^{-1}]_00 elementwise within
 1e-12 of its largest entry (the plain FP64 bar).  The paper's non-canted NiAu
 rank N = 6225 (lmax = 4, 249-atom LIZ) is checked against
 tests/golden/large_tau00.npz, written by make_large_golden.py beside it with
-the oracle alone; the spin-canted rank 4320 against canted_tau00.npz, and
+the oracle alone; the spin-canted ranks 4320 and 6750 against
+canted_tau00.npz, and
 the paper's spin-canted NiAu rank 12450 (2 kk 249, lmax = 4) against
 large_canted_tau00.npz (same script, argument `canted`).
 """
@@ -153,6 +154,14 @@ def test_large_spin(P, h):
         d = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         print(f"tau00_large canted rank 4320: rel_F {d:.2e}")
         assert d <= TOL
+        # rank 6750 (lmax = 4: a 50 x 50 central block), both contour ends
+        w4 = inputs.config_canted(lmax=4)
+        i4 = [int(i) for i in g["idx_l4"]]
+        got = _run(P, h, w4, i4)
+        ref = g["tau_l4"]
+        d = np.linalg.norm((got - ref).reshape(len(i4), -1), axis=1) / np.linalg.norm(ref.reshape(len(i4), -1), axis=1)
+        print(f"tau00_large canted rank 6750: rel_F max {d.max():.2e}")
+        assert d.max() <= TOL
 
 
 def test_large_spin_n12450(P, h):
