@@ -308,6 +308,9 @@ int tau00_spin_solve(lsms_handle_t h, const lsms_problem *p, const lsms_spin *sp
  *            info -4 when a barrier wait gave up (lsms_large_set_spin_limit)
  *   work     device, lsms_large_workspace_size bytes (pivots, two 64 x 64
  *            blocks; -8 when NULL, -9 when too small)
+ * Returns -10 when the device cannot hold all ceil(N / 128) workgroups of
+ * the first panel at once (queried with the occupancy API at lsms_create;
+ * a barrier needs them all resident).
  * Calls on one handle must not overlap in time (they share the second stream
  * and its events). */
 int lsms_large_workspace_size(lsms_handle_t h, const lsms_problem *p, const lsms_spin *spin, size_t *bytes);

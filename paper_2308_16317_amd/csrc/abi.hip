@@ -168,6 +168,7 @@ struct lsms_handle_s {
   hipStream_t aux = nullptr;
   std::vector<hipEvent_t> big_ev;
   int64_t big_spin = 0;  // polls of a grid-barrier wait, 0 = default
+  int big_resident = 0;  // panel workgroups the device holds at once
 };
 
 #define HIP_TRY(x)                          \
@@ -300,6 +301,7 @@ extern "C" int lsms_create(lsms_handle_t* out, int device) {
     return LSMS_EHIP;
   }
   h->scratch = g_scratch_ptr[device];
+  if (lsms_big_resident(device, &h->big_resident) != hipSuccess) h->big_resident = 0;
   *out = h;
   return 0;
 }
@@ -569,6 +571,9 @@ extern "C" int tau00_large(lsms_handle_t h, const lsms_problem* p, const lsms_sp
   if (!work) return -8;
   const lsms_prob_dev d = to_dev(p, spin);
   if (work_bytes < (size_t)lsms_big_work_bytes(d)) return -9;
+  // every workgroup of the first (largest) panel grid must be resident at
+  // once for its grid barriers
+  if (lsms_big_panel_groups(d) > h->big_resident) return -10;
   (void)hipSetDevice(h->device);
   if (!h->aux && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) {
     h->aux = nullptr;

@@ -171,6 +171,10 @@ int lsms_big_events(const lsms_prob_dev& p);
 hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* work, double* tau00, int32_t* info,
                            int32_t nb, int64_t spin, hipStream_t s0, hipStream_t s1, hipEvent_t* ev);
 hipError_t lsms_prepare_big_kernels();
+// Workgroups of the cooperative panel kernel the device holds at once, and
+// the workgroups of the first (largest) panel grid of a problem.
+hipError_t lsms_big_resident(int device, int* n);
+int lsms_big_panel_groups(const lsms_prob_dev& p);
 
 // out[r][0..2] = src[idx[r]][0..2] (liz.hip): per-row moments of the LIZs.
 hipError_t lsms_launch_gather3(int64_t n, const int32_t* idx, const double* src, int32_t n_src, double* out,

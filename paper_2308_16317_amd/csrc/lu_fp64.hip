@@ -2507,6 +2507,24 @@ hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* wor
   return hipGetLastError();
 }
 
+// Workgroups of the cooperative panel kernel that `device` can hold at once
+// (resident per compute unit, with its LDS and registers, times the compute
+// units): a panel's grid must not exceed it, so that every workgroup of a
+// grid barrier can be resident together.
+int lsms_big_panel_groups(const lsms_prob_dev& p) {
+  return (p.kc * p.max_liz + kCoopRows - 1) / kCoopRows;
+}
+
+hipError_t lsms_big_resident(int device, int* n) {
+  int per_cu = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)big_panel_coop_kernel, kThreads,
+                                                             coop_smem());
+  if (e != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess) return e;
+  *n = per_cu * cus;
+  return hipSuccess;
+}
+
 hipError_t lsms_prepare_big_kernels() {
   const int a = (int)sizeof(LuSmemD);
   const hipFuncAttribute attr = hipFuncAttributeMaxDynamicSharedMemorySize;
