@@ -807,17 +807,35 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
     for (int j = 0; j < KJ; ++j) an[j] = arow[min(kc + KJ * lq + j, s - 1)];
   };
   const LSMS_LDS C(*U)[kSWp<R>] = (const LSMS_LDS C(*)[kSWp<R>])Ub;
-  V4 accr[NCS], acci[NCS];
+  // FP64: complex products by the three-multiplication form: with P1 = Re a
+  // Re b, P2 = Im a Im b, P3 = (Re a + Im a)(Re b + Im b), a b = (P1 - P2) +
+  // i (P3 - P1 - P2), three MFMAs per operand pair instead of four (acc1..3
+  // hold the sums of P1, P2, P3).  FP32 keeps four (acc1, acc2 the real and
+  // imaginary parts of -a b): its three-accumulator form does not fit the
+  // registers of the 128-column strips.
+  constexpr bool k3M = sizeof(R) == 8;
+  V4 acc1[NCS], acc2[NCS], acc3[k3M ? NCS : 1];
   auto step = [&](int kc, int j, const C& aj) {
     const int k = (kc + KJ * lq + j) & (kPanelMax - 1);
-    const R nx = -aj.x, ny = -aj.y;
+    if constexpr (k3M) {
+      const R as = aj.x + aj.y;
 #pragma unroll
-    for (int cs = 0; cs < NCS; ++cs) {
-      const C b = U[k][16 * cs + li];
-      accr[cs] = Prec<R>::mfma(nx, b.x, accr[cs]);
-      accr[cs] = Prec<R>::mfma(aj.y, b.y, accr[cs]);
-      acci[cs] = Prec<R>::mfma(nx, b.y, acci[cs]);
-      acci[cs] = Prec<R>::mfma(ny, b.x, acci[cs]);
+      for (int cs = 0; cs < NCS; ++cs) {
+        const C b = U[k][16 * cs + li];
+        acc1[cs] = Prec<R>::mfma(aj.x, b.x, acc1[cs]);
+        acc2[cs] = Prec<R>::mfma(aj.y, b.y, acc2[cs]);
+        acc3[cs] = Prec<R>::mfma(as, b.x + b.y, acc3[cs]);
+      }
+    } else {
+      const R nx = -aj.x, ny = -aj.y;
+#pragma unroll
+      for (int cs = 0; cs < NCS; ++cs) {
+        const C b = U[k][16 * cs + li];
+        acc1[cs] = Prec<R>::mfma(nx, b.x, acc1[cs]);
+        acc1[cs] = Prec<R>::mfma(aj.y, b.y, acc1[cs]);
+        acc2[cs] = Prec<R>::mfma(nx, b.y, acc2[cs]);
+        acc2[cs] = Prec<R>::mfma(ny, b.x, acc2[cs]);
+      }
     }
   };
   const int klast = kUpdChunk<R> * ((s - 1) / kUpdChunk<R>);  // first k of the last chunk (> 0)
@@ -827,8 +845,9 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
     const int rn = rb + 16 * kLuWaves;
 #pragma unroll
     for (int cs = 0; cs < NCS; ++cs) {
-      accr[cs] = V4{R(0), R(0), R(0), R(0)};
-      acci[cs] = V4{R(0), R(0), R(0), R(0)};
+      acc1[cs] = V4{R(0), R(0), R(0), R(0)};
+      acc2[cs] = V4{R(0), R(0), R(0), R(0)};
+      if constexpr (k3M) acc3[cs] = V4{R(0), R(0), R(0), R(0)};
     }
     {
       C a[KJ];
@@ -862,7 +881,13 @@ __device__ __forceinline__ void update_rows(const Mat<typename Prec<R>::C>& A, i
 #pragma unroll
     for (int cs = 0; cs < NCS; ++cs)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) pv[cs][r] = zmake(cv[cs][r].x + accr[cs][r], cv[cs][r].y + acci[cs][r]);
+      for (int r = 0; r < 4; ++r) {
+        if constexpr (k3M)
+          pv[cs][r] = zmake(cv[cs][r].x - (acc1[cs][r] - acc2[cs][r]),
+                            cv[cs][r].y - (acc3[cs][r] - acc1[cs][r] - acc2[cs][r]));
+        else
+          pv[cs][r] = zmake(cv[cs][r].x + acc1[cs][r], cv[cs][r].y + acc2[cs][r]);
+      }
     pb = rb;
   }
   store_pv(pb);
