@@ -30,7 +30,8 @@
 //   3. the inverses of the unit lower diagonal blocks of L11 (LDS, global);
 //   4. per strip of trailing columns (64 in FP64, 128 in FP32): U12 = L11^-1
 //      A12 (MFMA) into LDS, then A22 -= L21 U12 (complex GEMM on MFMA; a
-//      complex product is four real MFMAs on real/imaginary accumulators).
+//      complex product is three real MFMAs in FP64, the three-multiplication
+//      form, and four on real/imaginary accumulators in FP32).
 // Finally S_A is inverted by Gauss-Jordan with partial pivoting.
 #include "kkr_device.h"
 #include "lsms_common.h"
