@@ -496,12 +496,17 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
     cok[t] = col < sw;
     bcol[t] = A.phys(s0 + min(col, sw - 1));
   }
-  V4 ar[NT], ai[NT];
+  // FP64: products by the three-multiplication form (ar, ai, a3 the sums of
+  // Re x Re b, Im x Im b, (Re x + Im x)(Re b + Im b) until the product is
+  // complete), as in update_rows
+  constexpr bool k3M = sizeof(R) == 8;
+  V4 ar[NT], ai[NT], a3[k3M ? NT : 1];
   // U_a = X_a B, B[k][col] = A(c + k, s0 + col)
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     ar[t] = V4{R(0), R(0), R(0), R(0)};
     ai[t] = V4{R(0), R(0), R(0), R(0)};
+    if constexpr (k3M) a3[t] = V4{R(0), R(0), R(0), R(0)};
   }
   {
     const int kend = 16 * rt + 16;
@@ -526,11 +531,25 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          ar[t] = Prec<R>::mfma(x[j].x, b[t][j].x, ar[t]);
-          ar[t] = Prec<R>::mfma(-x[j].y, b[t][j].y, ar[t]);
-          ai[t] = Prec<R>::mfma(x[j].x, b[t][j].y, ai[t]);
-          ai[t] = Prec<R>::mfma(x[j].y, b[t][j].x, ai[t]);
+          if constexpr (k3M) {
+            ar[t] = Prec<R>::mfma(x[j].x, b[t][j].x, ar[t]);
+            ai[t] = Prec<R>::mfma(x[j].y, b[t][j].y, ai[t]);
+            a3[t] = Prec<R>::mfma(x[j].x + x[j].y, b[t][j].x + b[t][j].y, a3[t]);
+          } else {
+            ar[t] = Prec<R>::mfma(x[j].x, b[t][j].x, ar[t]);
+            ar[t] = Prec<R>::mfma(-x[j].y, b[t][j].y, ar[t]);
+            ai[t] = Prec<R>::mfma(x[j].x, b[t][j].y, ai[t]);
+            ai[t] = Prec<R>::mfma(x[j].y, b[t][j].x, ai[t]);
+          }
         }
+    }
+  }
+  if constexpr (k3M) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const V4 re = ar[t] - ai[t], im = a3[t] - ar[t] - ai[t];
+      ar[t] = re;
+      ai[t] = im;
     }
   }
   __syncthreads();  // earlier readers of the strip are done
@@ -552,8 +571,14 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
       const int i = 16 * rt + Prec<R>::drow(r, lk);
       // rows >= wb clamped (their T rows meet zero columns of X_b and zero rows of it)
       const C v = A.base[A.phys(c + kNB + min(i, wb - 1)) * A.N + bcol[t]];
-      ar[t][r] = v.x;
-      ai[t][r] = v.y;
+      if constexpr (k3M) {  // sums (Re, 0, Re + Im) of the starting value
+        ar[t][r] = v.x;
+        ai[t][r] = R(0);
+        a3[t][r] = v.x + v.y;
+      } else {
+        ar[t][r] = v.x;
+        ai[t][r] = v.y;
+      }
     }
   {
     const auto lrow = A.base + A.phys(c + kNB + min(row, wb - 1)) * A.N + A.phys(c) + 4 * lk;
@@ -575,12 +600,26 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const C u = U2[k][16 * (ct0 + t) + li];
-          ar[t] = Prec<R>::mfma(nx, u.x, ar[t]);
-          ar[t] = Prec<R>::mfma(l[j].y, u.y, ar[t]);
-          ai[t] = Prec<R>::mfma(nx, u.y, ai[t]);
-          ai[t] = Prec<R>::mfma(ny, u.x, ai[t]);
+          if constexpr (k3M) {
+            ar[t] = Prec<R>::mfma(nx, u.x, ar[t]);
+            ai[t] = Prec<R>::mfma(ny, u.y, ai[t]);
+            a3[t] = Prec<R>::mfma(nx + ny, u.x + u.y, a3[t]);
+          } else {
+            ar[t] = Prec<R>::mfma(nx, u.x, ar[t]);
+            ar[t] = Prec<R>::mfma(l[j].y, u.y, ar[t]);
+            ai[t] = Prec<R>::mfma(nx, u.y, ai[t]);
+            ai[t] = Prec<R>::mfma(ny, u.x, ai[t]);
+          }
         }
       }
+    }
+  }
+  if constexpr (k3M) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const V4 re = ar[t] - ai[t], im = a3[t] - ar[t] - ai[t];
+      ar[t] = re;
+      ai[t] = im;
     }
   }
 #pragma unroll
@@ -596,6 +635,7 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
   for (int t = 0; t < NT; ++t) {
     ar[t] = V4{R(0), R(0), R(0), R(0)};
     ai[t] = V4{R(0), R(0), R(0), R(0)};
+    if constexpr (k3M) a3[t] = V4{R(0), R(0), R(0), R(0)};
   }
   {
     const int kend = min(wb, 16 * rt + 16);
@@ -618,12 +658,26 @@ __device__ __noinline__ void trsm2_strip(const Mat<typename Prec<R>::C>& Ain, in
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const C b = U2[kNB + k][16 * (ct0 + t) + li];
-          ar[t] = Prec<R>::mfma(x.x, b.x, ar[t]);
-          ar[t] = Prec<R>::mfma(-x.y, b.y, ar[t]);
-          ai[t] = Prec<R>::mfma(x.x, b.y, ai[t]);
-          ai[t] = Prec<R>::mfma(x.y, b.x, ai[t]);
+          if constexpr (k3M) {
+            ar[t] = Prec<R>::mfma(x.x, b.x, ar[t]);
+            ai[t] = Prec<R>::mfma(x.y, b.y, ai[t]);
+            a3[t] = Prec<R>::mfma(x.x + x.y, b.x + b.y, a3[t]);
+          } else {
+            ar[t] = Prec<R>::mfma(x.x, b.x, ar[t]);
+            ar[t] = Prec<R>::mfma(-x.y, b.y, ar[t]);
+            ai[t] = Prec<R>::mfma(x.x, b.y, ai[t]);
+            ai[t] = Prec<R>::mfma(x.y, b.x, ai[t]);
+          }
         }
       }
+    }
+  }
+  if constexpr (k3M) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const V4 re = ar[t] - ai[t], im = a3[t] - ar[t] - ai[t];
+      ar[t] = re;
+      ai[t] = im;
     }
   }
   __syncthreads();  // T fully read
@@ -678,11 +732,14 @@ __device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& Ain, int
   const int li = lane & 15, lk = lane >> 4;
   const int rt = wave < 4 ? wave : 7 - wave;  // row tile (r and 3 - r per SIMD, as in trsm2_strip)
   const int ct0 = NT * (wave >> 2);           // first of NT column tiles
-  V4 ar[NT], ai[NT];
+  // FP64: products by the three-multiplication form, as in trsm2_strip
+  constexpr bool k3M = sizeof(R) == 8;
+  V4 ar[NT], ai[NT], a3[k3M ? NT : 1];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     ar[t] = V4{R(0), R(0), R(0), R(0)};
     ai[t] = V4{R(0), R(0), R(0), R(0)};
+    if constexpr (k3M) a3[t] = V4{R(0), R(0), R(0), R(0)};
   }
   int64_t bcol[NT];
   bool cok[NT];
@@ -711,11 +768,25 @@ __device__ __noinline__ void trsm_strip(const Mat<typename Prec<R>::C>& Ain, int
       const R xi = (k < s) ? x.y : R(0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        ar[t] = Prec<R>::mfma(xr, b[t][j].x, ar[t]);
-        ar[t] = Prec<R>::mfma(-xi, b[t][j].y, ar[t]);
-        ai[t] = Prec<R>::mfma(xr, b[t][j].y, ai[t]);
-        ai[t] = Prec<R>::mfma(xi, b[t][j].x, ai[t]);
+        if constexpr (k3M) {
+          ar[t] = Prec<R>::mfma(xr, b[t][j].x, ar[t]);
+          ai[t] = Prec<R>::mfma(xi, b[t][j].y, ai[t]);
+          a3[t] = Prec<R>::mfma(xr + xi, b[t][j].x + b[t][j].y, a3[t]);
+        } else {
+          ar[t] = Prec<R>::mfma(xr, b[t][j].x, ar[t]);
+          ar[t] = Prec<R>::mfma(-xi, b[t][j].y, ar[t]);
+          ai[t] = Prec<R>::mfma(xr, b[t][j].y, ai[t]);
+          ai[t] = Prec<R>::mfma(xi, b[t][j].x, ai[t]);
+        }
       }
+    }
+  }
+  if constexpr (k3M) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const V4 re = ar[t] - ai[t], im = a3[t] - ar[t] - ai[t];
+      ar[t] = re;
+      ai[t] = im;
     }
   }
   __syncthreads();  // earlier readers of sh.U are done
