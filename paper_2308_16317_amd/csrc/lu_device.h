@@ -1030,8 +1030,13 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
       }
   };
   load_group(rb);
+  // FP64: products by the three-multiplication form (accr, acci, acc3 the
+  // sums of Re a Re u, Im a Im u, (Re a + Im a)(Re u + Im u) of the negated
+  // L entries, started from (Re c, 0, Re c + Im c) of the block's own
+  // entries), as in update_rows
+  constexpr bool k3M = sizeof(R) == 8;
   for (; rb < N; rb += RB * kStep) {
-    V4 accr[RB][NCS], acci[RB][NCS];
+    V4 accr[RB][NCS], acci[RB][NCS], acc3[k3M ? RB : 1][k3M ? NCS : 1];
     C a[RB][KA];
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
@@ -1039,8 +1044,14 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
       for (int cs = 0; cs < NCS; ++cs)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          accr[b][cs][r] = cn[b][cs][r].x;
-          acci[b][cs][r] = cn[b][cs][r].y;
+          if constexpr (k3M) {
+            accr[b][cs][r] = cn[b][cs][r].x;
+            acci[b][cs][r] = R(0);
+            acc3[b][cs][r] = cn[b][cs][r].x + cn[b][cs][r].y;
+          } else {
+            accr[b][cs][r] = cn[b][cs][r].x;
+            acci[b][cs][r] = cn[b][cs][r].y;
+          }
         }
 #pragma unroll
       for (int j = 0; j < KA; ++j) a[b][j] = an[b][j];
@@ -1059,10 +1070,16 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
           const R nx = -a[b][j].x, ny = -a[b][j].y;
-          accr[b][cs] = Prec<R>::mfma(nx, u.x, accr[b][cs]);
-          accr[b][cs] = Prec<R>::mfma(a[b][j].y, u.y, accr[b][cs]);
-          acci[b][cs] = Prec<R>::mfma(nx, u.y, acci[b][cs]);
-          acci[b][cs] = Prec<R>::mfma(ny, u.x, acci[b][cs]);
+          if constexpr (k3M) {
+            accr[b][cs] = Prec<R>::mfma(nx, u.x, accr[b][cs]);
+            acci[b][cs] = Prec<R>::mfma(ny, u.y, acci[b][cs]);
+            acc3[b][cs] = Prec<R>::mfma(nx + ny, u.x + u.y, acc3[b][cs]);
+          } else {
+            accr[b][cs] = Prec<R>::mfma(nx, u.x, accr[b][cs]);
+            accr[b][cs] = Prec<R>::mfma(a[b][j].y, u.y, accr[b][cs]);
+            acci[b][cs] = Prec<R>::mfma(nx, u.y, acci[b][cs]);
+            acci[b][cs] = Prec<R>::mfma(ny, u.x, acci[b][cs]);
+          }
         }
       }
     }
@@ -1071,7 +1088,12 @@ __device__ __forceinline__ void update_rows_multi(const Mat<typename Prec<R>::C>
 #pragma unroll
       for (int cs = 0; cs < NCS; ++cs)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) pv[b][cs][r] = zmake(accr[b][cs][r], acci[b][cs][r]);
+        for (int r = 0; r < 4; ++r) {
+          if constexpr (k3M)
+            pv[b][cs][r] = zmake(accr[b][cs][r] - acci[b][cs][r], acc3[b][cs][r] - accr[b][cs][r] - acci[b][cs][r]);
+          else
+            pv[b][cs][r] = zmake(accr[b][cs][r], acci[b][cs][r]);
+        }
     pb = rb;
   }
   store_group(pb);
