@@ -1855,7 +1855,7 @@ struct CoopSmem {
   zd rowj[kNB];            // the row that the pivot row replaces
   double candv[kLuWaves];
   int candi[kLuWaves];
-  int win, stop;
+  int stop;
   double winv;
 };
 
@@ -1954,7 +1954,10 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
       cs.candi[wave] = bi;
     }
     __syncthreads();
-    if (tid == 0) {
+    // wave 0 publishes: every lane reduces the eight wave candidates in the
+    // same order (so all agree), lane 0 stores value and row index, lanes
+    // < w the candidate's row and, in the owner of row cj, that row
+    if (wave == 0) {
       double bb = cs.candv[0];
       int ii = cs.candi[0];
       for (int q = 1; q < kLuWaves; ++q)
@@ -1962,16 +1965,14 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
           bb = cs.candv[q];
           ii = cs.candi[q];
         }
-      st_dev(cb.candv + buf * kCoopMaxP + b, bb);
-      st_dev(cb.candi + buf * kCoopMaxP + b, ii);
-      cs.win = ii;
-    }
-    __syncthreads();
-    {
-      const int wr = cs.win - row0;  // local row of the candidate (its values; any if none)
-      if (tid < w) {
-        st_dev(cb.candrow + ((int64_t)buf * kCoopMaxP + b) * kNB + tid, cs.blk[min(max(wr, 0), kCoopRows - 1)][tid]);
-        if (cj >= row0 && cj < row0 + nr) st_dev(cb.rowj + buf * kNB + tid, cs.blk[cj - row0][tid]);
+      if (lane == 0) {
+        st_dev(cb.candv + buf * kCoopMaxP + b, bb);
+        st_dev(cb.candi + buf * kCoopMaxP + b, ii);
+      }
+      const int wr = min(max(ii - row0, 0), kCoopRows - 1);  // local row of the candidate (its values; any if none)
+      if (lane < w) {
+        st_dev(cb.candrow + ((int64_t)buf * kCoopMaxP + b) * kNB + lane, cs.blk[wr][lane]);
+        if (cj >= row0 && cj < row0 + nr) st_dev(cb.rowj + buf * kNB + lane, cs.blk[cj - row0][lane]);
       }
     }
     if (!coop_barrier(cb.counter, P * (j + 1), spin, &cs.stop)) {
@@ -1979,9 +1980,12 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
       return;
     }
     // the winner, the same in every workgroup: wave 0 reads the P candidates
-    // at once (lane q those of workgroups q and q + 64) and reduces them;
-    // wave 1 reads row cj meanwhile
+    // (lane q those of workgroups q and q + 64) and row cj at once, reduces
+    // the candidates, takes lane 0's result, reads the winning row from its
+    // owner (workgroup 0 owns row cj) and swaps the two rows where it owns them
     if (wave == 0) {
+      zd rj = zmake(0.0, 0.0);
+      if (lane < w) rj = ld_dev(cb.rowj + buf * kNB + lane);
       double bb = -1.0;
       int ii = 0x7fffffff;
       if (lane < P) {
@@ -1997,38 +2001,50 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
         }
       }
       wave_argmax(bb, ii);
+      bb = __shfl(bb, 0);
+      ii = __shfl(ii, 0);
+      const bool zero = !(bb > 0.0);
+      const int pr = zero ? cj : ii;
       if (lane == 0) {
-        const bool zero = !(bb > 0.0);
-        cs.win = zero ? cj : ii;
         cs.winv = zero ? 0.0 : bb;
         if (zero && bb == 0.0 && b == 0 && state[0] == 0) state[0] = cj + 1;
-        if (b == 0) ipiv[cj] = cs.win;
+        if (b == 0) ipiv[cj] = pr;
       }
-    } else if (wave == 1 && lane < w) {
-      cs.rowj[lane] = ld_dev(cb.rowj + buf * kNB + lane);
-    }
-    __syncthreads();
-    const int pr = cs.win;
-    // the winning row, published by its owner (workgroup 0 owns row cj)
-    const int wb = min(max((pr - c) / kCoopRows, 0), P - 1);
-    if (tid < w) cs.prow[tid] = ld_dev(cb.candrow + ((int64_t)buf * kCoopMaxP + wb) * kNB + tid);
-    __syncthreads();
-    if (pr != cj && tid < w) {
-      if (pr >= row0 && pr < row0 + nr) cs.blk[pr - row0][tid] = cs.rowj[tid];
-      if (cj >= row0 && cj < row0 + nr) cs.blk[cj - row0][tid] = cs.prow[tid];
+      const int wb = min(max((pr - c) / kCoopRows, 0), P - 1);
+      if (lane < w) {
+        const zd pv = ld_dev(cb.candrow + ((int64_t)buf * kCoopMaxP + wb) * kNB + lane);
+        cs.prow[lane] = pv;
+        if (pr != cj) {
+          if (pr >= row0 && pr < row0 + nr) cs.blk[pr - row0][lane] = rj;
+          if (cj >= row0 && cj < row0 + nr) cs.blk[cj - row0][lane] = pv;
+        }
+      }
     }
     __syncthreads();
     if (cs.winv > 0.0) {
-      // rows below the pivot: l = a_rj / pivot, a_r(j+1..) -= l prow(j+1..);
-      // four threads per row, each a quarter of the columns
+      // rows below the pivot: l = a_rj / pivot, a_r(j+1..) -= l prow(j+1..),
+      // a_rj := l; four threads per row, each every fourth column, sixteen
+      // columns per group with the group's loads issued together
       const zd inv = zinv(cs.prow[j]);
       const int r = tid >> 2, part = tid & 3;
       if (r < nr && row0 + r > cj) {
         const zd l = zmul(cs.blk[r][j], inv);
-        for (int jj = j + 1 + part; jj < w; jj += 4) cs.blk[r][jj] = zfms(cs.blk[r][jj], l, cs.prow[jj]);
+        for (int g = (j + 1) >> 4; g < ((w + 15) >> 4); ++g) {
+          zd a[4], u[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int jj = 16 * g + 4 * m + part;
+            a[m] = cs.blk[r][jj];
+            u[m] = cs.prow[jj];
+          }
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int jj = 16 * g + 4 * m + part;
+            if (jj > j && jj < w) cs.blk[r][jj] = zfms(a[m], l, u[m]);
+          }
+        }
+        if (part == 0) cs.blk[r][j] = l;
       }
-      __syncthreads();
-      if (tid < nr && row0 + tid > cj) cs.blk[tid][j] = zmul(cs.blk[tid][j], inv);
     }
     __syncthreads();
   }
