@@ -1796,13 +1796,14 @@ __global__ __launch_bounds__(kThreads) void tau00_gmres_persistent_kernel(
 //   big_u12_kernel: one workgroup per 64-column strip of the trailing
 //     columns applies the panel's interchanges to the strip and forms
 //     U12 = L11^{-1} A12 (stored in A);
-//   big_gemm_kernel: one workgroup per (strip, 512 rows) updates
+//   big_gemm_kernel: one workgroup per (strip, block of rows) updates
 //     A22 -= L21 U12 on MFMA.
 // The host issues the launches on two streams with one panel of
 // look-ahead: the next strip's update and the next panel run on the
 // caller's stream while the rest of the trailing update runs on the second.
 // ======================================================================
-constexpr int kBigRows = 512;  // trailing-update rows per workgroup
+constexpr int kBigRows = 512;    // trailing-update rows per workgroup (up to 4x while >= 1024 workgroups)
+constexpr int kAheadRows = 128;  // rows per workgroup in the next panel's strip
 
 struct BigView {
   Mat<zd> A;
@@ -2493,16 +2494,21 @@ hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* wor
     hipLaunchKernelGGL(big_panel_coop_kernel, dim3(P), dim3(kThreads), coop_smem(), s, p, M, c, w, ipiv, xgk(k),
                        state, cb, spin);
   };
-  // the update by panel k of the columns [a, b)
-  auto update = [&](int k, int a, int b, hipStream_t s) {
+  // the update by panel k of the columns [a, b).  The next panel's strip
+  // (`ahead`, on the path to the next panel) spreads its rows over many small
+  // workgroups; the rest gives each workgroup up to 2048 rows (fewer U12
+  // loads and pipeline starts) while keeping at least 1024 workgroups.
+  auto update = [&](int k, int a, int b, hipStream_t s, bool ahead) {
     if (a >= b) return;
     const int c = kNB * k, w = min(kNB, Nd - c);
     const unsigned ns = (unsigned)((b - a + kNB - 1) / kNB);
     hipLaunchKernelGGL(big_u12_kernel, dim3(ns), dim3(kThreads), smem, s, p, M, c, w, ipiv, xgk(k), a, b);
     const int below = N - (c + w);
-    const unsigned nr = w <= 32 ? 1u : (unsigned)((below + kBigRows - 1) / kBigRows);
+    int rows = ahead ? kAheadRows : kBigRows;
+    while (!ahead && rows < 4 * kBigRows && (int64_t)ns * ((below + 2 * rows - 1) / (2 * rows)) >= 1024) rows *= 2;
+    const unsigned nr = w <= 32 ? 1u : (unsigned)((below + rows - 1) / rows);
     if (below > 0)
-      hipLaunchKernelGGL(big_gemm_kernel, dim3(ns, nr), dim3(kThreads), smem, s, p, M, c, w, a, b, kBigRows);
+      hipLaunchKernelGGL(big_gemm_kernel, dim3(ns, nr), dim3(kThreads), smem, s, p, M, c, w, a, b, rows);
   };
   hipLaunchKernelGGL(big_init_kernel, dim3(1), dim3(256), 0, s0, p, state, counters, np, ipiv, N);
   panel(0, s0);
@@ -2512,11 +2518,11 @@ hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* wor
     hipError_t e = hipEventRecord(ev[2 * k], s0);
     if (e != hipSuccess) return e;
     if (k + 1 < np) {
-      update(k, next, rest, s0);  // the next panel's columns first
+      update(k, next, rest, s0, true);  // the next panel's columns first
       panel(k + 1, s0);
     }
     if ((e = hipStreamWaitEvent(s1, ev[2 * k], 0)) != hipSuccess) return e;
-    update(k, rest, N, s1);  // every other trailing column, beside the next panel
+    update(k, rest, N, s1, false);  // every other trailing column, beside the next panel
     if ((e = hipEventRecord(ev[2 * k + 1], s1)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s0, ev[2 * k + 1], 0)) != hipSuccess) return e;
   }
