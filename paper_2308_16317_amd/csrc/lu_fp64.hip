@@ -1800,7 +1800,8 @@ __global__ __launch_bounds__(kThreads) void tau00_gmres_persistent_kernel(
 //     A22 -= L21 U12 on MFMA.
 // The host issues the launches on two streams with one panel of
 // look-ahead: the next strip's update and the next panel run on the
-// caller's stream while the rest of the trailing update runs on the second.
+// caller's stream while the rest of the trailing update runs on the second,
+// started once the next strip's update is done.
 // ======================================================================
 constexpr int kBigRows = 512;    // trailing-update rows per workgroup (up to 4x while >= 1024 workgroups)
 constexpr int kAheadRows = 128;  // rows per workgroup in the next panel's strip
@@ -2515,12 +2516,12 @@ hipError_t lsms_launch_big(const lsms_prob_dev& p, double* M, unsigned char* wor
   for (int k = 0; k < np; ++k) {
     const int next = kNB * (k + 1);  // first column of panel k + 1 (Nd after the last)
     const int rest = k + 1 < np ? min(next + kNB, Nd) : Nd;
+    // the next panel's columns first, alone on the device (on the path to
+    // the next panel); the rest of the update then starts beside that panel
+    if (k + 1 < np) update(k, next, rest, s0, true);
     hipError_t e = hipEventRecord(ev[2 * k], s0);
     if (e != hipSuccess) return e;
-    if (k + 1 < np) {
-      update(k, next, rest, s0, true);  // the next panel's columns first
-      panel(k + 1, s0);
-    }
+    if (k + 1 < np) panel(k + 1, s0);
     if ((e = hipStreamWaitEvent(s1, ev[2 * k], 0)) != hipSuccess) return e;
     update(k, rest, N, s1, false);  // every other trailing column, beside the next panel
     if ((e = hipEventRecord(ev[2 * k + 1], s1)) != hipSuccess) return e;
