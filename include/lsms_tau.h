@@ -288,16 +288,16 @@ int tau00_spin_solve(lsms_handle_t h, const lsms_problem *p, const lsms_spin *sp
 /* One instance across the whole GPU (paper Sec. 5: offloading the inverse of
  * the whole KKR matrix; Sec. 4.1: ranks 6225 to 12450).  tau00 of a single
  * caller-built matrix with every compute unit taking part: per panel of 64
- * columns one workgroup factorises the panel (partial pivoting among the
- * non-central rows, as tau00_batched), then one workgroup per 64-column
- * strip applies the interchanges and forms U12, and one per (strip, 512
- * rows) applies the MFMA update; the panel itself is factorised by
- * ceil(rows / 128) workgroups together (each holding 128 of its rows in LDS,
- * one grid barrier per column for the pivot choice; the workgroups of a
- * panel are at most 128, one per compute unit, and every barrier wait gives up
- * after a bounded number of polls); the next panel is factorised while the rest
- * of the update runs (one panel of look-ahead, on a second stream of the
- * handle, joined back to `stream` before the call's last kernel).
+ * columns ceil(rows / 128) workgroups factorise the panel together (partial
+ * pivoting among the non-central rows, as tau00_batched; each workgroup
+ * holds 128 of the panel's rows in LDS, one grid barrier per column for the
+ * pivot choice; the workgroups of a panel are at most 128, one per compute
+ * unit, and every barrier wait gives up after a bounded number of polls),
+ * then one workgroup per 64-column strip applies the interchanges and forms
+ * U12, and workgroups of 128 to 2048 rows of a strip apply the MFMA update;
+ * the next panel is factorised while the rest of the update runs (one panel
+ * of look-ahead, on a second stream of the handle, joined back to `stream`
+ * before the call's last kernel).
  *   p        n_inst = 1, the instance's LIZ exactly max_liz sites (info -3
  *            otherwise); N = kk * max_liz (2 kk * max_liz with spin) <= 16384
  *   spin     NULL, or spin canting as tau00_spin_batched

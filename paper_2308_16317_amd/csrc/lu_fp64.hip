@@ -1854,7 +1854,6 @@ constexpr int kCoopMaxP = 128;  // workgroups of a panel (N <= 16384)
 struct CoopSmem {
   zd blk[kCoopRows][kNB + 1];  // this workgroup's rows of the panel (row stride padded: rows start on different LDS banks)
   zd prow[kNB];            // the pivot row
-  zd rowj[kNB];            // the row that the pivot row replaces
   double candv[kLuWaves];
   int candi[kLuWaves];
   int stop;
