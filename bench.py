@@ -364,6 +364,61 @@ def time_row(args, P, h, w, liz, energy, e_idx, delta, max_liz, n: int = 256):
     return res
 
 
+def time_phases(args, P, h, w, liz, energy, e_idx, delta, max_liz, n: int = 256):
+    """The phases of the path on the first n instances (one per compute unit),
+    each one pass after a warm-up, HIP events on the current stream: the
+    build of M alone (build_kkr into a caller buffer), the elimination alone
+    (tau00_batched on that M), the fused path that the benchmark times
+    (tau00_solve, persistent: build and elimination in one kernel, M in a
+    workspace slot), and the fused path plus the copy of tau00 to host
+    memory (end to end, wall clock)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    prob = P.Problem(w.lmax, liz["liz_off"][:n + 1], liz["pos"], liz["species"], energy, e_idx[:n], delta,
+                     max_liz=max_liz)
+    N = w.kk * (liz["liz_off"][1:n + 1] - liz["liz_off"][:n])
+    m_off = torch.cumsum(N * N, 0) - N * N
+    M = torch.empty(int((N * N).sum().item()), dtype=torch.complex128, device=dev)
+    xg = torch.empty(n * P.BATCHED_WORK_PER_INST, dtype=torch.uint8, device=dev)
+    opts = P.Opts(0, args.nb, 0, 0)
+    fopts = P.Opts(P.PREC_FP64, args.nb, 0, P.PERSISTENT)
+    work = torch.empty(P.workspace_size(h, prob, 0, fopts), dtype=torch.uint8, device=dev)
+    tau = torch.empty((n, w.kk * w.kk), dtype=torch.complex128, device=dev)
+    info = torch.empty(n, dtype=torch.int32, device=dev)
+    host = torch.empty((n, w.kk * w.kk), dtype=torch.complex128, pin_memory=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    t_build = timed(lambda: P.build_kkr(h, prob, M, m_off))
+    t_factor = timed(lambda: (P.build_kkr(h, prob, M, m_off),
+                              P.tau00_batched(h, prob, M, m_off, opts, tau=tau, info=info, work=xg))) - t_build
+    t_fused = timed(lambda: P.tau00_solve(h, prob, work, fopts, tau=tau, info=info))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.tau00_solve(h, prob, work, fopts, tau=tau, info=info)
+    host.copy_(tau, non_blocking=True)
+    torch.cuda.synchronize()
+    t_e2e = (time.perf_counter() - t0) * 1e3
+    res = {"instances": n, "N": int(N.max().item()),
+           "build_ms": t_build, "factor_ms": t_factor, "fused_ms": t_fused,
+           "fused_plus_tau00_d2h_ms": t_e2e, "tau00_bytes": int(tau.numel() * 16),
+           "build_share_of_separate": t_build / (t_build + t_factor),
+           "errors": int((info != 0).sum().item()),
+           "kernels": "build_kkr_kernel; lu_schur_fp64_kernel; tau00_persistent_kernel (build + elimination)"}
+    del M, xg, work
+    return res
+
+
 def bench_large(args, canted: bool = False):
     """One matrix across the whole GPU (tau00_large) at the paper's
     non-canted NiAu rank N = 6225 (lmax = 4, 249-atom LIZ), or with `canted`
@@ -729,6 +784,12 @@ def main():
             log(f"[bench] block row: {out['block_row_logdet']}")
         except Exception as e:  # reported, not fatal
             out["block_row_logdet"] = {"error": repr(e)}
+    if args.forms == "all" and args.workload == "benchmark" and args.mode != "chunked":
+        try:
+            out["phases"] = time_phases(args, P, h, w, liz, energy, e_idx, delta, max_liz)
+            log(f"[bench] phases: {out['phases']}")
+        except Exception as e:  # reported, not fatal
+            out["phases"] = {"error": repr(e)}
     if not args.no_cpu:
         nthr = args.cpu_threads or host_cores()
         idx = cpu_sample_indices(w)[:args.cpu_sample]
