@@ -571,7 +571,7 @@ def bench_canted(args, lmax: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", choices=["chunked", "persistent", "graph"], default="persistent",
                     help="chunked: build_kkr + tau00_batched per pass; persistent: tau00_solve with one "
