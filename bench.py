@@ -9,7 +9,10 @@ are synthetic and resident on the GPU before the timed region.
 Prints one JSON line: metric, value (solves/s), timing, the roofline of the
 dominant kernel (HIP-event timing, measured HBM traffic when the kernel
 sources match the profiled ones), the other forms timed on the same
-instances, and the CPU oracle baseline.
+instances, the block row with ln det M, the phases of the path (build,
+elimination, fused, fused plus the copy of tau00 to the host), the CPU
+baselines (the oracle and LAPACK) and the check of the GPU's tau00 against
+the oracle.
 """
 
 from __future__ import annotations
