@@ -1895,10 +1895,13 @@ __device__ __forceinline__ zd ld_dev(zd* a) {
 // Arrival of this workgroup at barrier `target` (all threads call it) and the
 // wait for every workgroup; false (uniform) when the wait gave up.  Every
 // thread's exchange stores are acknowledged (all memory counters drained)
-// before thread 0 adds the arrival.
-__device__ bool coop_barrier(int32_t* counter, int target, int64_t spin, int* stop) {
+// before thread 0 adds the arrival; meanwhile the threads of waves 1.. run
+// `work` (bounded, no barrier inside).
+template <typename F>
+__device__ bool coop_barrier(int32_t* counter, int target, int64_t spin, int* stop, F&& work) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  if (threadIdx.x >= 64) work();  // waves 1.. work while thread 0 waits
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
@@ -1937,6 +1940,12 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
     cs.blk[r][j] = (r < nr && j < w) ? *v.A.ptr(row0 + r, c + j) : zmake(0.0, 0.0);
   }
   __syncthreads();
+  // Column j's elimination updates column j + 1 at once and the columns
+  // > j + 1 during the next column's barrier wait, so the rows published
+  // for column j + 1 lack that update in the columns > j + 1: their readers
+  // apply it (multiplier in the row's column j, column j's pivot row still
+  // in cs.prow).  pend: such an update is outstanding.
+  bool pend = false;
   for (int j = 0; j < w; ++j) {
     const int cj = c + j, buf = j & 1;
     // candidate of this workgroup (threads 0..127 take one row each)
@@ -1976,14 +1985,40 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
         if (cj >= row0 && cj < row0 + nr) st_dev(cb.rowj + buf * kNB + lane, cs.blk[cj - row0][lane]);
       }
     }
-    if (!coop_barrier(cb.counter, P * (j + 1), spin, &cs.stop)) {
+    // the barrier; meanwhile waves 1-7 apply column j - 1's update to the
+    // columns > j of the rows below its pivot (four threads per row)
+    const bool pj = pend;
+    const bool ok = coop_barrier(cb.counter, P * (j + 1), spin, &cs.stop, [&]() {
+      if (!pj) return;
+      const int t = tid - 64, part = t & 3;
+      for (int r = t >> 2; r < nr; r += (kThreads - 64) / 4) {
+        if (row0 + r < cj) continue;
+        const zd l = cs.blk[r][j - 1];
+        for (int g = (j + 1) >> 4; g < ((w + 15) >> 4); ++g) {
+          zd a[4], u[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int jj = 16 * g + 4 * m + part;
+            a[m] = cs.blk[r][jj];
+            u[m] = cs.prow[jj];
+          }
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int jj = 16 * g + 4 * m + part;
+            if (jj > j && jj < w) cs.blk[r][jj] = zfms(a[m], l, u[m]);
+          }
+        }
+      }
+    });
+    if (!ok) {
       if (tid == 0) state[1] = 1;
       return;
     }
     // the winner, the same in every workgroup: wave 0 reads the P candidates
     // (lane q those of workgroups q and q + 64) and row cj at once, reduces
     // the candidates, takes lane 0's result, reads the winning row from its
-    // owner (workgroup 0 owns row cj) and swaps the two rows where it owns them
+    // owner (workgroup 0 owns row cj), brings both rows up to date and swaps
+    // them where it owns them
     if (wave == 0) {
       zd rj = zmake(0.0, 0.0);
       if (lane < w) rj = ld_dev(cb.rowj + buf * kNB + lane);
@@ -2012,8 +2047,19 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
         if (b == 0) ipiv[cj] = pr;
       }
       const int wb = min(max((pr - c) / kCoopRows, 0), P - 1);
+      zd pv = zmake(0.0, 0.0);
+      if (lane < w) pv = ld_dev(cb.candrow + ((int64_t)buf * kCoopMaxP + wb) * kNB + lane);
+      if (pj) {
+        // column j - 1's update of the columns > j, as the other rows had it
+        const zd mp = zmake(__shfl(pv.x, j - 1), __shfl(pv.y, j - 1));
+        const zd mr = zmake(__shfl(rj.x, j - 1), __shfl(rj.y, j - 1));
+        if (lane > j && lane < w) {
+          const zd pu = cs.prow[lane];
+          pv = zfms(pv, mp, pu);
+          rj = zfms(rj, mr, pu);
+        }
+      }
       if (lane < w) {
-        const zd pv = ld_dev(cb.candrow + ((int64_t)buf * kCoopMaxP + wb) * kNB + lane);
         cs.prow[lane] = pv;
         if (pr != cj) {
           if (pr >= row0 && pr < row0 + nr) cs.blk[pr - row0][lane] = rj;
@@ -2022,29 +2068,15 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
       }
     }
     __syncthreads();
-    if (cs.winv > 0.0) {
-      // rows below the pivot: l = a_rj / pivot, a_r(j+1..) -= l prow(j+1..),
-      // a_rj := l; four threads per row, each every fourth column, sixteen
-      // columns per group with the group's loads issued together
+    // rows below the pivot: l = a_rj / pivot, a_rj := l, a_r(j+1) -= l prow(j+1)
+    // (one thread per row); the columns > j + 1 follow in the next barrier
+    pend = cs.winv > 0.0;
+    if (pend) {
       const zd inv = zinv(cs.prow[j]);
-      const int r = tid >> 2, part = tid & 3;
-      if (r < nr && row0 + r > cj) {
-        const zd l = zmul(cs.blk[r][j], inv);
-        for (int g = (j + 1) >> 4; g < ((w + 15) >> 4); ++g) {
-          zd a[4], u[4];
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int jj = 16 * g + 4 * m + part;
-            a[m] = cs.blk[r][jj];
-            u[m] = cs.prow[jj];
-          }
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int jj = 16 * g + 4 * m + part;
-            if (jj > j && jj < w) cs.blk[r][jj] = zfms(a[m], l, u[m]);
-          }
-        }
-        if (part == 0) cs.blk[r][j] = l;
+      if (tid < nr && row0 + tid > cj) {
+        const zd l = zmul(cs.blk[tid][j], inv);
+        cs.blk[tid][j] = l;
+        if (j + 1 < w) cs.blk[tid][j + 1] = zfms(cs.blk[tid][j + 1], l, cs.prow[j + 1]);
       }
     }
     __syncthreads();
