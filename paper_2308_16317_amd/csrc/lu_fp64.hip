@@ -1895,15 +1895,15 @@ __device__ __forceinline__ zd ld_dev(zd* a) {
 // Arrival of this workgroup at barrier `target` (all threads call it) and the
 // wait for every workgroup; false (uniform) when the wait gave up.  Every
 // thread's exchange stores are acknowledged (all memory counters drained)
-// before thread 0 adds the arrival; meanwhile the threads of waves 1.. run
-// `work` (bounded, no barrier inside).
+// before thread 0 adds the arrival; then every thread runs `work` (bounded,
+// no barrier inside) while the other workgroups arrive, and thread 0 waits.
 template <typename F>
 __device__ bool coop_barrier(int32_t* counter, int target, int64_t spin, int* stop, F&& work) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x >= 64) work();  // waves 1.. work while thread 0 waits
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  work();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     int64_t it = 0;
     while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -1941,7 +1941,8 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
   }
   __syncthreads();
   // Column j's elimination updates column j + 1 at once and the columns
-  // > j + 1 during the next column's barrier wait, so the rows published
+  // > j + 1 during the next column's barrier (after this workgroup's arrival,
+  // while the others arrive), so the rows published
   // for column j + 1 lack that update in the columns > j + 1: their readers
   // apply it (multiplier in the row's column j, column j's pivot row still
   // in cs.prow).  pend: such an update is outstanding.
@@ -1985,14 +1986,14 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
         if (cj >= row0 && cj < row0 + nr) st_dev(cb.rowj + buf * kNB + lane, cs.blk[cj - row0][lane]);
       }
     }
-    // the barrier; meanwhile waves 1-7 apply column j - 1's update to the
-    // columns > j of the rows below its pivot (four threads per row)
+    // the barrier; once this workgroup has arrived, its threads apply column
+    // j - 1's update to the columns > j of the rows below its pivot (four
+    // threads per row, each every fourth column)
     const bool pj = pend;
     const bool ok = coop_barrier(cb.counter, P * (j + 1), spin, &cs.stop, [&]() {
       if (!pj) return;
-      const int t = tid - 64, part = t & 3;
-      for (int r = t >> 2; r < nr; r += (kThreads - 64) / 4) {
-        if (row0 + r < cj) continue;
+      const int r = tid >> 2, part = tid & 3;
+      if (r < nr && row0 + r >= cj) {
         const zd l = cs.blk[r][j - 1];
         for (int g = (j + 1) >> 4; g < ((w + 15) >> 4); ++g) {
           zd a[4], u[4];
