@@ -1854,8 +1854,6 @@ constexpr int kCoopMaxP = 128;  // workgroups of a panel (N <= 16384)
 struct CoopSmem {
   zd blk[kCoopRows][kNB + 1];  // this workgroup's rows of the panel (row stride padded: rows start on different LDS banks)
   zd prow[kNB];            // the pivot row
-  double candv[kLuWaves];
-  int candi[kLuWaves];
   int stop;
   double winv;
 };
@@ -1949,33 +1947,27 @@ __global__ __launch_bounds__(kThreads) void big_panel_coop_kernel(lsms_prob_dev 
   bool pend = false;
   for (int j = 0; j < w; ++j) {
     const int cj = c + j, buf = j & 1;
-    // candidate of this workgroup (threads 0..127 take one row each)
-    double best = -1.0;
-    int bi = cj;
-    if (tid < nr) {
-      const int g = row0 + tid;
-      if (g >= cj && g < plim) {
-        best = zcabs1(cs.blk[tid][j]);
-        bi = g;
-      }
-    }
-    wave_argmax(best, bi);
-    if (lane == 0) {
-      cs.candv[wave] = best;
-      cs.candi[wave] = bi;
-    }
-    __syncthreads();
-    // wave 0 publishes: every lane reduces the eight wave candidates in the
-    // same order (so all agree), lane 0 stores value and row index, lanes
-    // < w the candidate's row and, in the owner of row cj, that row
+    // wave 0 finds this workgroup's candidate (lane q takes rows q and q + 64:
+    // |Re| + |Im| among the rows in [cj, plim), lowest row on ties) and
+    // publishes it: lane 0 the value and row index, lanes < w the candidate's
+    // row and, in the owner of row cj, that row
     if (wave == 0) {
-      double bb = cs.candv[0];
-      int ii = cs.candi[0];
-      for (int q = 1; q < kLuWaves; ++q)
-        if (better(cs.candv[q], cs.candi[q], bb, ii)) {
-          bb = cs.candv[q];
-          ii = cs.candi[q];
+      double bb = -1.0;
+      int ii = cj;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = lane + 64 * h, g = row0 + r;
+        if (r < nr && g >= cj && g < plim) {
+          const double x = zcabs1(cs.blk[r][j]);
+          if (better(x, g, bb, ii)) {
+            bb = x;
+            ii = g;
+          }
         }
+      }
+      wave_argmax(bb, ii);
+      bb = __shfl(bb, 0);
+      ii = __shfl(ii, 0);
       if (lane == 0) {
         st_dev(cb.candv + buf * kCoopMaxP + b, bb);
         st_dev(cb.candi + buf * kCoopMaxP + b, ii);
