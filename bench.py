@@ -34,7 +34,7 @@ FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per instance moved by the fused kernel (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, each scaled by the counts of a plain copy of known size), valid
 # only for the kernel code whose hash is given; null otherwise.
-TRAFFIC_PER_INSTANCE = {("fp64", "57f833c53f58f9fa"): 2.0341e+09, ("fp32ir", "57f833c53f58f9fa"): 1.1881e+09}
+TRAFFIC_PER_INSTANCE = {("fp64", "90c86cd25f803934"): 2.0338e+09, ("fp32ir", "90c86cd25f803934"): 1.1884e+09}
 KERNEL_SOURCES = ("kkr_device.h", "lu_device.h", "lu_fp64.hip", "lsms_common.h")
 
 
